@@ -1,0 +1,237 @@
+"""ClusterMerge written out sequentially.  Test infrastructure only.
+
+Algorithm 2 (BottomUpMerge, Section 3.2): every element starts as a one-cluster
+set in a FIFO queue; two sets are popped, merged with Algorithm 1 and the
+result is pushed back until one set remains.
+
+Algorithm 1 (Cluster Set Merge, Section 3.1): every cluster of the first set is
+compared with every not-yet-merged cluster of the second set through their
+representatives.  Similar representatives are then tested for transitivity
+both ways (Section 3.3: approximate transitivity is not symmetric).  A
+transitive pair is fully merged; a similar but non-transitive pair exchanges
+members similar to the other representative; dissimilar pairs are left alone.
+
+Section 4 defines the protein transitivity: the score must exceed mT and the
+absorbed representative may leave fewer than mU residues outside the local
+alignment.
+
+Readings where the paper is silent (each is listed in the design notes):
+  * similarity is ``score >= T`` (the listing's "skip if s < T");
+  * alignment orientation for representatives: rows = cluster of the first
+    set, columns = cluster of the second set;
+  * "uncovered" = residues of the absorbed representative outside
+    [start, end] on both flanks, from the tie-broken span;
+  * ExchangeSimilar takes snapshots of both member lists, adds (in member
+    order) the members of the other cluster that are similar to this
+    cluster's representative and not already present;
+  * a full merge appends the absorbed members in order, skipping any already
+    present.
+"""
+from __future__ import annotations
+
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .sw import sw, sw_span
+
+
+@dataclass
+class Cluster:
+    rep: int
+    objs: list = field(default_factory=list)
+    merged: bool = False
+
+
+@dataclass
+class Stats:
+    rep_comparisons: int = 0       # f(rep1, rep2) evaluations of Algorithm 1
+    exchange_alignments: int = 0   # member-vs-representative evaluations
+    full_merges: int = 0
+    exchanges: int = 0
+
+
+def merge_schedule(n: int):
+    """The FIFO merge order of Algorithm 2 as (first, second, result) set ids.
+
+    Sets 0..n-1 are the singletons in element order; merges create n, n+1, ...
+    """
+    q = deque(range(n))
+    out, nxt = [], n
+    while len(q) > 1:
+        x = q.popleft()
+        y = q.popleft()
+        out.append((x, y, nxt))
+        q.append(nxt)
+        nxt += 1
+    return out
+
+
+class ProteinJudge:
+    """f = Smith-Waterman score; R = score > mT and absorbed rep's uncovered < mU."""
+
+    def __init__(self, residues, offsets, M, T=120, mT=166, mU=15, go=-11, ge=-1):
+        self.res = np.asarray(residues, dtype=np.uint8)
+        self.off = np.asarray(offsets, dtype=np.int64)
+        self.M = np.asarray(M, dtype=np.int32)
+        self.T, self.mT, self.mU, self.go, self.ge = T, mT, mU, go, ge
+        self._score = {}
+        self._span = {}
+
+    def seq(self, i):
+        return self.res[self.off[i]:self.off[i + 1]]
+
+    def score(self, x, y):
+        key = (x, y) if x <= y else (y, x)
+        s = self._score.get(key)
+        if s is None:
+            s = sw(self.seq(key[0]), self.seq(key[1]), self.M, self.go, self.ge)[0]
+            self._score[key] = s
+        return s
+
+    def rep_test(self, r1, r2):
+        """(similar, cluster2 absorbs cluster1, cluster1 absorbs cluster2) for reps r1 (set 1), r2 (set 2)."""
+        key = (r1, r2)
+        v = self._span.get(key)
+        if v is None:
+            s = self.score(r1, r2)
+            if s > self.mT:
+                S, ei, ej, si, sj = sw_span(self.seq(r1), self.seq(r2), self.M, self.go, self.ge)
+                assert S == s
+                u1 = len(self.seq(r1)) - (ei - si + 1)
+                u2 = len(self.seq(r2)) - (ej - sj + 1)
+                v = (s >= self.T, u1 < self.mU, u2 < self.mU)
+            else:
+                v = (s >= self.T, False, False)
+            self._span[key] = v
+        return v
+
+    def member_similar(self, m, rep):
+        return self.score(m, rep) >= self.T
+
+
+class TableJudge:
+    """Injected similarity and transitivity (for the tree-shape and semantic pins)."""
+
+    def __init__(self, similar, transitive):
+        self._similar = similar          # (x, y) -> bool
+        self._transitive = transitive    # (absorber, absorbed) -> bool
+
+    def rep_test(self, r1, r2):
+        s = self._similar(r1, r2)
+        return (s, s and self._transitive(r2, r1), s and self._transitive(r1, r2))
+
+    def member_similar(self, m, rep):
+        return self._similar(m, rep)
+
+
+def _append_missing(dst, src):
+    have = set(dst)
+    for x in src:
+        if x not in have:
+            dst.append(x)
+            have.add(x)
+
+
+def exchange_similar(c1, c2, judge, stats):
+    m1 = list(c1.objs)
+    m2 = list(c2.objs)
+    in1, in2 = set(m1), set(m2)
+    add1 = [m for m in m2 if m not in in1 and judge.member_similar(m, c1.rep)]
+    add2 = [m for m in m1 if m not in in2 and judge.member_similar(m, c2.rep)]
+    stats.exchange_alignments += sum(1 for m in m2 if m not in in1)
+    stats.exchange_alignments += sum(1 for m in m1 if m not in in2)
+    c1.objs.extend(add1)
+    c2.objs.extend(add2)
+    stats.exchanges += 1
+
+
+def merge(cs1, cs2, judge, stats):
+    """Algorithm 1 on two ordered cluster lists; returns the new ordered list."""
+    out = []
+    for c1 in cs1:
+        for c2 in cs2:
+            if c2.merged:
+                continue
+            stats.rep_comparisons += 1
+            similar, c2_takes_c1, c1_takes_c2 = judge.rep_test(c1.rep, c2.rep)
+            if not similar:
+                continue
+            if c2_takes_c1:
+                _append_missing(c2.objs, c1.objs)
+                c1.merged = True
+                stats.full_merges += 1
+                break
+            elif c1_takes_c2:
+                _append_missing(c1.objs, c2.objs)
+                c2.merged = True
+                stats.full_merges += 1
+            else:
+                exchange_similar(c1, c2, judge, stats)
+        if not c1.merged:
+            out.append(c1)
+    for c2 in cs2:
+        if not c2.merged:
+            out.append(c2)
+    return out
+
+
+def bottom_up_merge(n, judge, stats=None):
+    """Algorithm 2 over elements 0..n-1 in index order; returns (clusters, stats)."""
+    stats = stats or Stats()
+    q = deque([[Cluster(e, [e])] for e in range(n)])
+    while len(q) > 1:
+        cs1 = q.popleft()
+        cs2 = q.popleft()
+        q.append(merge(cs1, cs2, judge, stats))
+    final = q.popleft() if q else []
+    return final, stats
+
+
+def cluster_pairs(clusters):
+    """Unique (x, y), x < y, over the members of every final cluster, sorted."""
+    s = set()
+    for c in clusters:
+        objs = sorted(set(c.objs))
+        for i in range(len(objs)):
+            for j in range(i + 1, len(objs)):
+                s.add((objs[i], objs[j]))
+    return sorted(s)
+
+
+def similar_pairs(clusters, score, T):
+    """Final stage (Section 6.1): align all pairs inside each cluster, keep score >= T."""
+    out = []
+    for x, y in cluster_pairs(clusters):
+        s = score(x, y)
+        if s >= T:
+            out.append((x, y, s))
+    return out
+
+
+def clustermerge(residues, offsets, M, T=120, mT=166, mU=15, go=-11, ge=-1):
+    """Plain ClusterMerge end to end: (clusters, similar pairs, stats)."""
+    n = len(offsets) - 1
+    judge = ProteinJudge(residues, offsets, M, T, mT, mU, go, ge)
+    clusters, stats = bottom_up_merge(n, judge)
+    pairs = similar_pairs(clusters, judge.score, T)
+    return clusters, pairs, stats
+
+
+def allvsall(residues, offsets, M, T=120, go=-11, ge=-1):
+    """Ground truth: every (x, y), x < y, with score >= T."""
+    from .sw import sw_batch
+    n = len(offsets) - 1
+    a, b = np.triu_indices(n, k=1)
+    pr = np.stack([a, b], axis=1).astype(np.int32)
+    sc = sw_batch(residues, offsets, pr, M, go, ge, with_end=False)
+    keep = sc >= T
+    return [(int(x), int(y), int(s)) for x, y, s in zip(a[keep], b[keep], sc[keep])]
+
+
+def recall(found, truth):
+    """|found intersect truth| / |truth| over (x, y) pairs (Section 6.1)."""
+    f = {(x, y) for x, y, *_ in found}
+    t = {(x, y) for x, y, *_ in truth}
+    return len(f & t) / len(t) if t else 1.0

@@ -1,0 +1,110 @@
+"""Pins for the sequential ClusterMerge oracle (CPU only).
+
+Algorithm 2's FIFO tree shape is checked by hand for small n; Algorithm 1 is
+checked against the consequences the paper states in Sections 3.3-3.4: a
+transitivity function that never holds forces every pair of elements to meet
+once as representatives (the worst case, n(n-1)/2 comparisons); a complete
+transitivity function (an equivalence relation) loses no similar pair; and
+identical proteins collapse into one cluster after n-1 comparisons.
+"""
+import numpy as np
+
+import cmgen
+from oracle import clustermerge as cm
+from oracle import sw
+
+
+def test_fifo_tree_shape_by_hand():
+    assert cm.merge_schedule(1) == []
+    assert cm.merge_schedule(2) == [(0, 1, 2)]
+    assert cm.merge_schedule(3) == [(0, 1, 3), (2, 3, 4)]
+    assert cm.merge_schedule(4) == [(0, 1, 4), (2, 3, 5), (4, 5, 6)]
+    # n=5: (0,1)->A, (2,3)->B, (4,A)->C, (B,C)->D
+    assert cm.merge_schedule(5) == [(0, 1, 5), (2, 3, 6), (4, 5, 7), (6, 7, 8)]
+    assert cm.merge_schedule(6) == [(0, 1, 6), (2, 3, 7), (4, 5, 8), (6, 7, 9), (8, 9, 10)]
+    assert cm.merge_schedule(7) == [(0, 1, 7), (2, 3, 8), (4, 5, 9), (6, 7, 10), (8, 9, 11),
+                                    (10, 11, 12)]
+    assert cm.merge_schedule(8)[-1] == (12, 13, 14)
+    assert cm.merge_schedule(9) == [(0, 1, 9), (2, 3, 10), (4, 5, 11), (6, 7, 12), (8, 9, 13),
+                                    (10, 11, 14), (12, 13, 15), (14, 15, 16)]
+    for n in range(1, 40):
+        assert len(cm.merge_schedule(n)) == max(0, n - 1)
+
+
+def test_never_transitive_is_all_vs_all():
+    for n in (1, 2, 5, 9, 17):
+        judge = cm.TableJudge(lambda x, y: True, lambda r, s: False)
+        clusters, st = cm.bottom_up_merge(n, judge)
+        assert st.rep_comparisons == n * (n - 1) // 2
+        assert sorted(c.rep for c in clusters) == list(range(n))
+        found = {(x, y) for x, y in cm.cluster_pairs(clusters)}
+        assert found == {(x, y) for x in range(n) for y in range(x + 1, n)}
+
+
+def test_equivalence_relation_gives_label_classes():
+    rng = np.random.default_rng(3)
+    for n in (7, 20, 33):
+        lab = rng.integers(0, 4, size=n)
+        same = lambda x, y: lab[x] == lab[y]  # noqa: E731
+        clusters, st = cm.bottom_up_merge(n, cm.TableJudge(same, same))
+        got = sorted(sorted(c.objs) for c in clusters)
+        want = sorted(sorted(np.flatnonzero(lab == v).tolist()) for v in np.unique(lab))
+        assert got == want
+        truth = {(x, y) for x in range(n) for y in range(x + 1, n) if lab[x] == lab[y]}
+        assert set(cm.cluster_pairs(clusters)) == truth
+
+
+def test_identical_proteins_collapse():
+    rng = np.random.default_rng(4)
+    a = rng.integers(0, 20, size=60).astype(np.uint8)
+    ds = cmgen.from_list([a] * 4)
+    clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    assert len(clusters) == 1
+    assert clusters[0].rep == 3 and clusters[0].objs == [3, 2, 1, 0]
+    assert st.rep_comparisons == 3
+    assert [(x, y) for x, y, _ in pairs] == [(x, y) for x in range(4) for y in range(x + 1, 4)]
+
+
+def test_exchange_semantics():
+    # reps 0 and 2 similar but never transitive; member 1 of cluster(0) is
+    # similar to rep 2, member 3 of cluster(2) is not similar to rep 0.
+    sim = {(0, 1), (2, 3), (0, 2), (1, 2)}
+    similar = lambda x, y: (min(x, y), max(x, y)) in sim  # noqa: E731
+    trans_within = {(0, 1), (2, 3)}   # absorber, absorbed
+    transitive = lambda r, s: (r, s) in trans_within or (s, r) in trans_within  # noqa: E731
+    clusters, st = cm.bottom_up_merge(4, cm.TableJudge(similar, transitive))
+    byrep = {c.rep: c.objs for c in clusters}
+    # (0,1): cluster(1) absorbs cluster(0) -> rep 1, objs [1, 0]
+    # (2,3): cluster(3) absorbs cluster(2) -> rep 3, objs [3, 2]
+    # merge reps 1 and 3: not similar -> unchanged
+    assert byrep == {1: [1, 0], 3: [3, 2]}
+
+
+def test_exchange_adds_reps_and_similar_members():
+    sim = {(0, 2), (1, 2), (0, 3)}
+    similar = lambda x, y: (min(x, y), max(x, y)) in sim  # noqa: E731
+    never = lambda r, s: False  # noqa: E731
+    # Tree: (0,1) -> [c0, c1]; (2,3) -> [c2, c3]; then merge the two sets.
+    clusters, st = cm.bottom_up_merge(4, cm.TableJudge(similar, never))
+    byrep = {c.rep: c.objs for c in clusters}
+    assert byrep == {0: [0, 2, 3], 1: [1, 2], 2: [2, 0, 1], 3: [3, 0]}
+
+
+def test_precision_and_recall_small_families():
+    ds = cmgen.allvsall_small()
+    clusters, found, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    truth = cm.allvsall(ds.residues, ds.offsets, ds.matrix)
+    tset = {(x, y) for x, y, _ in truth}
+    # precision is 100% by construction: every reported pair was aligned
+    assert all((x, y) in tset for x, y, _ in found)
+    for x, y, s in found[:50]:
+        assert sw(ds.seq(x), ds.seq(y), ds.matrix)[0] == s
+    r = cm.recall(found, truth)
+    assert r >= 0.9, r
+    assert st.rep_comparisons < ds.n * (ds.n - 1) // 2
+    # every element ends in at least one cluster; reps are members of their own cluster
+    members = set()
+    for c in clusters:
+        assert c.rep in c.objs and len(set(c.objs)) == len(c.objs)
+        members.update(c.objs)
+    assert members == set(range(ds.n))

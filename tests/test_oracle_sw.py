@@ -1,0 +1,211 @@
+"""Pins for the scalar Smith-Waterman oracle (CPU only).
+
+The oracle is checked against things other than itself: exhaustive enumeration
+of alignments, the cubic general-gap recurrence, closed forms and invariants
+that follow from the definition (Section 4: local-alignment score under a
+substitution matrix; affine gap model W(k) = go + (k-1)*ge).
+"""
+import numpy as np
+import pytest
+
+import cmgen
+from oracle import sw, sw_span, sw_batch, span_batch
+from oracle.brute import enumerate_local, general_gap, ungapped_best
+
+M0 = cmgen.make_matrix()
+GO, GE = cmgen.GAP_OPEN, cmgen.GAP_EXTEND
+
+
+def rand_seq(rng, lo, hi, alphabet=20):
+    return rng.integers(0, alphabet, size=int(rng.integers(lo, hi + 1))).astype(np.uint8)
+
+
+def tie_matrix():
+    """Residues 0..3: mutual score 0 among 0,1; strong matches elsewhere (tie-heavy)."""
+    M = M0.copy()
+    M[0, 1] = M[1, 0] = 0
+    M[0, 0] = M[1, 1] = 4
+    M[2, 3] = M[3, 2] = 0
+    return M
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_tiny(seed):
+    rng = np.random.default_rng(1000 + seed)
+    mats = [M0, tie_matrix()]
+    params = [(GO, GE), (-3, -1), (-2, -2), (-4, 0)]
+    for trial in range(40):
+        M = mats[trial % 2]
+        go, ge = params[trial % len(params)]
+        alpha = 4 if trial % 3 == 0 else 20       # small alphabet => many matches and ties
+        a = rand_seq(rng, 0, 5, alpha)
+        b = rand_seq(rng, 0, 5, alpha)
+        S, end, start = enumerate_local(a, b, M, go, ge)
+        got = sw_span(a, b, M, go, ge)
+        assert got[0] == S, (a, b, go, ge)
+        assert (got[1], got[2]) == end, (a, b, go, ge)
+        assert (got[3], got[4]) == start, (a, b, go, ge)
+
+
+def test_bruteforce_len6():
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        a = rng.integers(0, 4, size=6).astype(np.uint8)
+        b = rng.integers(0, 4, size=6).astype(np.uint8)
+        S, end, start = enumerate_local(a, b, tie_matrix(), -3, -1)
+        got = sw_span(a, b, tie_matrix(), -3, -1)
+        assert got == (S, end[0], end[1], start[0], start[1])
+
+
+def test_general_gap_recurrence():
+    rng = np.random.default_rng(11)
+    params = [(GO, GE), (-5, -2), (-3, -3), (-6, 0)]
+    for t in range(30):
+        go, ge = params[t % len(params)]
+        alpha = 5 if t % 2 else 20
+        a = rand_seq(rng, 1, 30, alpha)
+        b = rand_seq(rng, 1, 30, alpha)
+        assert sw(a, b, M0, go, ge)[0] == general_gap(a, b, M0, go, ge)
+
+
+def test_general_gap_longer():
+    rng = np.random.default_rng(12)
+    anc = rng.integers(0, 20, size=60).astype(np.uint8)
+    a = cmgen.mutate(rng, anc)
+    b = cmgen.mutate(rng, anc)
+    assert sw(a, b, M0, GO, GE)[0] == general_gap(a, b, M0, GO, GE)
+
+
+def test_symmetry_and_transposed_end():
+    rng = np.random.default_rng(13)
+    for _ in range(40):
+        a = rand_seq(rng, 0, 120)
+        b = rand_seq(rng, 0, 120)
+        s, ei, ej = sw(a, b, M0)
+        s2, fi, fj = sw(b, a, M0)
+        assert s == s2
+        if s > 0:
+            # H(a,b) at the transposed end cell of (b,a) must also hold S:
+            # the prefix pair a[..fj], b[..fi] reaches S.
+            assert sw(a[:fj + 1], b[:fi + 1], M0)[0] == s
+
+
+def test_reversal():
+    rng = np.random.default_rng(14)
+    for _ in range(40):
+        a = rand_seq(rng, 0, 150)
+        b = rand_seq(rng, 0, 150)
+        assert sw(a, b, M0)[0] == sw(a[::-1], b[::-1], M0)[0]
+
+
+def test_self_score_closed_form():
+    # diag >= 4 > 3 >= off-diag: the best alignment of a with itself is the identity.
+    rng = np.random.default_rng(15)
+    assert M0.diagonal().min() >= 4 and (M0 - np.diag(M0.diagonal())).max() <= 3
+    for _ in range(20):
+        a = rand_seq(rng, 1, 300)
+        S, ei, ej, si, sj = sw_span(a, a, M0)
+        assert S == int(M0[a, a].sum())
+        assert (ei, ej, si, sj) == (len(a) - 1, len(a) - 1, 0, 0)
+
+
+def test_bound_and_substring():
+    rng = np.random.default_rng(16)
+    for _ in range(20):
+        a = rand_seq(rng, 1, 150)
+        b = rand_seq(rng, 1, 150)
+        self_a = int(M0[a, a].sum())
+        self_b = int(M0[b, b].sum())
+        assert sw(a, b, M0)[0] <= min(self_a, self_b)
+        x = rand_seq(rng, 0, 40)
+        y = rand_seq(rng, 0, 40)
+        big = np.concatenate([x, a, y])
+        S, ei, ej, si, sj = sw_span(a, big, M0)
+        assert S == self_a
+        assert (ei, si) == (len(a) - 1, 0)
+        # the first exact occurrence of a inside big
+        first = next(k for k in range(len(big) - len(a) + 1) if np.array_equal(big[k:k + len(a)], a))
+        assert (sj, ej) == (first, first + len(a) - 1)
+
+
+def test_single_residue():
+    rng = np.random.default_rng(17)
+    for _ in range(40):
+        x = rng.integers(0, 20, size=1).astype(np.uint8)
+        b = rand_seq(rng, 0, 60)
+        s, ei, ej = sw(x, b, M0)
+        vals = [int(M0[x[0], c]) for c in b]
+        expect = max([0] + vals)
+        assert s == expect
+        if expect > 0:
+            assert (ei, ej) == (0, vals.index(expect))
+        else:
+            assert (ei, ej) == (-1, -1)
+
+
+def test_no_gap_limit_is_kadane():
+    rng = np.random.default_rng(18)
+    for _ in range(30):
+        a = rand_seq(rng, 0, 80)
+        b = rand_seq(rng, 0, 80)
+        assert sw(a, b, M0, -10**6, -1)[0] == ungapped_best(a, b, M0)
+
+
+def test_monotone_under_append():
+    rng = np.random.default_rng(19)
+    for _ in range(30):
+        a = rand_seq(rng, 0, 100)
+        b = rand_seq(rng, 0, 100)
+        s = sw(a, b, M0)[0]
+        a2 = np.concatenate([a, rand_seq(rng, 1, 20)])
+        b2 = np.concatenate([rand_seq(rng, 1, 20), b])
+        assert sw(a2, b, M0)[0] >= s
+        assert sw(a, b2, M0)[0] >= s
+
+
+def test_empty_and_all_zero():
+    assert sw(np.zeros(0, np.uint8), np.arange(5, dtype=np.uint8), M0) == (0, -1, -1)
+    assert sw(np.zeros(0, np.uint8), np.zeros(0, np.uint8), M0) == (0, -1, -1)
+    # every pair scores negative: the empty alignment wins
+    M = -np.ones((20, 20), np.int32)
+    assert sw_span(np.arange(5, dtype=np.uint8), np.arange(5, dtype=np.uint8), M) == (0, -1, -1, -1, -1)
+
+
+def test_batch_matches_single():
+    ds = cmgen.uniform_pool(30, 0, 200, seed=21)
+    rng = np.random.default_rng(22)
+    pairs = cmgen.random_pairs(rng, ds.n, 60)
+    sc, ea, eb = sw_batch(ds.residues, ds.offsets, pairs, ds.matrix)
+    sp = span_batch(ds.residues, ds.offsets, pairs, ds.matrix)
+    for p, (x, y) in enumerate(pairs):
+        s, ei, ej = sw(ds.seq(x), ds.seq(y), ds.matrix)
+        assert (sc[p], ea[p], eb[p]) == (s, ei, ej)
+        assert tuple(sp[p, :3]) == (s, ei, ej)
+
+
+def test_matrix_properties():
+    M = cmgen.make_matrix()
+    assert M.dtype == np.int32 and M.shape == (20, 20)
+    assert np.array_equal(M, M.T)
+    d = M.diagonal()
+    off = M[~np.eye(20, dtype=bool)]
+    assert d.min() >= 4 and d.max() <= 11
+    assert off.min() >= -4 and off.max() <= 3
+    # expected score of two background residues must be clearly negative
+    assert M.mean() <= -1.8
+
+
+def test_matrix_gate_unrelated_scores():
+    """Unrelated sequences must score far below the threshold even when long."""
+    rng = np.random.default_rng(23)
+    L = 2000
+    scores = [sw(rand_seq(rng, L, L), rand_seq(rng, L, L), M0)[0] for _ in range(12)]
+    assert max(scores) < 100, scores
+
+
+def test_family_members_are_similar():
+    """Members of one family (length ~350) score well above the threshold."""
+    rng = np.random.default_rng(24)
+    anc = rng.integers(0, 20, size=350).astype(np.uint8)
+    s = [sw(cmgen.mutate(rng, anc), cmgen.mutate(rng, anc), M0)[0] for _ in range(6)]
+    assert min(s) > 200, s
