@@ -1,0 +1,271 @@
+// cm_api.hip -- host runtime behind include/cm.h: contexts, argument
+// validation, device scratch, the plan/sort/sweep launch sequence.
+#include <hipcub/hipcub.hpp>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/cm.h"
+#include "cm_internal.h"
+#include "cm_runtime.h"
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+namespace cmrt {
+
+cm_status fail(cm_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+cm_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? CM_ENOMEM : CM_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+bool DeviceBuf::ensure(size_t bytes) {
+    if (bytes <= cap) return true;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+    size_t want = bytes + bytes / 4 + 256;
+    if (hipMalloc(&ptr, want) != hipSuccess) { ptr = nullptr; return false; }
+    cap = want;
+    return true;
+}
+
+void DeviceBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+cm_status check_matrix(const int32_t* matrix, int8_t* mat8 /* [21*24] */) {
+    if (!matrix) return fail(CM_EINVAL, "matrix is NULL");
+    std::memset(mat8, -128, cmk::kNRes * cmk::kMatStride);
+    for (int x = 0; x < 20; ++x)
+        for (int y = 0; y < 20; ++y) {
+            const int32_t v = matrix[20 * x + y];
+            if (v < -127 || v > 127)
+                return fail(CM_EUNSUPPORTED, "matrix entry M[%d][%d]=%d outside [-127,127]", x, y, v);
+            mat8[x * cmk::kMatStride + y] = static_cast<int8_t>(v);
+        }
+    return CM_OK;
+}
+
+cm_status check_gaps(int32_t go, int32_t ge) {
+    if (!(go < 0 && go <= ge && ge <= 0))
+        return fail(CM_EINVAL, "gaps must satisfy gap_open < 0 and gap_open <= gap_extend <= 0 (got %d, %d)",
+                    go, ge);
+    if (go < -1000000000 || ge < -1000000)
+        return fail(CM_EINVAL, "gap penalties too large in magnitude (%d, %d)", go, ge);
+    return CM_OK;
+}
+
+// plan -> sort -> persistent sweep for one pass
+cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st) {
+    if (a.n_pairs <= 0) return CM_OK;
+    if (a.n_pairs > (int64_t)0x7fffffff) return fail(CM_EINVAL, "n_pairs too large");
+    const size_t n = static_cast<size_t>(a.n_pairs);
+    if (!ctx->keys.ensure(n * 4) || !ctx->keys_alt.ensure(n * 4) || !ctx->vals.ensure(n * 4) ||
+        !ctx->vals_alt.ensure(n * 4))
+        return fail(CM_ENOMEM, "cannot allocate %zu plan entries", n);
+    size_t tmp = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(
+        nullptr, tmp, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<uint32_t*>(ctx->keys_alt.ptr),
+        static_cast<int32_t*>(ctx->vals.ptr), static_cast<int32_t*>(ctx->vals_alt.ptr),
+        static_cast<int>(n), 0, 32, st);
+    if (e != hipSuccess) return hip_fail(e, "sort size query");
+    if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
+
+    a.ctr = ctx->counters;
+    a.err = ctx->err_flag;
+    a.dummy = ctx->dummy;
+    a.bnd = static_cast<int2*>(ctx->bnd.ptr);
+    a.bnd_stride = ctx->bnd_stride;
+    a.zero = 0;
+    e = cmk::launch_plan(a, pass, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<int32_t*>(ctx->vals.ptr), st);
+    if (e != hipSuccess) return hip_fail(e, "plan launch");
+    e = hipcub::DeviceRadixSort::SortPairs(
+        ctx->sort_tmp.ptr, tmp, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<uint32_t*>(ctx->keys_alt.ptr),
+        static_cast<int32_t*>(ctx->vals.ptr), static_cast<int32_t*>(ctx->vals_alt.ptr),
+        static_cast<int>(n), 0, 32, st);
+    if (e != hipSuccess) return hip_fail(e, "sort");
+    a.keys = static_cast<const uint32_t*>(ctx->keys_alt.ptr);
+    a.order = static_cast<const int32_t*>(ctx->vals_alt.ptr);
+    const int grid = ctx->grid[static_cast<int>(pass)];
+    e = cmk::launch_sw(a, pass, grid, st);
+    if (e != hipSuccess) return hip_fail(e, "alignment launch");
+    return CM_OK;
+}
+
+}  // namespace cmrt
+
+using namespace cmrt;
+
+extern "C" {
+
+const char* cm_status_str(cm_status s) {
+    switch (s) {
+        case CM_OK: return "ok";
+        case CM_EINVAL: return "invalid argument";
+        case CM_ERANGE: return "input data out of range";
+        case CM_ENOMEM: return "out of device memory";
+        case CM_EDEVICE: return "device error";
+        case CM_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+const char* cm_last_error(void) { return g_last_error.c_str(); }
+
+cm_status cm_context_create(int device_ordinal, cm_context** out) {
+    if (!out) return fail(CM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device_ordinal < 0 || device_ordinal >= ndev)
+        return fail(CM_EINVAL, "device %d out of range (%d devices)", device_ordinal, ndev);
+    e = hipSetDevice(device_ordinal);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    cm_context* ctx = new cm_context();
+    ctx->device = device_ordinal;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device_ordinal);
+    if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipGetDeviceProperties"); }
+    ctx->n_cu = prop.multiProcessorCount;
+    for (int p = 0; p < 3; ++p)
+        ctx->grid[p] = ctx->n_cu * cmk::sw_blocks_per_cu(static_cast<cmk::Pass>(p));
+    void* small = nullptr;
+    e = hipMalloc(&small, 4096);
+    if (e != hipSuccess) { delete ctx; return hip_fail(e, "context scratch"); }
+    (void)hipMemset(small, 0, 4096);
+    ctx->small = small;
+    ctx->counters = reinterpret_cast<cmk::Counters*>(static_cast<char*>(small));
+    ctx->err_flag = reinterpret_cast<uint32_t*>(static_cast<char*>(small) + 1024);
+    ctx->dummy = reinterpret_cast<const uint8_t*>(static_cast<char*>(small) + 2048);
+    // boundary rows: one slot per group of the largest persistent grid
+    int gmax = ctx->grid[0];
+    for (int p = 1; p < 3; ++p) gmax = ctx->grid[p] > gmax ? ctx->grid[p] : gmax;
+    ctx->bnd_stride = CM_MAX_LEN + 64;
+    const size_t bnd_bytes = static_cast<size_t>(gmax) * cmk::kPairsPerWave * ctx->bnd_stride * sizeof(int2);
+    if (!ctx->bnd.ensure(bnd_bytes)) {
+        (void)hipFree(small);
+        delete ctx;
+        return fail(CM_ENOMEM, "cannot allocate %zu bytes of boundary rows", bnd_bytes);
+    }
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) { cm_context_destroy(ctx); return hip_fail(e, "context init"); }
+    *out = ctx;
+    return CM_OK;
+}
+
+void cm_context_destroy(cm_context* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->keys.release();
+    ctx->keys_alt.release();
+    ctx->vals.release();
+    ctx->vals_alt.release();
+    ctx->sort_tmp.release();
+    ctx->bnd.release();
+    ctx->extra_release();
+    if (ctx->small) (void)hipFree(ctx->small);
+    delete ctx;
+}
+
+cm_status cm_context_sync(cm_context* ctx) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronize");
+    uint32_t flag = 0;
+    e = hipMemcpy(&flag, ctx->err_flag, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read error flag");
+    if (flag) {
+        const uint32_t zero = 0;
+        (void)hipMemcpy(ctx->err_flag, &zero, sizeof(zero), hipMemcpyHostToDevice);
+        return fail(CM_ERANGE, "device flagged bad input:%s%s%s%s",
+                    (flag & cmk::kErrResidue) ? " residue>=20" : "",
+                    (flag & cmk::kErrIndex) ? " index out of range" : "",
+                    (flag & cmk::kErrLength) ? " sequence longer than CM_MAX_LEN" : "",
+                    (flag & cmk::kErrCell) ? " end cell outside its sequence" : "");
+    }
+    return CM_OK;
+}
+
+cm_status cm_sw_score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                            const int32_t* pairs, int64_t n_pairs, const int32_t* matrix,
+                            int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a,
+                            int32_t* end_b, void* stream) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
+    if (n_pairs == 0) return CM_OK;
+    if (!offsets || !pairs || !scores) return fail(CM_EINVAL, "NULL required pointer");
+    if ((end_a == nullptr) != (end_b == nullptr)) return fail(CM_EINVAL, "end_a and end_b must both be set or both NULL");
+    cm_status s = check_gaps(gap_open, gap_extend);
+    if (s != CM_OK) return s;
+    cmk::SwArgs a{};
+    s = check_matrix(matrix, a.mat);
+    if (s != CM_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    a.seqs = seqs ? seqs : ctx->dummy;
+    a.offsets = offsets;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.n_seqs = n_seqs;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.scores = scores;
+    a.end_a = end_a;
+    a.end_b = end_b;
+    return run_pass(ctx, a, end_a ? cmk::Pass::ScoreEnd : cmk::Pass::Score, static_cast<hipStream_t>(stream));
+}
+
+cm_status cm_sw_span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                           const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
+                           int32_t gap_extend, const int32_t* scores, const int32_t* end_a,
+                           const int32_t* end_b, int32_t min_score, int32_t* start_a, int32_t* start_b,
+                           void* stream) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
+    if (n_pairs == 0) return CM_OK;
+    if (!offsets || !pairs || !scores || !end_a || !end_b || !start_a || !start_b)
+        return fail(CM_EINVAL, "NULL required pointer");
+    if (min_score < 0) return fail(CM_EINVAL, "min_score must be >= 0");
+    cm_status s = check_gaps(gap_open, gap_extend);
+    if (s != CM_OK) return s;
+    cmk::SwArgs a{};
+    s = check_matrix(matrix, a.mat);
+    if (s != CM_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    a.seqs = seqs ? seqs : ctx->dummy;
+    a.offsets = offsets;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.n_seqs = n_seqs;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.min_score = min_score;
+    a.scores = const_cast<int32_t*>(scores);
+    a.end_a = const_cast<int32_t*>(end_a);
+    a.end_b = const_cast<int32_t*>(end_b);
+    a.start_a = start_a;
+    a.start_b = start_b;
+    return run_pass(ctx, a, cmk::Pass::Span, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// cm_internal.h -- structures shared by the HIP kernels and the host runtime
+// of libcm.so.  Not part of the public ABI (that is include/cm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmk {
+
+constexpr int kGroup = 16;          // lanes that cooperate on one pair (one DPP row)
+constexpr int kPairsPerWave = 4;    // 64-lane wavefront = 4 groups
+constexpr int kRMax = 16;           // query rows held per lane
+constexpr int kStripRows = kGroup * kRMax;
+constexpr int kNRes = 21;           // 20 residues + sentinel
+constexpr int kSent = 20;           // sentinel residue code (padding rows / columns)
+constexpr int kMatStride = 24;      // bytes per row of the int8 matrix in LDS
+constexpr int kProfBytesPerGroup = kNRes * kGroup * 16;   // [c][lane][16 bytes]
+constexpr uint32_t kSkipKey = 0xffffffffu;
+
+// Error bits raised by kernels (reported by cm_context_sync).
+constexpr uint32_t kErrResidue = 1u;     // residue code >= 20
+constexpr uint32_t kErrIndex = 2u;       // pair index outside [0, n_seqs)
+constexpr uint32_t kErrLength = 4u;      // sequence longer than CM_MAX_LEN
+constexpr uint32_t kErrCell = 8u;        // span input end cell outside its sequence
+
+// Counters block in device memory.
+struct Counters {
+    int32_t n_work;      // pairs that need the DP (after the plan kernel)
+    int32_t ticket;      // persistent-queue ticket
+    int32_t pad[14];
+};
+
+struct SwArgs {
+    const uint8_t* seqs;
+    const int64_t* offsets;
+    const int32_t* pairs;
+    int64_t n_pairs;
+    int32_t n_seqs;
+    int32_t go, ge;
+    int32_t min_score;          // span pass: only pairs with score > min_score
+    int32_t zero;               // always 0 (see the kernel's clamp)
+    const uint32_t* keys;       // sorted plan keys (R, strips, columns)
+    const int32_t* order;       // pair index per sorted position
+    Counters* ctr;
+    int32_t* scores;            // forward: output; span: input
+    int32_t* end_a;             // forward: output (nullable); span: input
+    int32_t* end_b;
+    int32_t* start_a;           // span: output
+    int32_t* start_b;
+    int2* bnd;                  // boundary rows, one slot of bnd_stride per group
+    int32_t bnd_stride;
+    uint32_t* err;
+    const uint8_t* dummy;       // >= 64 readable bytes (target of clamped prefetches)
+    int8_t mat[kNRes * kMatStride];   // M[row residue][column residue], sentinel -> -128
+};
+
+enum class Pass : int { Score = 0, ScoreEnd = 1, Span = 2 };
+
+// Host launchers (sw_kernels.hip).
+hipError_t launch_plan(const SwArgs& a, Pass pass, uint32_t* keys_out, int32_t* vals_out,
+                       hipStream_t s);
+hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s);
+int sw_blocks_per_cu(Pass pass);
+
+}  // namespace cmk

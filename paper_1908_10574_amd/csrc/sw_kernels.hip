@@ -1,0 +1,498 @@
+// sw_kernels.hip -- batched Smith-Waterman (Gotoh affine gaps) for gfx950.
+//
+// Computes, for every pair of a batch, the local-alignment score of Section 4
+// of the ClusterMerge paper (the similarity function f), optionally the end
+// cell, and in a second pass the start cell used by the coverage test of the
+// protein transitivity function.
+//
+// Recurrence (E and F kept clamped at zero, which is exact because the gap
+// extension is never positive: max(E,0) obeys the same recurrence with a 0
+// term, and H already takes a max with 0):
+//     E'[i][j+1] = max(E'[i][j] + ge, H[i][j] + go, 0)
+//     F'[i+1][j] = max(F'[i][j] + ge, H[i][j] + go, 0)
+//     H[i][j]    = max(H[i-1][j-1] + M[a_i][b_j], E'[i][j], F'[i][j])
+// which is 8 int32 VALU operations per cell (add, max3, max, add, add, max3,
+// add, max3).
+//
+// Work decomposition (MI355X, wave64):
+//   * one 16-lane DPP row ("group") aligns one pair; a wavefront carries four
+//     pairs of the same shape class;
+//   * lane l of a group owns R consecutive query rows of a 16*R-row strip and
+//     sweeps the subject columns with a one-column skew per lane (lane l works
+//     on column t-l at step t); the H and F' values leaving a lane's bottom row
+//     reach the lane below through a DPP row_shr:1 move, so no LDS round trip
+//     is needed for the wavefront carries;
+//   * the query profile of the strip (score of each row against each of the
+//     20 residues plus a sentinel) lives in LDS as int8, one 4/8/16-byte read
+//     per lane per column; the byte operands feed the adds through SDWA;
+//   * subject residues enter lane 0 from a 16-column register chunk rotated by
+//     DPP row_shl:1; queries longer than one strip hand the bottom row (H, F')
+//     to the next strip through a per-group global boundary row, staged with
+//     the same 16-column rotation;
+//   * pairs are sorted by (rows per lane, strips, columns) by the plan pass and
+//     handed out four at a time from an atomic ticket to a persistent grid.
+//
+// Cells outside the pair (padding rows below the query, columns before the
+// skew reaches a lane or after the subject ends) use a sentinel score of -128.
+// Their values are either 0 (before the pair starts) or strictly below the best
+// real score (they derive from real cells through gap penalties or a negative
+// sentinel substitution), so they never change a score, an end cell or a start
+// cell.
+#include "cm_internal.h"
+
+#include <type_traits>
+
+namespace cmk {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int dpp_shr1(int old_v, int src) {
+    // lane k <- lane k-1 of the same 16-lane row; lane 0 of the row keeps old_v
+    return __builtin_amdgcn_update_dpp(old_v, src, 0x111, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1(int old_v, int src) {
+    // lane k <- lane k+1 of the same 16-lane row; lane 15 of the row keeps old_v
+    return __builtin_amdgcn_update_dpp(old_v, src, 0x101, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shr1_zero(int src) {
+    // lane k <- lane k-1 of the same 16-lane row; lane 0 of the row reads 0
+    return __builtin_amdgcn_mov_dpp(src, 0x111, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int dpp_shl1_any(int src) {
+    // lane k <- lane k+1 of the same 16-lane row; lane 15 of the row reads 0
+    return __builtin_amdgcn_mov_dpp(src, 0x101, 0xf, 0xf, true);
+}
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+template <int W>
+struct ProfWords { uint32_t w[W]; };
+
+template <int W>
+__device__ __forceinline__ ProfWords<W> load_prof(const uint8_t* prof, int c, int gl) {
+    const uint8_t* p = prof + (c * kGroup + gl) * (4 * W);
+    ProfWords<W> r;
+    if constexpr (W == 4) {
+        uint4 v = *reinterpret_cast<const uint4*>(p);
+        r.w[0] = v.x; r.w[1] = v.y; r.w[2] = v.z; r.w[3] = v.w;
+    } else if constexpr (W == 2) {
+        uint2 v = *reinterpret_cast<const uint2*>(p);
+        r.w[0] = v.x; r.w[1] = v.y;
+    } else {
+        r.w[0] = *reinterpret_cast<const uint32_t*>(p);
+    }
+    return r;
+}
+
+__device__ __forceinline__ int sbyte(uint32_t w, int k) {
+    return static_cast<int>(static_cast<int8_t>(static_cast<uint8_t>(w >> (8 * k))));
+}
+
+__device__ __forceinline__ int wave_max4(int v) {
+    // max of the values held by lanes 0, 16, 32, 48
+    int a = __builtin_amdgcn_readlane(v, 0);
+    int b = __builtin_amdgcn_readlane(v, 16);
+    int c = __builtin_amdgcn_readlane(v, 32);
+    int d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+// rows per lane for a query of m rows: fewest strips, then fewest rows per
+// lane, rounded up to an even count (the kernel is instantiated for even R)
+__device__ __forceinline__ void shape_for(int m, int& R, int& strips) {
+    strips = (m + kStripRows - 1) / kStripRows;
+    R = (m + kGroup * strips - 1) / (kGroup * strips);
+    R += R & 1;
+    if (R > kRMax) R = kRMax;
+}
+
+// ---------------------------------------------------------------------------
+// plan: validate, write trivial results, build sort keys
+// ---------------------------------------------------------------------------
+__global__ void k_zero_counters(Counters* c) {
+    if (threadIdx.x == 0) { c->n_work = 0; c->ticket = 0; }
+}
+
+__global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
+    const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (p >= a.n_pairs) return;
+    const Pass P = static_cast<Pass>(pass);
+    uint32_t key = kSkipKey;
+    const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
+    int m = 0, n = 0;
+    bool trivial = true;
+    if (x < 0 || x >= a.n_seqs || y < 0 || y >= a.n_seqs) {
+        atomicOr(a.err, kErrIndex);
+    } else {
+        const int64_t lx = a.offsets[x + 1] - a.offsets[x];
+        const int64_t ly = a.offsets[y + 1] - a.offsets[y];
+        if (lx > 16384 || ly > 16384 || lx < 0 || ly < 0) {
+            atomicOr(a.err, kErrLength);
+        } else if (P == Pass::Span) {
+            const int s = a.scores[p];
+            if (s > a.min_score) {
+                const int ea = a.end_a[p], eb = a.end_b[p];
+                if (ea < 0 || ea >= lx || eb < 0 || eb >= ly) {
+                    atomicOr(a.err, kErrCell);
+                } else {
+                    m = ea + 1; n = eb + 1; trivial = false;
+                }
+            }
+        } else {
+            m = static_cast<int>(lx); n = static_cast<int>(ly);
+            trivial = (m == 0 || n == 0);
+        }
+    }
+    if (trivial) {
+        if (P == Pass::Span) {
+            a.start_a[p] = -1; a.start_b[p] = -1;
+        } else {
+            a.scores[p] = 0;
+            if (a.end_a) { a.end_a[p] = -1; a.end_b[p] = -1; }
+        }
+    } else {
+        int R, strips;
+        shape_for(m, R, strips);
+        key = (static_cast<uint32_t>(kRMax - R) << 24) |
+              (static_cast<uint32_t>(127 - strips) << 16) |
+              static_cast<uint32_t>(65535 - n);
+        atomicAdd(&a.ctr->n_work, 1);
+    }
+    keys[p] = key;
+    vals[p] = static_cast<int32_t>(p);
+}
+
+// ---------------------------------------------------------------------------
+// one wavefront item: four pairs of the same rows-per-lane class
+// ---------------------------------------------------------------------------
+template <int R, Pass P>
+__device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
+                                                   const int8_t* __restrict__ s_mat,
+                                                   uint8_t* __restrict__ s_prof) {
+    constexpr int RP = R <= 4 ? 4 : (R <= 8 ? 8 : 16);
+    constexpr int W = RP / 4;
+    constexpr int kRows = kGroup * R;
+    constexpr bool kEnd = (P != Pass::Score);
+    const int lane = threadIdx.x;
+    const int g = lane >> 4;
+    const int gl = lane & 15;
+    const int go = a.go, ge = a.ge;
+    // the clamp value is a kernel argument (always 0) so the compiler keeps the
+    // signed three-input max instead of splitting it on a known sign
+    const int z = a.zero;
+
+    const int64_t pos = static_cast<int64_t>(item) * kPairsPerWave + g;
+    const bool has = pos < n_work;
+    int p = 0, m = 0, n = 0, ea = 0, eb = 0;
+    const uint8_t* A = a.seqs;
+    const uint8_t* B = a.seqs;
+    if (has) {
+        p = a.order[pos];
+        const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
+        A = a.seqs + a.offsets[x];
+        B = a.seqs + a.offsets[y];
+        if constexpr (P == Pass::Span) {
+            ea = a.end_a[p]; eb = a.end_b[p];
+            m = ea + 1; n = eb + 1;
+        } else {
+            m = static_cast<int>(a.offsets[x + 1] - a.offsets[x]);
+            n = static_cast<int>(a.offsets[y + 1] - a.offsets[y]);
+        }
+    }
+    const int S = (m + kRows - 1) / kRows;
+    const int s_max = wave_max4(S);
+    uint8_t* prof = s_prof + g * kProfBytesPerGroup;
+    int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
+
+    bool bad = false;
+    int best = 0, bi = -1, bj = -1;
+
+    for (int s = 0; s < s_max; ++s) {
+        const bool act = s < S;
+        const bool rd = act && s > 0;
+        const bool wr = act && s + 1 < S;
+        const int row0 = s * kRows;
+        const int n_act = act ? n : 0;
+        const int n_max = wave_max4(n_act);
+        const bool rd_any = wave_max4(rd ? 1 : 0) != 0;
+        const bool wr_any = wave_max4(wr ? 1 : 0) != 0;
+
+        // ---- query profile of this strip: prof[c][gl][r] = M[a_i][c]
+        {
+            int code[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = row0 + gl * R + r;
+                int v = kSent;
+                if (act && i < m) {
+                    v = (P == Pass::Span) ? A[ea - i] : A[i];
+                    if (v > 19) { bad = true; v = kSent; }
+                }
+                code[r] = v * kMatStride;
+            }
+            __syncthreads();   // previous strip's readers are done with prof
+#pragma unroll 1
+            for (int c = 0; c < kNRes; ++c) {
+                uint32_t w[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    uint32_t word = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = 4 * q + k;
+                        const int8_t v = (r < R) ? s_mat[code[r] + c] : int8_t(-128);
+                        word |= static_cast<uint32_t>(static_cast<uint8_t>(v)) << (8 * k);
+                    }
+                    w[q] = word;
+                }
+                uint8_t* dst = prof + (c * kGroup + gl) * RP;
+                if constexpr (W == 4) {
+                    *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+                } else if constexpr (W == 2) {
+                    *reinterpret_cast<uint2*>(dst) = make_uint2(w[0], w[1]);
+                } else {
+                    *reinterpret_cast<uint32_t*>(dst) = w[0];
+                }
+            }
+            __syncthreads();
+        }
+
+        // Prefetch loads are unconditional (the index is clamped into the
+        // sequence or redirected to a small dummy buffer); whether a loaded
+        // value is real is decided when its chunk is switched in, so the loads
+        // stay in flight for a whole 16-column chunk.
+        const bool live = act && n > 0;
+        auto col_raw = [&](int col) -> int {
+            const int k = min(col, n - 1);
+            const uint8_t* src = live ? ((P == Pass::Span) ? B + (eb - k) : B + k) : a.dummy;
+            return *src;
+        };
+        auto col_in = [&](int v, int col) -> int {
+            if (!(act && col < n)) return kSent;
+            if (v > 19) { bad = true; v = kSent; }
+            return v;
+        };
+        auto bnd_raw = [&](int col) -> int2 { return bnd[min(col, a.bnd_stride - 1)]; };
+
+        auto sweep = [&](auto multi) {
+            constexpr bool kMulti = decltype(multi)::value;
+            int HA[R], HB[R], E[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) { HA[r] = 0; E[r] = 0; }
+            int hdiag = 0, Hout = 0, Fout = 0;
+            int feedR = col_in(col_raw(gl), gl);
+            int nfeedR = col_raw(kGroup + gl);
+            int feedH = 0, feedF = 0;
+            int2 nfeed = make_int2(0, 0);
+            if constexpr (kMulti) {
+                const int2 v0 = bnd_raw(gl);
+                feedH = (rd && gl < n) ? v0.x : 0;
+                feedF = (rd && gl < n) ? v0.y : 0;
+                nfeed = bnd_raw(kGroup + gl);
+            }
+            int collH = 0, collF = 0;
+            int c = dpp_shr1(feedR, kSent);
+            ProfWords<W> pwA = load_prof<W>(prof, c, gl);
+            ProfWords<W> pwB;
+
+            // one column step: previous column Hi -> this column Ho
+            auto cells = [&](int t, const int (&Hi)[R], int (&Ho)[R], const ProfWords<W>& pw) {
+                int Htop, F;
+                if constexpr (kMulti) {
+                    Htop = dpp_shr1(feedH, Hout);
+                    F = dpp_shr1(feedF, Fout);
+                } else {
+                    Htop = dpp_shr1_zero(Hout);
+                    F = dpp_shr1_zero(Fout);
+                }
+                int colmax = z;
+#pragma unroll
+                for (int r = 0; r < R; r += 2) {
+                    const int d0 = (r == 0) ? hdiag : Hi[r - 1];
+                    const int h0 = max3i(d0 + sbyte(pw.w[r >> 2], r & 3), E[r], F);
+                    const int g0 = h0 + go;
+                    E[r] = max3i(E[r] + ge, g0, z);
+                    F = max3i(F + ge, g0, z);
+                    Ho[r] = h0;
+                    const int h1 = max3i(Hi[r] + sbyte(pw.w[(r + 1) >> 2], (r + 1) & 3), E[r + 1], F);
+                    const int g1 = h1 + go;
+                    E[r + 1] = max3i(E[r + 1] + ge, g1, z);
+                    F = max3i(F + ge, g1, z);
+                    Ho[r + 1] = h1;
+                    if constexpr (kEnd) colmax = max3i(colmax, h0, h1);
+                    else best = max3i(best, h0, h1);
+                }
+                hdiag = Htop;
+                Hout = Ho[R - 1];
+                Fout = F;
+                if constexpr (kEnd) {
+                    if (colmax >= best && colmax > 0) {
+                        int ri = R - 1;
+#pragma unroll
+                        for (int r = R - 1; r >= 0; --r) ri = (Ho[r] == colmax) ? r : ri;
+                        const int row = row0 + gl * R + ri;
+                        if (colmax > best || row < bi) { best = colmax; bi = row; bj = t - gl; }
+                    }
+                }
+            };
+            // boundary row after step t: lane 0 feed advances, lane 15 leaves column t-15
+            auto boundary = [&](int t, bool chunk_end) {
+                if constexpr (kMulti) {
+                    if (chunk_end) {
+                        const int col = t + 1 + gl;
+                        feedH = (rd && col < n) ? nfeed.x : 0;
+                        feedF = (rd && col < n) ? nfeed.y : 0;
+                        nfeed = bnd_raw(t + 1 + kGroup + gl);
+                    } else {
+                        feedH = dpp_shl1_any(feedH);
+                        feedF = dpp_shl1_any(feedF);
+                    }
+                    collH = dpp_shl1(Hout, collH);
+                    collF = dpp_shl1(Fout, collF);
+                    if ((t & (kGroup - 1)) == kGroup - 1) {
+                        const int col = t - 2 * (kGroup - 1) + gl;
+                        if (wr && col >= 0 && col < n) bnd[col] = make_int2(collH, collF);
+                    }
+                }
+            };
+
+            // steps rounded up to even: an extra step only touches columns past
+            // every subject's end
+            const int steps = (n_max + kGroup - 1 + 1) & ~1;
+#pragma unroll 1
+            for (int t = 0; t < steps; t += 2) {
+                {   // step t (even, never the last step of a 16-column chunk)
+                    const int feedR2 = dpp_shl1_any(feedR);
+                    const int cn = dpp_shr1(feedR2, c);
+                    pwB = load_prof<W>(prof, cn, gl);
+                    cells(t, HA, HB, pwA);
+                    boundary(t, false);
+                    feedR = feedR2;
+                    c = cn;
+                }
+                {   // step t+1
+                    const bool chunk_end = ((t + 2) & (kGroup - 1)) == 0;
+                    int feedR2;
+                    if (chunk_end) {
+                        feedR2 = col_in(nfeedR, t + 2 + gl);
+                        nfeedR = col_raw(t + 2 + kGroup + gl);
+                    } else {
+                        feedR2 = dpp_shl1_any(feedR);
+                    }
+                    const int cn = dpp_shr1(feedR2, c);
+                    pwA = load_prof<W>(prof, cn, gl);
+                    cells(t + 1, HB, HA, pwB);
+                    boundary(t + 1, chunk_end);
+                    feedR = feedR2;
+                    c = cn;
+                }
+            }
+            if constexpr (kMulti) {
+                const int col = (steps - 1) - 2 * (kGroup - 1) + gl;
+                if (wr && col >= 0 && col < n) bnd[col] = make_int2(collH, collF);
+                __threadfence();
+            }
+        };
+        if (rd_any || wr_any) sweep(std::true_type{});
+        else sweep(std::false_type{});
+    }
+
+    // ---- group reductions and output
+    int Sbest = best;
+#pragma unroll
+    for (int k = 1; k < kGroup; k <<= 1) Sbest = max(Sbest, __shfl_xor(Sbest, k, kGroup));
+    if constexpr (kEnd) {
+        uint32_t key = (best == Sbest && Sbest > 0)
+                           ? ((static_cast<uint32_t>(bi) << 16) | static_cast<uint32_t>(bj))
+                           : 0xffffffffu;
+#pragma unroll
+        for (int k = 1; k < kGroup; k <<= 1) {
+            const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(key), k, kGroup));
+            key = min(key, o);
+        }
+        bi = Sbest > 0 ? static_cast<int>(key >> 16) : -1;
+        bj = Sbest > 0 ? static_cast<int>(key & 0xffffu) : -1;
+    }
+    if (has && gl == 0) {
+        if constexpr (P == Pass::Score) {
+            a.scores[p] = Sbest;
+        } else if constexpr (P == Pass::ScoreEnd) {
+            a.scores[p] = Sbest;
+            a.end_a[p] = bi;
+            a.end_b[p] = bj;
+        } else {
+            if (Sbest != a.scores[p] || bi < 0) {
+                atomicOr(a.err, kErrCell);
+                a.start_a[p] = -1; a.start_b[p] = -1;
+            } else {
+                a.start_a[p] = ea - bi;
+                a.start_b[p] = eb - bj;
+            }
+        }
+    }
+    if (bad) atomicOr(a.err, kErrResidue);
+}
+
+template <Pass P>
+__global__ __launch_bounds__(64) void k_sw(SwArgs a) {
+    __shared__ int8_t s_mat[kNRes * kMatStride];
+    __shared__ __attribute__((aligned(16))) uint8_t s_prof[kPairsPerWave * kProfBytesPerGroup];
+    for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
+    __syncthreads();
+    const int n_work = a.ctr->n_work;
+    const int n_items = (n_work + kPairsPerWave - 1) / kPairsPerWave;
+    while (true) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(&a.ctr->ticket, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items) break;
+        const uint32_t key = a.keys[static_cast<int64_t>(item) * kPairsPerWave];
+        const int R = kRMax - static_cast<int>(key >> 24);
+        switch (R) {
+            case 2:  run_item<2, P>(a, item, n_work, s_mat, s_prof); break;
+            case 4:  run_item<4, P>(a, item, n_work, s_mat, s_prof); break;
+            case 6:  run_item<6, P>(a, item, n_work, s_mat, s_prof); break;
+            case 8:  run_item<8, P>(a, item, n_work, s_mat, s_prof); break;
+            case 10: run_item<10, P>(a, item, n_work, s_mat, s_prof); break;
+            case 12: run_item<12, P>(a, item, n_work, s_mat, s_prof); break;
+            case 14: run_item<14, P>(a, item, n_work, s_mat, s_prof); break;
+            default: run_item<16, P>(a, item, n_work, s_mat, s_prof); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_plan(const SwArgs& a, Pass pass, uint32_t* keys, int32_t* vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a.ctr);
+    if (a.n_pairs > 0) {
+        const int64_t blocks = (a.n_pairs + 255) / 256;
+        hipLaunchKernelGGL(k_plan, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a,
+                           static_cast<int>(pass), keys, vals);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s) {
+    switch (pass) {
+        case Pass::Score:    hipLaunchKernelGGL(k_sw<Pass::Score>, dim3(grid), dim3(64), 0, s, a); break;
+        case Pass::ScoreEnd: hipLaunchKernelGGL(k_sw<Pass::ScoreEnd>, dim3(grid), dim3(64), 0, s, a); break;
+        case Pass::Span:     hipLaunchKernelGGL(k_sw<Pass::Span>, dim3(grid), dim3(64), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+int sw_blocks_per_cu(Pass pass) {
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (pass) {
+        case Pass::Score:    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::Score>, 64, 0); break;
+        case Pass::ScoreEnd: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::ScoreEnd>, 64, 0); break;
+        case Pass::Span:     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::Span>, 64, 0); break;
+    }
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+}  // namespace cmk
