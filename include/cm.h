@@ -98,6 +98,86 @@ cm_status cm_sw_span_batch(cm_context* ctx,
                            int32_t min_score, int32_t* start_a, int32_t* start_b,
                            void* stream);
 
+
+/* ---------------------------------------------------------------------------
+ * ClusterMerge (Algorithm 2 "BottomUpMerge" over Algorithm 1 "Cluster Set
+ * Merge", Section 3; protein similarity and transitivity of Section 4; final
+ * in-cluster all-against-all of Section 6.1).
+ *
+ * The result equals the plain sequential algorithm: elements 0..n-1 start as
+ * one-cluster sets in a FIFO queue; two sets are popped, merged, the result
+ * pushed back, until one set remains.  Within a merge, clusters of the first
+ * set are compared in order with the not-yet-merged clusters of the second:
+ * representatives similar (score >= T) and transitive one way fully merge
+ * (the absorbed members are appended in order, skipping duplicates; the
+ * second set's cluster is tested as absorber first), otherwise the two
+ * clusters exchange the members similar to the other representative.
+ * Transitivity of representative r over representative q: score > mT and
+ * fewer than mU residues of q lie outside the optimal local alignment (both
+ * flanks).  Representative alignments are oriented (cluster of the first set
+ * = rows, cluster of the second set = columns).  Merges of one tree level are
+ * scored together on the GPU; the replay on the host is exactly sequential.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t matrix[400];
+    int32_t gap_open, gap_extend;   /* e.g. -11, -1 */
+    int32_t T;                      /* similar pair: score >= T (e.g. 120) */
+    int32_t mT;                     /* full merge needs score > mT (e.g. 166) */
+    int32_t mU;                     /* and uncovered residues < mU (e.g. 15) */
+    uint32_t screen_stages;         /* CM_STAGE_* bits screened when a screen is given */
+    float screen_tau;               /* keep a candidate pair iff logit >= screen_tau */
+    int64_t max_result_pairs;       /* keep at most this many similar pairs in the result
+                                       (counts and the set hash always cover all) */
+} cm_params;
+
+#define CM_STAGE_REP       1u       /* representative vs representative */
+#define CM_STAGE_EXCHANGE  2u       /* member vs other representative */
+#define CM_STAGE_FINAL     4u       /* in-cluster all-against-all */
+
+typedef struct {
+    int64_t rep_comparisons;        /* f(rep1, rep2) evaluations of Algorithm 1 */
+    int64_t exchange_alignments;    /* member-vs-representative tests required */
+    int64_t full_merges, exchanges;
+    int64_t rounds, waves;          /* tree levels; GPU batches */
+    int64_t aligned_pairs;          /* pairs aligned on the GPU, all stages */
+    double  aligned_cells;          /* sum of m*n over them */
+    int64_t speculative_pairs;      /* aligned but not needed by the replay */
+    int64_t cache_hits;
+    int64_t screened_out;           /* candidate pairs dropped by the screen */
+    int64_t n_clusters;
+    int64_t final_candidates;       /* unique in-cluster pairs of the final stage */
+    int64_t n_similar_pairs;        /* pairs reported (score >= T) */
+    uint64_t pair_set_hash;         /* order-independent hash of the reported (x, y, score) */
+    double  t_total_s, t_merge_s, t_final_s, t_gpu_s, t_host_s;
+} cm_stats;
+
+typedef struct cm_result cm_result;
+typedef struct cm_screen cm_screen;
+
+/* Run ClusterMerge on a device-resident sequence store (seqs, offsets: device
+ * pointers as in cm_sw_score_batch).  Synchronous.  `screen` may be NULL
+ * (plain method).  *out is library-owned; free it with cm_result_free. */
+cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets,
+                              int32_t n_seqs, const cm_params* params, const cm_screen* screen,
+                              cm_result** out);
+/* Final clusters in final-set order; members of cluster k are
+ * members[member_offsets[k] .. member_offsets[k+1]) in cluster order. */
+cm_status cm_result_clusters(const cm_result* r, int32_t* n_clusters, const int32_t** reps,
+                             const int64_t** member_offsets, const int32_t** members);
+/* Similar pairs (x < y, score >= T), sorted by (x, y); pairs/scores are
+ * NULL-free arrays of *n_pairs rows (possibly truncated to max_result_pairs). */
+cm_status cm_result_pairs(const cm_result* r, int64_t* n_pairs, const int32_t** pairs,
+                          const int32_t** scores);
+cm_status cm_result_stats(const cm_result* r, cm_stats* out);
+void      cm_result_free(cm_result* r);
+
+/* Number of pairs (x < y) of the whole store with score >= T: the all-vs-all
+ * ground truth against which ClusterMerge recall is measured (Section 6.1).
+ * Synchronous; pairs are generated on the device in triangle tiles. */
+cm_status cm_allvsall_count(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets,
+                            int32_t n_seqs, const int32_t* matrix, int32_t gap_open,
+                            int32_t gap_extend, int32_t T, int64_t* count, double* cells);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,40 @@ _lib.cm_sw_score_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _
 _lib.cm_sw_span_batch.restype = _i32
 _lib.cm_sw_span_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P, _P, _P, _i32, _P, _P, _P]
 
+
+class CMParams(ctypes.Structure):
+    _fields_ = [("matrix", _i32 * 400), ("gap_open", _i32), ("gap_extend", _i32), ("T", _i32),
+                ("mT", _i32), ("mU", _i32), ("screen_stages", ctypes.c_uint32), ("screen_tau", _f32),
+                ("max_result_pairs", _i64)]
+
+
+class CMStats(ctypes.Structure):
+    _fields_ = [("rep_comparisons", _i64), ("exchange_alignments", _i64), ("full_merges", _i64),
+                ("exchanges", _i64), ("rounds", _i64), ("waves", _i64), ("aligned_pairs", _i64),
+                ("aligned_cells", ctypes.c_double), ("speculative_pairs", _i64), ("cache_hits", _i64),
+                ("screened_out", _i64), ("n_clusters", _i64), ("final_candidates", _i64),
+                ("n_similar_pairs", _i64), ("pair_set_hash", _u64), ("t_total_s", ctypes.c_double),
+                ("t_merge_s", ctypes.c_double), ("t_final_s", ctypes.c_double), ("t_gpu_s", ctypes.c_double),
+                ("t_host_s", ctypes.c_double)]
+
+
+_lib.cm_clustermerge_run.restype = _i32
+_lib.cm_clustermerge_run.argtypes = [_P, _P, _P, _i32, ctypes.POINTER(CMParams), _P, ctypes.POINTER(_P)]
+_lib.cm_result_clusters.restype = _i32
+_lib.cm_result_clusters.argtypes = [_P, ctypes.POINTER(_i32), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                    ctypes.POINTER(_P)]
+_lib.cm_result_pairs.restype = _i32
+_lib.cm_result_pairs.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_P), ctypes.POINTER(_P)]
+_lib.cm_result_stats.restype = _i32
+_lib.cm_result_stats.argtypes = [_P, ctypes.POINTER(CMStats)]
+_lib.cm_result_free.restype = None
+_lib.cm_result_free.argtypes = [_P]
+_lib.cm_allvsall_count.restype = _i32
+_lib.cm_allvsall_count.argtypes = [_P, _P, _P, _i32, _P, _i32, _i32, _i32, ctypes.POINTER(_i64),
+                                   ctypes.POINTER(ctypes.c_double)]
+
+CM_STAGE_REP, CM_STAGE_EXCHANGE, CM_STAGE_FINAL = 1, 2, 4
+
 CM_OK, CM_EINVAL, CM_ERANGE, CM_ENOMEM, CM_EDEVICE, CM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CM_MAX_LEN = 16384
 
@@ -168,3 +202,77 @@ def sw_span_batch(residues, offsets, pairs, matrix, scores, end_a, end_b, min_sc
 
 def sync(ctx: Context | None = None):
     (ctx or context()).sync()
+
+
+def _np_from(ptr, n, dtype):
+    if n == 0 or not ptr:
+        return np.zeros(0, dtype=dtype)
+    ct = {np.int32: _i32, np.int64: _i64}[dtype]
+    return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ct)), shape=(n,)).copy()
+
+
+def make_params(matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, screen_stages=0,
+                screen_tau=0.0, max_result_pairs=1 << 62) -> CMParams:
+    p = CMParams()
+    m = _matrix_host(matrix)
+    for k in range(400):
+        p.matrix[k] = int(m[k])
+    p.gap_open, p.gap_extend, p.T, p.mT, p.mU = int(gap_open), int(gap_extend), int(T), int(mT), int(mU)
+    p.screen_stages, p.screen_tau, p.max_result_pairs = int(screen_stages), float(screen_tau), int(max_result_pairs)
+    return p
+
+
+def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1,
+                     screen=None, screen_stages=CM_STAGE_REP | CM_STAGE_EXCHANGE, screen_tau=0.0,
+                     max_result_pairs=1 << 62, ctx: Context | None = None):
+    """ClusterMerge on a device-resident store (residues u8, offsets i64: CUDA tensors).
+
+    Returns dict(clusters=[(rep, members ndarray)], pairs=ndarray [k,2], scores=ndarray [k],
+    stats=dict).  Synchronous.
+    """
+    import torch
+    ctx = ctx or context()
+    residues = _dev(residues, torch.uint8, "residues")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    torch.cuda.current_stream().synchronize()
+    p = make_params(matrix, T, mT, mU, gap_open, gap_extend, screen_stages if screen else 0, screen_tau,
+                    max_result_pairs)
+    res = _P()
+    _check(_lib.cm_clustermerge_run(ctx.handle, residues.data_ptr() if residues.numel() else None,
+                                    offsets.data_ptr(), offsets.numel() - 1, ctypes.byref(p),
+                                    screen.handle if screen is not None else None, ctypes.byref(res)))
+    try:
+        nc = _i32()
+        reps, moff, mem = _P(), _P(), _P()
+        _check(_lib.cm_result_clusters(res, ctypes.byref(nc), ctypes.byref(reps), ctypes.byref(moff),
+                                       ctypes.byref(mem)))
+        reps_a = _np_from(reps.value, nc.value, np.int32)
+        moff_a = _np_from(moff.value, nc.value + 1, np.int64)
+        mem_a = _np_from(mem.value, int(moff_a[-1]) if len(moff_a) else 0, np.int32)
+        clusters = [(int(reps_a[k]), mem_a[moff_a[k]:moff_a[k + 1]]) for k in range(nc.value)]
+        npr = _i64()
+        pp, ps = _P(), _P()
+        _check(_lib.cm_result_pairs(res, ctypes.byref(npr), ctypes.byref(pp), ctypes.byref(ps)))
+        pairs = _np_from(pp.value, 2 * npr.value, np.int32).reshape(-1, 2)
+        scores = _np_from(ps.value, npr.value, np.int32)
+        st = CMStats()
+        _check(_lib.cm_result_stats(res, ctypes.byref(st)))
+        stats = {k: getattr(st, k) for k, _ in CMStats._fields_}
+    finally:
+        _lib.cm_result_free(res)
+    return dict(clusters=clusters, pairs=pairs, scores=scores, stats=stats)
+
+
+def allvsall_count(residues, offsets, matrix, T=120, gap_open=-11, gap_extend=-1, ctx: Context | None = None):
+    """(count of pairs x < y with score >= T over the whole store, cells aligned)."""
+    import torch
+    ctx = ctx or context()
+    residues = _dev(residues, torch.uint8, "residues")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    torch.cuda.current_stream().synchronize()
+    m = _matrix_host(matrix)
+    cnt, cells = _i64(), ctypes.c_double()
+    _check(_lib.cm_allvsall_count(ctx.handle, residues.data_ptr() if residues.numel() else None,
+                                  offsets.data_ptr(), offsets.numel() - 1, m.ctypes.data, int(gap_open),
+                                  int(gap_extend), int(T), ctypes.byref(cnt), ctypes.byref(cells)))
+    return cnt.value, cells.value

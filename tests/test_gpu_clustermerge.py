@@ -1,0 +1,131 @@
+"""GPU ClusterMerge vs the sequential oracle (Algorithms 1 and 2, Section 6.1 final stage).
+
+Exact equality of the final cluster list (representatives and member order),
+of the similar-pair set with scores, and of the Algorithm 1 statistics.
+"""
+import numpy as np
+import pytest
+
+import cmgen
+from oracle import clustermerge as ocm
+from oracle import sw, sw_batch
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cm():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1908_10574_amd as cm
+    return cm
+
+
+def dev_store(ds):
+    res = torch.from_numpy(ds.residues.copy() if len(ds.residues) else np.zeros(1, np.uint8)).cuda()
+    return res, torch.from_numpy(ds.offsets.copy()).cuda()
+
+
+def run_both(cm, ds, T=120, mT=166, mU=15):
+    res, off = dev_store(ds)
+    g = cm.clustermerge_run(res, off, ds.matrix, T=T, mT=mT, mU=mU)
+    clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix, T=T, mT=mT, mU=mU)
+    return g, clusters, pairs, st
+
+
+def assert_same(g, clusters, pairs, st):
+    got = [(r, list(m)) for r, m in g["clusters"]]
+    want = [(c.rep, list(c.objs)) for c in clusters]
+    assert len(got) == len(want)
+    for k, (a, b) in enumerate(zip(got, want)):
+        assert a == b, f"cluster {k}: gpu {a[0]} {a[1][:10]} oracle {b[0]} {b[1][:10]}"
+    gp = [(int(x), int(y), int(s)) for (x, y), s in zip(g["pairs"], g["scores"])]
+    assert gp == [tuple(p) for p in pairs]
+    s = g["stats"]
+    assert s["rep_comparisons"] == st.rep_comparisons
+    assert s["exchange_alignments"] == st.exchange_alignments
+    assert s["full_merges"] == st.full_merges
+    assert s["exchanges"] == st.exchanges
+    assert s["n_similar_pairs"] == len(pairs)
+    assert s["n_clusters"] == len(clusters)
+
+
+def test_small_families_exact(cm):
+    ds = cmgen.allvsall_small()
+    g, clusters, pairs, st = run_both(cm, ds)
+    assert_same(g, clusters, pairs, st)
+    truth, cells = cm.allvsall_count(*dev_store(ds), ds.matrix)
+    otruth = ocm.allvsall(ds.residues, ds.offsets, ds.matrix)
+    assert truth == len(otruth)
+    L = ds.lengths().astype(np.float64)
+    assert cells == pytest.approx((L.sum() ** 2 - (L ** 2).sum()) / 2)
+    assert len(pairs) / truth > 0.9
+
+
+def test_zipf_families_exact(cm):
+    ds = cmgen.clustermerge_families(n_seqs=500, n_families=50, seed=212, median=120, hi=400)
+    g, clusters, pairs, st = run_both(cm, ds)
+    assert_same(g, clusters, pairs, st)
+    assert st.full_merges > 0 and st.exchanges > 0
+
+
+@pytest.mark.parametrize("mT,mU", [(10**6, 15), (120, 400), (166, 0)])
+def test_parameter_extremes_exact(cm, mT, mU):
+    ds = cmgen.clustermerge_families(n_seqs=160, n_families=20, seed=213, median=100, hi=300)
+    g, clusters, pairs, st = run_both(cm, ds, mT=mT, mU=mU)
+    assert_same(g, clusters, pairs, st)
+    if mT == 10**6:     # transitivity never holds: every pair meets once as representatives
+        assert st.rep_comparisons == ds.n * (ds.n - 1) // 2
+        truth, _ = cm.allvsall_count(*dev_store(ds), ds.matrix)
+        assert len(pairs) == truth
+
+
+def test_identical_proteins(cm):
+    rng = np.random.default_rng(4)
+    a = rng.integers(0, 20, size=60).astype(np.uint8)
+    ds = cmgen.from_list([a] * 4)
+    res, off = dev_store(ds)
+    g = cm.clustermerge_run(res, off, ds.matrix)
+    assert [(r, list(m)) for r, m in g["clusters"]] == [(3, [3, 2, 1, 0])]
+    assert g["stats"]["rep_comparisons"] == 3
+    assert len(g["pairs"]) == 6
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_tiny_inputs(cm, n):
+    ds = cmgen.clustermerge_families(n_seqs=n, n_families=1, seed=214, median=80, hi=200) if n > 0 else None
+    g, clusters, pairs, st = run_both(cm, ds)
+    assert_same(g, clusters, pairs, st)
+
+
+def test_full_scale_20k_properties(cm):
+    """The 20,000-protein workload: checks that hold at any size, oracle on a sample."""
+    ds = cmgen.clustermerge_families()
+    res, off = dev_store(ds)
+    g = cm.clustermerge_run(res, off, ds.matrix)
+    s = g["stats"]
+    pairs, scores = g["pairs"], g["scores"]
+    assert s["n_similar_pairs"] == len(pairs) > 0
+    assert (pairs[:, 0] < pairs[:, 1]).all()
+    key = pairs[:, 0].astype(np.int64) * ds.n + pairs[:, 1]
+    assert (np.diff(key) > 0).all()          # sorted and unique
+    assert (scores >= 120).all()
+    rng = np.random.default_rng(5)
+    pick = rng.choice(len(pairs), size=min(300, len(pairs)), replace=False)
+    osc = sw_batch(ds.residues, ds.offsets, pairs[pick], ds.matrix, with_end=False)
+    assert np.array_equal(osc, scores[pick])
+    # every element is in some cluster; every member appears once per cluster
+    seen = np.zeros(ds.n, bool)
+    for r, m in g["clusters"]:
+        assert r in set(m.tolist()) and len(set(m.tolist())) == len(m)
+        seen[m] = True
+    assert seen.all()
+    assert s["rep_comparisons"] < ds.n * (ds.n - 1) // 2
+    # deterministic: same result hash on a second run
+    g2 = cm.clustermerge_run(res, off, ds.matrix)
+    assert g2["stats"]["pair_set_hash"] == s["pair_set_hash"]
+    assert g2["stats"]["rep_comparisons"] == s["rep_comparisons"]
+    print({k: s[k] for k in ("rep_comparisons", "exchange_alignments", "full_merges", "exchanges", "rounds",
+                             "waves", "aligned_pairs", "aligned_cells", "n_clusters", "n_similar_pairs",
+                             "t_total_s", "t_gpu_s", "t_host_s")})
