@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the ClusterMerge hot path on one MI355X.
+
+Step = one ClusterMerge run (Algorithm 2 over Algorithm 1, the protein
+transitivity test of Section 4 and the final in-cluster all-against-all of
+Section 6.1) over 20,000 synthetic proteins in 2,000 Zipf(1.2) families
+(lognormal lengths, median 350, sigma 0.6, clipped to 30-2,000), with the
+sequence store already resident in HBM.  Every alignment is Smith-Waterman
+(Gotoh, gap open -11, extend -1, seeded 20x20 matrix), int32, bit-exact.
+
+Printed (rank 0, one JSON line): whole-step throughput in GCUPS (aligned
+cells / wall time of the step), the forward alignment kernel's achieved
+int32 op rate against the VALU roofline (HIP events around every launch in
+the timed region), ClusterMerge time and pair recall (found / all-vs-all
+truth count), a throughput leg on 1,000,000 random pairs of a 200,000-protein
+pool, and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SW GCUPS (bit-exact int32); ClusterMerge time + pair recall, learned vs plain"
+OPS_PER_CELL = 8                       # add, max3, max, add, add, max3, add, max3
+PEAK_INT32_OPS = 256 * 64 * 2.4e9      # CUs x lanes/clk x clock (MI355X)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(ds, n_sample, T=120, mT=166, mU=15):
+    """The CPU oracle (scalar C Smith-Waterman + sequential Algorithms 1-2 in
+    Python) on the first n_sample proteins of the same store."""
+    import numpy as np
+    import cmgen  # noqa: F401
+    from oracle import clustermerge as ocm
+    off = ds.offsets[: n_sample + 1]
+    res = ds.residues[: int(off[-1])]
+    judge = ocm.ProteinJudge(res, off, ds.matrix, T, mT, mU)
+    t0 = time.perf_counter()
+    clusters, _ = ocm.bottom_up_merge(n_sample, judge)
+    ocm.similar_pairs(clusters, judge.score, T)
+    dt = time.perf_counter() - t0
+    L = np.diff(off).astype(np.float64)
+    cells = sum(L[x] * L[y] for x, y in judge._score)
+    return dict(value=cells / dt / 1e9, unit="GCUPS", cores=1, kind="oracle",
+                sample=f"ClusterMerge oracle on the first {n_sample} proteins of the same store "
+                       f"({len(judge._score)} alignments, {cells:.3e} cells, {dt:.1f} s, single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-seqs", type=int, default=20000)
+    ap.add_argument("--n-families", type=int, default=2000)
+    ap.add_argument("--throughput-pairs", type=int, default=1000000)
+    ap.add_argument("--cpu-sample", type=int, default=250)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-throughput", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import cmgen
+    import paper_1908_10574_amd as cm
+
+    dev = torch.device("cuda:0")
+    ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families)
+    res = torch.from_numpy(ds.residues).to(dev)
+    off = torch.from_numpy(ds.offsets).to(dev)
+    M = ds.matrix
+    ctx = cm.context()
+    torch.cuda.synchronize()
+    log(f"store: {ds.n} proteins, {len(ds.residues)} residues")
+
+    for w in range(args.warmup):
+        g = cm.clustermerge_run(res, off, M)
+        log(f"warmup {w}: {g['stats']['t_total_s']:.2f} s")
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        g = cm.clustermerge_run(res, off, M)
+        stats.append(g["stats"])
+        log(f"step {k}: {g['stats']['t_total_s']:.2f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_s = wall / args.steps
+    s = stats[-1]
+    cells = s["aligned_cells"]
+    value = cells / step_s / 1e9
+    k_launch = sum(x["sw_launches"] for x in stats)
+    k_sec = sum(x["sw_kernel_s"] for x in stats)
+    k_cells = sum(x["aligned_cells"] for x in stats)
+    achieved = OPS_PER_CELL * k_cells / k_sec
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12, unit="TOP/s",
+                    frac=achieved / PEAK_INT32_OPS, traffic=None,
+                    kernel="k_sw (forward Smith-Waterman, score / score+end)",
+                    launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
+                    ops_per_launch=OPS_PER_CELL * k_cells / max(k_launch, 1))
+
+    out = dict(metric=METRIC, value=value, unit="GCUPS", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * step_s, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="i32", data="synthetic",
+               config=dict(workload=f"clustermerge-{ds.n}: {args.n_families} Zipf(1.2) families, lognormal "
+                                    "lengths median 350 sigma 0.6 clipped 30-2000, T=120 mT=166 mU=15, "
+                                    "gap -11/-1, matrix seed 1917, plain method",
+                           n_seqs=ds.n, residues=int(len(ds.residues))),
+               roofline=roofline)
+    out["clustermerge"] = dict(
+        time_s=step_s, aligned_cells=cells, aligned_pairs=s["aligned_pairs"], rep_comparisons=s["rep_comparisons"],
+        exchange_alignments=s["exchange_alignments"], full_merges=s["full_merges"], exchanges=s["exchanges"],
+        n_clusters=s["n_clusters"], n_similar_pairs=s["n_similar_pairs"], waves=s["waves"],
+        gpu_s=s["t_gpu_s"], host_s=s["t_host_s"], merge_s=s["t_merge_s"], final_s=s["t_final_s"])
+
+    if not args.no_recall:
+        t = time.perf_counter()
+        truth, tcells = cm.allvsall_count(res, off, M)
+        tt = time.perf_counter() - t
+        out["clustermerge"].update(truth_pairs=truth, recall=s["n_similar_pairs"] / max(truth, 1),
+                                   allvsall_s=tt, allvsall_gcups=tcells / tt / 1e9)
+        log(f"all-vs-all truth {truth} in {tt:.1f} s")
+
+    if not args.no_throughput:
+        tp = cmgen.throughput_pool(n_pairs=args.throughput_pairs)
+        r2 = torch.from_numpy(tp.residues).to(dev)
+        o2 = torch.from_numpy(tp.offsets).to(dev)
+        p2 = torch.from_numpy(tp.pairs).to(dev)
+        L = tp.lengths().astype(np.float64)
+        tcells = float((L[tp.pairs[:, 0]] * L[tp.pairs[:, 1]]).sum())
+        cm.sw_score_batch(r2, o2, p2, M)
+        ctx.sync()
+        ctx.set_timing(True)
+        n0, s0 = ctx.kernel_time(0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        reps = 3
+        for _ in range(reps):
+            cm.sw_score_batch(r2, o2, p2, M)
+        e1.record()
+        ctx.sync()
+        n1, s1 = ctx.kernel_time(0)
+        ctx.set_timing(False)
+        bt = e0.elapsed_time(e1) / 1e3 / reps
+        ks = (s1 - s0) / max(n1 - n0, 1)
+        out["sw_throughput"] = dict(
+            workload=f"throughput-{args.throughput_pairs}: random pairs of a 200,000-protein pool, 80% "
+                     "lognormal(300, 0.6) / 20% U[1000,5000]", cells=tcells, batch_s=bt, gcups=tcells / bt / 1e9,
+            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
+        log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
+        del r2, o2, p2
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ds, args.cpu_sample)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} GCUPS")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -68,6 +68,16 @@ void      cm_context_destroy(cm_context* ctx);
  * flagged bad input data since the previous sync (and clears the flag). */
 cm_status cm_context_sync(cm_context* ctx);
 
+/* Timing of the alignment kernels (not of plan/sort/copies): when on, every
+ * launch is bracketed by HIP events on its stream; cm_context_kernel_time
+ * waits for outstanding launches and returns the running totals for `pass`
+ * (CM_PASS_*): number of launches and summed device seconds. */
+#define CM_PASS_SCORE     0
+#define CM_PASS_SCORE_END 1
+#define CM_PASS_SPAN      2
+cm_status cm_context_set_timing(cm_context* ctx, int on);
+cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
+
 /* Smith-Waterman scores of a batch of pairs (Section 4: f(i, j) is the local
  * alignment score; Section 6.1: the similar-pair test).
  *   seqs     device u8 [offsets[n_seqs]]          residue codes
@@ -149,6 +159,9 @@ typedef struct {
     int64_t n_similar_pairs;        /* pairs reported (score >= T) */
     uint64_t pair_set_hash;         /* order-independent hash of the reported (x, y, score) */
     double  t_total_s, t_merge_s, t_final_s, t_gpu_s, t_host_s;
+    int64_t sw_launches;            /* forward alignment-kernel launches (timed) */
+    double  sw_kernel_s;            /* their summed device time; aligned_cells / sw_kernel_s
+                                       is the forward kernel's cell rate */
 } cm_stats;
 
 typedef struct cm_result cm_result;

@@ -33,6 +33,10 @@ _lib.cm_context_destroy.restype = None
 _lib.cm_context_destroy.argtypes = [_P]
 _lib.cm_context_sync.restype = _i32
 _lib.cm_context_sync.argtypes = [_P]
+_lib.cm_context_set_timing.restype = _i32
+_lib.cm_context_set_timing.argtypes = [_P, ctypes.c_int]
+_lib.cm_context_kernel_time.restype = _i32
+_lib.cm_context_kernel_time.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.cm_sw_score_batch.restype = _i32
 _lib.cm_sw_score_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P, _P, _P, _P]
 _lib.cm_sw_span_batch.restype = _i32
@@ -52,7 +56,7 @@ class CMStats(ctypes.Structure):
                 ("screened_out", _i64), ("n_clusters", _i64), ("final_candidates", _i64),
                 ("n_similar_pairs", _i64), ("pair_set_hash", _u64), ("t_total_s", ctypes.c_double),
                 ("t_merge_s", ctypes.c_double), ("t_final_s", ctypes.c_double), ("t_gpu_s", ctypes.c_double),
-                ("t_host_s", ctypes.c_double)]
+                ("t_host_s", ctypes.c_double), ("sw_launches", _i64), ("sw_kernel_s", ctypes.c_double)]
 
 
 _lib.cm_clustermerge_run.restype = _i32
@@ -115,6 +119,16 @@ class Context:
 
     def sync(self):
         _check(_lib.cm_context_sync(self.handle))
+
+    def set_timing(self, on: bool):
+        _check(_lib.cm_context_set_timing(self.handle, int(bool(on))))
+
+    def kernel_time(self, pass_: int):
+        """(launches, seconds) of alignment-kernel launches timed so far for a pass
+        (0 score, 1 score+end, 2 span)."""
+        n, sec = _i64(), ctypes.c_double()
+        _check(_lib.cm_context_kernel_time(self.handle, int(pass_), ctypes.byref(n), ctypes.byref(sec)))
+        return n.value, sec.value
 
 
 _default_ctx: Context | None = None

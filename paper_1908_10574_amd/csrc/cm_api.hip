@@ -103,9 +103,44 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     a.keys = static_cast<const uint32_t*>(ctx->keys_alt.ptr);
     a.order = static_cast<const int32_t*>(ctx->vals_alt.ptr);
     const int grid = ctx->grid[static_cast<int>(pass)];
+    KernelTimer& kt = ctx->timer;
+    int pair = -1;
+    if (kt.on) {
+        if (kt.next * 2 + 2 > kt.pool.size()) {
+            hipEvent_t b, c;
+            if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&c) != hipSuccess)
+                return fail(CM_EDEVICE, "timing events");
+            kt.pool.push_back(b);
+            kt.pool.push_back(c);
+        }
+        pair = static_cast<int>(kt.next++);
+        (void)hipEventRecord(kt.pool[2 * pair], st);
+    }
     e = cmk::launch_sw(a, pass, grid, st);
     if (e != hipSuccess) return hip_fail(e, "alignment launch");
+    if (pair >= 0) {
+        (void)hipEventRecord(kt.pool[2 * pair + 1], st);
+        kt.pending.emplace_back(static_cast<int>(pass), pair);
+    }
     return CM_OK;
+}
+
+void drain_timers(cm_context* ctx, bool blocking) {
+    KernelTimer& kt = ctx->timer;
+    size_t k = 0;
+    for (; k < kt.pending.size(); ++k) {
+        const int pass = kt.pending[k].first, pair = kt.pending[k].second;
+        hipEvent_t end = kt.pool[2 * pair + 1];
+        if (blocking) (void)hipEventSynchronize(end);
+        else if (hipEventQuery(end) != hipSuccess) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, kt.pool[2 * pair], end) == hipSuccess) {
+            kt.secs[pass] += ms * 1e-3;
+            kt.launches[pass] += 1;
+        }
+    }
+    kt.pending.erase(kt.pending.begin(), kt.pending.begin() + static_cast<long>(k));
+    if (kt.pending.empty()) kt.next = 0;
 }
 
 }  // namespace cmrt
@@ -181,6 +216,7 @@ void cm_context_destroy(cm_context* ctx) {
     ctx->sort_tmp.release();
     ctx->bnd.release();
     ctx->extra_release();
+    for (hipEvent_t ev : ctx->timer.pool) (void)hipEventDestroy(ev);
     if (ctx->small) (void)hipFree(ctx->small);
     delete ctx;
 }
@@ -190,6 +226,7 @@ cm_status cm_context_sync(cm_context* ctx) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "synchronize");
+    drain_timers(ctx, true);
     uint32_t flag = 0;
     e = hipMemcpy(&flag, ctx->err_flag, sizeof(flag), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read error flag");
@@ -202,6 +239,21 @@ cm_status cm_context_sync(cm_context* ctx) {
                     (flag & cmk::kErrLength) ? " sequence longer than CM_MAX_LEN" : "",
                     (flag & cmk::kErrCell) ? " end cell outside its sequence" : "");
     }
+    return CM_OK;
+}
+
+cm_status cm_context_set_timing(cm_context* ctx, int on) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    drain_timers(ctx, true);
+    ctx->timer.on = on != 0;
+    return CM_OK;
+}
+
+cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds) {
+    if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
+    drain_timers(ctx, true);
+    if (launches) *launches = ctx->timer.launches[pass];
+    if (seconds) *seconds = ctx->timer.secs[pass];
     return CM_OK;
 }
 

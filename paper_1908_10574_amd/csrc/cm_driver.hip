@@ -19,6 +19,8 @@
 // generated per element in sorted order, reusing scores already computed.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_set>
 #include <vector>
@@ -134,41 +136,58 @@ struct Aligner {
     const cm_params* p = nullptr;
     const std::vector<int32_t>* len = nullptr;
     hipStream_t st = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    Pinned h_pairs, h_out;
     cm_stats* stats = nullptr;
+    // two staging slots so that the host can prepare one batch while the
+    // device aligns the other (batches still run in order on one stream)
+    struct Slot {
+        Pinned h_pairs, h_out, h_err;
+        hipEvent_t e0 = nullptr, e1 = nullptr, done = nullptr;
+        int64_t np = 0;
+        bool spans = false;
+        double cells = 0;
+    } slot[2];
 
     cm_status init() {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(CM_EDEVICE, "stream");
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(CM_EDEVICE, "events");
+        for (Slot& sl : slot)
+            if (hipEventCreate(&sl.e0) != hipSuccess || hipEventCreate(&sl.e1) != hipSuccess ||
+                hipEventCreate(&sl.done) != hipSuccess)
+                return fail(CM_EDEVICE, "events");
         return CM_OK;
     }
     ~Aligner() {
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
+        for (Slot& sl : slot) {
+            if (sl.e0) (void)hipEventDestroy(sl.e0);
+            if (sl.e1) (void)hipEventDestroy(sl.e1);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
         if (st) (void)hipStreamDestroy(st);
     }
 
-    // Align np pairs (flat a,b).  out receives np scores, and with spans
-    // 4 more int32 per pair: end_a, end_b, start_a, start_b (start only for
-    // scores > mT, else -1).
-    cm_status run(const int32_t* pairs, int64_t np, bool spans, std::vector<int32_t>& out) {
-        out.assign(static_cast<size_t>(np) * (spans ? 5 : 1), 0);
+    // Enqueue the alignment of np pairs (flat a,b) in slot k.  With spans,
+    // the output holds 5 int32 planes: score, end_a, end_b, start_a, start_b
+    // (start only for scores > mT, else -1).
+    cm_status submit(int k, const int32_t* pairs, int64_t np, bool spans) {
+        Slot& sl = slot[k];
+        sl.np = np;
+        sl.spans = spans;
+        sl.cells = 0;
         if (np == 0) return CM_OK;
         const size_t pb = static_cast<size_t>(np) * 8, ob = static_cast<size_t>(np) * 4;
-        cmrt::DeviceBuf& d_pairs = ctx->drv[0];
-        cmrt::DeviceBuf& d_out = ctx->drv[1];
-        if (!d_pairs.ensure(pb) || !d_out.ensure(ob * 5) || !h_pairs.ensure(pb) || !h_out.ensure(ob * 5))
+        cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
+        cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
+        if (!d_pairs.ensure(pb) || !d_out.ensure(ob * (spans ? 5 : 1)) || !sl.h_pairs.ensure(pb) ||
+            !sl.h_out.ensure(ob * (spans ? 5 : 1)))
             return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(np));
-        std::memcpy(h_pairs.ptr, pairs, pb);
+        std::memcpy(sl.h_pairs.ptr, pairs, pb);
         int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
         int32_t* dea = dsc + np;
         int32_t* deb = dea + np;
         int32_t* dsa = deb + np;
         int32_t* dsb = dsa + np;
-        hipError_t e = hipMemcpyAsync(d_pairs.ptr, h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
+        hipError_t e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
-        (void)hipEventRecord(e0, st);
+        (void)hipEventRecord(sl.e0, st);
         cm_status s = cm_sw_score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np,
                                         p->matrix, p->gap_open, p->gap_extend, dsc, spans ? dea : nullptr,
                                         spans ? deb : nullptr, st);
@@ -178,24 +197,47 @@ struct Aligner {
                                  p->gap_open, p->gap_extend, dsc, dea, deb, p->mT, dsa, dsb, st);
             if (s != CM_OK) return s;
         }
-        (void)hipEventRecord(e1, st);
-        e = hipMemcpyAsync(h_out.ptr, dsc, ob * (spans ? 5 : 1), hipMemcpyDeviceToHost, st);
+        (void)hipEventRecord(sl.e1, st);
+        e = hipMemcpyAsync(sl.h_out.ptr, dsc, ob * (spans ? 5 : 1), hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "scores download");
-        e = hipStreamSynchronize(st);
+        if (!sl.h_err.ensure(16)) return fail(CM_ENOMEM, "pinned flag");
+        e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "flag download");
+        (void)hipEventRecord(sl.done, st);
+        double cells = 0;
+        for (int64_t q = 0; q < np; ++q)
+            cells += static_cast<double>((*len)[pairs[2 * q]]) * (*len)[pairs[2 * q + 1]];
+        sl.cells = cells;
+        return CM_OK;
+    }
+
+    // Wait for slot k and copy its results into out.
+    cm_status wait(int k, std::vector<int32_t>& out) {
+        Slot& sl = slot[k];
+        out.resize(static_cast<size_t>(sl.np) * (sl.spans ? 5 : 1));
+        if (sl.np == 0) return CM_OK;
+        hipError_t e = hipEventSynchronize(sl.done);
         if (e != hipSuccess) return hip_fail(e, "alignment batch");
         float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        s = cm_context_sync(ctx);   // device-side data errors
-        if (s != CM_OK) return s;
-        std::memcpy(out.data(), h_out.ptr, ob * (spans ? 5 : 1));
+        (void)hipEventElapsedTime(&ms, sl.e0, sl.e1);
+        if (*static_cast<const uint32_t*>(sl.h_err.ptr) != 0) {
+            cm_status s = cm_context_sync(ctx);   // clears the flag and describes it
+            return s != CM_OK ? s : fail(CM_ERANGE, "device flagged bad input");
+        }
+        std::memcpy(out.data(), sl.h_out.ptr, out.size() * 4);
+        cmrt::drain_timers(ctx, false);
         stats->t_gpu_s += ms * 1e-3;
         stats->waves += 1;
-        stats->aligned_pairs += np;
-        double cells = 0;
-        for (int64_t k = 0; k < np; ++k)
-            cells += static_cast<double>((*len)[pairs[2 * k]]) * (*len)[pairs[2 * k + 1]];
-        stats->aligned_cells += cells;
+        stats->aligned_pairs += sl.np;
+        stats->aligned_cells += sl.cells;
+        sl.np = 0;
         return CM_OK;
+    }
+
+    cm_status run(const int32_t* pairs, int64_t np, bool spans, std::vector<int32_t>& out) {
+        cm_status s = submit(0, pairs, np, spans);
+        if (s != CM_OK) return s;
+        return wait(0, out);
     }
 };
 
@@ -206,7 +248,6 @@ struct Cluster {
     int32_t rep;
     std::vector<int32_t> objs;
     std::unordered_set<int32_t> mem;
-    bool merged = false;
     void add(int32_t x) {
         if (mem.insert(x).second) objs.push_back(x);
     }
@@ -214,13 +255,25 @@ struct Cluster {
 };
 
 // representative-pair outcome bits
-constexpr int32_t kSim = 1, kT21 = 2, kT12 = 4;
+constexpr uint8_t kSim = 1, kT21 = 2, kT12 = 4;
+
+// One step of Algorithm 1 that changes memberships.  The order of these
+// events and the clusters that survive depend only on representative scores:
+// ExchangeSimilar changes member lists, never the merged flags or the loop.
+enum EventType : uint8_t { kAbsorb21 = 0, kAbsorb12 = 1, kExchange = 2 };
+struct Event {
+    uint8_t type;
+    int32_t i, j;             // cluster positions in the first / second set
+    size_t seen1 = 0, seen2 = 0;   // member counts at the last speculative request
+};
 
 struct MergeJob {
     int32_t set1, set2, out;
-    size_t i = 0, j = 0;          // position of the Algorithm 1 double loop
+    size_t rep_off = 0;           // offset of this merge's rep pairs in the level batch
+    std::vector<Event> events;
+    size_t next = 0;              // next event to apply
     bool done = false;
-    std::vector<int32_t> result;  // clusters of the new set
+    std::vector<int32_t> result;  // clusters of the new set, in Algorithm 1 order
 };
 
 class Driver {
@@ -234,6 +287,8 @@ public:
         al_.p = &p_;
         al_.len = &len_;
         al_.stats = &st_;
+        const char* lg = getenv("CM_LOG");
+        log_ = lg && *lg && *lg != '0';
     }
 
     cm_status run(cm_result** out);
@@ -241,18 +296,13 @@ public:
 private:
     cm_status load_lengths();
     cm_status merge_level(std::vector<MergeJob>& jobs);
-    // replay one merge until done or blocked; returns true when blocked
+    void simulate(MergeJob& job, const uint8_t* bits);
+    // apply events until done or blocked on missing scores; true when blocked
     bool replay(MergeJob& job, std::vector<int32_t>& req);
-    void dry_walk(const MergeJob& job, std::vector<int32_t>& req);
     void request_exchange(const Cluster& c1, const Cluster& c2, std::vector<int32_t>& req);
     cm_status align_requests(std::vector<int32_t>& req);
     cm_status final_stage(cm_result* res);
 
-    int32_t rep_bits(int32_t r1, int32_t r2) const {
-        int32_t v = 0;
-        rep_.find(PairMap::key(r1, r2), &v);
-        return v;
-    }
     bool score_of(int32_t x, int32_t y, int32_t* s) const { return cache_.find(unordered_key(x, y), s); }
 
     cm_context* ctx_;
@@ -260,11 +310,11 @@ private:
     cm_params p_;
     Aligner al_;
     cm_stats st_{};
+    bool log_ = false;
     std::vector<int32_t> len_;
     std::vector<Cluster> cl_;
     std::vector<std::vector<int32_t>> sets_;
     PairMap cache_;    // unordered pair -> score
-    PairMap rep_;      // oriented representative pair -> outcome bits (current level)
     PairMap pending_;  // pairs requested in the current wave
 };
 
@@ -296,93 +346,102 @@ void Driver::request_exchange(const Cluster& c1, const Cluster& c2, std::vector<
         if (!c2.has(m)) want(m, c2.rep);
 }
 
+// Algorithm 1's control flow on representative outcomes only.
+void Driver::simulate(MergeJob& job, const uint8_t* bits) {
+    const std::vector<int32_t>& cs1 = sets_[job.set1];
+    const std::vector<int32_t>& cs2 = sets_[job.set2];
+    const size_t n2 = cs2.size();
+    std::vector<uint8_t> merged2(n2, 0);
+    for (size_t i = 0; i < cs1.size(); ++i) {
+        bool merged1 = false;
+        for (size_t j = 0; j < n2; ++j) {
+            if (merged2[j]) continue;
+            ++st_.rep_comparisons;
+            const uint8_t b = bits[i * n2 + j];
+            if (!(b & kSim)) continue;
+            if (b & kT21) {                 // cluster2 absorbs cluster1; leave the inner loop
+                job.events.push_back({kAbsorb21, static_cast<int32_t>(i), static_cast<int32_t>(j)});
+                merged1 = true;
+                break;
+            }
+            if (b & kT12) {                 // cluster1 absorbs cluster2
+                job.events.push_back({kAbsorb12, static_cast<int32_t>(i), static_cast<int32_t>(j)});
+                merged2[j] = 1;
+                continue;
+            }
+            job.events.push_back({kExchange, static_cast<int32_t>(i), static_cast<int32_t>(j)});
+        }
+        if (!merged1) job.result.push_back(cs1[i]);
+    }
+    for (size_t j = 0; j < n2; ++j)
+        if (!merged2[j]) job.result.push_back(cs2[j]);
+}
+
 bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
     const std::vector<int32_t>& cs1 = sets_[job.set1];
     const std::vector<int32_t>& cs2 = sets_[job.set2];
-    while (job.i < cs1.size()) {
-        Cluster& c1 = cl_[cs1[job.i]];
-        while (job.j < cs2.size()) {
-            Cluster& c2 = cl_[cs2[job.j]];
-            if (c2.merged) { ++job.j; continue; }
-            const int32_t bits = rep_bits(c1.rep, c2.rep);
-            if (!(bits & kSim)) { ++st_.rep_comparisons; ++job.j; continue; }
-            if (bits & kT21) {                       // cluster2 absorbs cluster1
-                ++st_.rep_comparisons;
-                for (int32_t x : c1.objs) c2.add(x);
-                c1.merged = true;
-                ++st_.full_merges;
-                break;
-            }
-            if (bits & kT12) {                       // cluster1 absorbs cluster2
-                ++st_.rep_comparisons;
-                for (int32_t x : c2.objs) c1.add(x);
-                c2.merged = true;
-                ++st_.full_merges;
-                ++job.j;
-                continue;
-            }
-            // ExchangeSimilar: every member-vs-representative score must be known
-            std::vector<int32_t> add1, add2;
-            bool missing = false;
-            int64_t tests = 0;
-            for (int32_t m : c2.objs) {
-                if (c1.has(m)) continue;
-                ++tests;
-                int32_t s;
-                if (!score_of(m, c1.rep, &s)) { missing = true; continue; }
-                if (s >= p_.T) add1.push_back(m);
-            }
-            for (int32_t m : c1.objs) {
-                if (c2.has(m)) continue;
-                ++tests;
-                int32_t s;
-                if (!score_of(m, c2.rep, &s)) { missing = true; continue; }
-                if (s >= p_.T) add2.push_back(m);
-            }
-            if (missing) {
-                request_exchange(c1, c2, req);
-                dry_walk(job, req);
-                return true;
-            }
-            ++st_.rep_comparisons;
-            st_.exchange_alignments += tests;
-            ++st_.exchanges;
-            for (int32_t m : add1) c1.add(m);
-            for (int32_t m : add2) c2.add(m);
-            ++job.j;
+    std::vector<int32_t> add1, add2;
+    while (job.next < job.events.size()) {
+        Event& ev = job.events[job.next];
+        Cluster& c1 = cl_[cs1[ev.i]];
+        Cluster& c2 = cl_[cs2[ev.j]];
+        if (ev.type == kAbsorb21) {
+            for (int32_t x : c1.objs) c2.add(x);
+            ++st_.full_merges;
+            ++job.next;
+            continue;
         }
-        if (!c1.merged) job.result.push_back(cs1[job.i]);
-        ++job.i;
-        job.j = 0;
+        if (ev.type == kAbsorb12) {
+            for (int32_t x : c2.objs) c1.add(x);
+            ++st_.full_merges;
+            ++job.next;
+            continue;
+        }
+        // ExchangeSimilar: every member-vs-representative score must be known
+        add1.clear();
+        add2.clear();
+        bool missing = false;
+        int64_t tests = 0;
+        for (int32_t m : c2.objs) {
+            if (c1.has(m)) continue;
+            ++tests;
+            int32_t s;
+            if (!score_of(m, c1.rep, &s)) { missing = true; continue; }
+            if (s >= p_.T) add1.push_back(m);
+        }
+        for (int32_t m : c1.objs) {
+            if (c2.has(m)) continue;
+            ++tests;
+            int32_t s;
+            if (!score_of(m, c2.rep, &s)) { missing = true; continue; }
+            if (s >= p_.T) add2.push_back(m);
+        }
+        if (missing) {
+            request_exchange(c1, c2, req);
+            ev.seen1 = c1.objs.size();
+            ev.seen2 = c2.objs.size();
+            // speculative requests for the later exchanges, with the member
+            // lists known now; skipped when nothing grew since the last time
+            for (size_t k = job.next + 1; k < job.events.size(); ++k) {
+                Event& e2 = job.events[k];
+                if (e2.type != kExchange) continue;
+                const Cluster& d1 = cl_[cs1[e2.i]];
+                const Cluster& d2 = cl_[cs2[e2.j]];
+                if (d1.objs.size() == e2.seen1 && d2.objs.size() == e2.seen2) continue;
+                request_exchange(d1, d2, req);
+                e2.seen1 = d1.objs.size();
+                e2.seen2 = d2.objs.size();
+            }
+            return true;
+        }
+        st_.exchange_alignments += tests;
+        ++st_.exchanges;
+        for (int32_t m : add1) c1.add(m);
+        for (int32_t m : add2) c2.add(m);
+        ++job.next;
     }
-    for (int32_t c : cs2)
-        if (!cl_[c].merged) job.result.push_back(c);
     job.done = true;
     return false;
-}
-
-// After the replay blocks at (i, j): walk the rest of the merge with the
-// full-merge and break decisions (known from representative scores alone) and
-// request the pairs of every later exchange with the memberships known now.
-void Driver::dry_walk(const MergeJob& job, std::vector<int32_t>& req) {
-    const std::vector<int32_t>& cs1 = sets_[job.set1];
-    const std::vector<int32_t>& cs2 = sets_[job.set2];
-    std::unordered_set<int32_t> merged2;   // clusters of cs2 merged during the walk
-    size_t i = job.i, j = job.j + 1;
-    while (i < cs1.size()) {
-        const Cluster& c1 = cl_[cs1[i]];
-        for (; j < cs2.size(); ++j) {
-            const Cluster& c2 = cl_[cs2[j]];
-            if (c2.merged || merged2.count(cs2[j])) continue;
-            const int32_t bits = rep_bits(c1.rep, c2.rep);
-            if (!(bits & kSim)) continue;
-            if (bits & kT21) break;
-            if (bits & kT12) { merged2.insert(cs2[j]); continue; }
-            request_exchange(c1, c2, req);
-        }
-        ++i;
-        j = 0;
-    }
 }
 
 cm_status Driver::align_requests(std::vector<int32_t>& req) {
@@ -396,36 +455,55 @@ cm_status Driver::align_requests(std::vector<int32_t>& req) {
 }
 
 cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
+    const auto t0 = Clock::now();
     // wave A: all representative pairs, oriented (cs1 rep, cs2 rep), with spans
     std::vector<int32_t> pairs;
-    for (const MergeJob& job : jobs)
-        for (int32_t a : sets_[job.set1])
+    size_t total = 0;
+    for (MergeJob& job : jobs) {
+        job.rep_off = total;
+        total += sets_[job.set1].size() * sets_[job.set2].size();
+    }
+    pairs.resize(2 * total);
+    for (const MergeJob& job : jobs) {
+        size_t k = job.rep_off;
+        for (int32_t a : sets_[job.set1]) {
+            const int32_t ra = cl_[a].rep;
             for (int32_t b : sets_[job.set2]) {
-                pairs.push_back(cl_[a].rep);
-                pairs.push_back(cl_[b].rep);
+                pairs[2 * k] = ra;
+                pairs[2 * k + 1] = cl_[b].rep;
+                ++k;
             }
+        }
+    }
     std::vector<int32_t> out;
-    cm_status s = al_.run(pairs.data(), static_cast<int64_t>(pairs.size() / 2), true, out);
+    cm_status s = al_.run(pairs.data(), static_cast<int64_t>(total), true, out);
     if (s != CM_OK) return s;
-    rep_.clear();
-    const size_t np = pairs.size() / 2;
-    for (size_t k = 0; k < np; ++k) {
+    const auto t1 = Clock::now();
+    std::vector<uint8_t> bits(total);
+    for (size_t k = 0; k < total; ++k) {
         const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
         const int32_t sc = out[k];
-        int32_t bits = 0;
-        if (sc >= p_.T) bits |= kSim;
+        uint8_t b = 0;
+        if (sc >= p_.T) {
+            b |= kSim;
+            // similar representative scores may be needed again (exchanges, final stage)
+            cache_.put(unordered_key(r1, r2), sc);
+        }
         if (sc > p_.mT) {
-            const int32_t ea = out[np + k], eb = out[2 * np + k], sa = out[3 * np + k], sb = out[4 * np + k];
+            const int32_t ea = out[total + k], eb = out[2 * total + k];
+            const int32_t sa = out[3 * total + k], sb = out[4 * total + k];
             const int32_t u1 = len_[r1] - (ea - sa + 1);
             const int32_t u2 = len_[r2] - (eb - sb + 1);
-            if (u1 < p_.mU) bits |= kT21;   // cluster2's rep covers nearly all of rep1
-            if (u2 < p_.mU) bits |= kT12;
+            if (u1 < p_.mU) b |= kT21;   // cluster2's rep covers nearly all of rep1
+            if (u2 < p_.mU) b |= kT12;
         }
-        rep_.put(PairMap::key(r1, r2), bits);
-        cache_.put(unordered_key(r1, r2), sc);
+        bits[k] = b;
     }
+    for (MergeJob& job : jobs) simulate(job, bits.data() + job.rep_off);
+    const auto t2 = Clock::now();
     // exchange waves
     std::vector<int32_t> req;
+    int waves = 0;
     while (true) {
         bool any_blocked = false;
         for (MergeJob& job : jobs)
@@ -433,13 +511,20 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
         if (!any_blocked) break;
         s = align_requests(req);
         if (s != CM_OK) return s;
+        ++waves;
     }
+    const auto t3 = Clock::now();
+    if (log_)
+        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs simulate=%.3fs exchange=%.3fs (%d waves)\n",
+                jobs.size(), total, secs(t0, t1), secs(t1, t2), secs(t2, t3), waves);
     return CM_OK;
 }
 
 // Final stage: unique (x, y), x < y, sharing a cluster, generated per x in
-// sorted order; scores reused from the cache when known.
+// sorted order; scores reused from the cache when known.  Candidate
+// generation for the next chunk overlaps the alignment of the current one.
 cm_status Driver::final_stage(cm_result* res) {
+    const auto t0 = Clock::now();
     const std::vector<int32_t>& fin = sets_.back();
     std::vector<std::vector<int32_t>> sorted(fin.size());
     std::vector<std::vector<int32_t>> of(n_);   // clusters containing each element
@@ -448,10 +533,11 @@ cm_status Driver::final_stage(cm_result* res) {
         std::sort(sorted[k].begin(), sorted[k].end());
         for (int32_t x : sorted[k]) of[x].push_back(static_cast<int32_t>(k));
     }
-    const int64_t kChunk = 1 << 22;
-    std::vector<int32_t> batch, cand_x, cand_y, known_s;   // candidates of the current chunk
-    std::vector<int8_t> known;
-    std::vector<int32_t> gpu;
+    const int64_t kChunk = 1 << 21;
+    struct Chunk {
+        std::vector<int32_t> gpu;            // pairs sent to the device
+        std::vector<int32_t> cx, cy, cs;     // candidates; cs = known score or -1
+    } ch[2];
     uint64_t hash = 0;
     auto mixp = [](uint64_t z) {
         z += 0x9e3779b97f4a7c15ull;
@@ -459,28 +545,40 @@ cm_status Driver::final_stage(cm_result* res) {
         z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
         return z ^ (z >> 31);
     };
-    auto flush = [&]() -> cm_status {
-        std::vector<int32_t> out;
-        cm_status s = al_.run(batch.data(), static_cast<int64_t>(batch.size() / 2), false, out);
-        if (s != CM_OK) return s;
+    auto consume = [&](Chunk& c, const std::vector<int32_t>& out) {
         size_t g = 0;
-        for (size_t k = 0; k < cand_x.size(); ++k) {
-            const int32_t sc = known[k] ? known_s[k] : out[g++];
+        for (size_t k = 0; k < c.cx.size(); ++k) {
+            const int32_t sc = c.cs[k] >= 0 ? c.cs[k] : out[g++];
             if (sc >= p_.T) {
                 ++st_.n_similar_pairs;
-                hash += mixp((static_cast<uint64_t>(cand_x[k]) << 32 | static_cast<uint32_t>(cand_y[k])) ^
+                hash += mixp((static_cast<uint64_t>(c.cx[k]) << 32 | static_cast<uint32_t>(c.cy[k])) ^
                              (static_cast<uint64_t>(sc) << 17));
                 if (static_cast<int64_t>(res->pair_scores.size()) < p_.max_result_pairs) {
-                    res->pairs.push_back(cand_x[k]);
-                    res->pairs.push_back(cand_y[k]);
+                    res->pairs.push_back(c.cx[k]);
+                    res->pairs.push_back(c.cy[k]);
                     res->pair_scores.push_back(sc);
                 }
             }
         }
-        batch.clear(); cand_x.clear(); cand_y.clear(); known.clear(); known_s.clear();
+        c.gpu.clear(); c.cx.clear(); c.cy.clear(); c.cs.clear();
+    };
+    int cur = 0;
+    bool inflight = false;      // chunk 1-cur is on the device
+    std::vector<int32_t> out, ys;
+    auto ship = [&]() -> cm_status {
+        // submit the current chunk, then finish the previous one
+        Chunk& c = ch[cur];
+        cm_status s = al_.submit(cur, c.gpu.data(), static_cast<int64_t>(c.gpu.size() / 2), false);
+        if (s != CM_OK) return s;
+        if (inflight) {
+            s = al_.wait(1 - cur, out);
+            if (s != CM_OK) return s;
+            consume(ch[1 - cur], out);
+        }
+        inflight = true;
+        cur = 1 - cur;
         return CM_OK;
     };
-    std::vector<int32_t> ys;
     for (int32_t x = 0; x < n_; ++x) {
         ys.clear();
         for (int32_t k : of[x]) {
@@ -492,29 +590,31 @@ cm_status Driver::final_stage(cm_result* res) {
             std::sort(ys.begin(), ys.end());
             ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
         }
+        Chunk& c = ch[cur];
         for (int32_t y : ys) {
             ++st_.final_candidates;
             int32_t sc;
-            cand_x.push_back(x);
-            cand_y.push_back(y);
+            c.cx.push_back(x);
+            c.cy.push_back(y);
             if (cache_.find(PairMap::key(x, y), &sc)) {
                 ++st_.cache_hits;
-                known.push_back(1);
-                known_s.push_back(sc);
+                c.cs.push_back(sc);
             } else {
-                known.push_back(0);
-                known_s.push_back(0);
-                batch.push_back(x);
-                batch.push_back(y);
+                c.cs.push_back(-1);
+                c.gpu.push_back(x);
+                c.gpu.push_back(y);
             }
         }
-        if (static_cast<int64_t>(batch.size() / 2) >= kChunk || static_cast<int64_t>(cand_x.size()) >= 4 * kChunk) {
-            cm_status s = flush();
+        if (static_cast<int64_t>(c.gpu.size() / 2) >= kChunk || static_cast<int64_t>(c.cx.size()) >= 4 * kChunk) {
+            cm_status s = ship();
             if (s != CM_OK) return s;
         }
     }
-    cm_status s = flush();
+    cm_status s = ship();
     if (s != CM_OK) return s;
+    s = al_.wait(1 - cur, out);
+    if (s != CM_OK) return s;
+    consume(ch[1 - cur], out);
     st_.pair_set_hash = hash;
     // clusters in final-set order
     res->member_offsets.push_back(0);
@@ -524,12 +624,20 @@ cm_status Driver::final_stage(cm_result* res) {
         res->member_offsets.push_back(static_cast<int64_t>(res->members.size()));
     }
     st_.n_clusters = static_cast<int64_t>(fin.size());
+    if (log_)
+        fprintf(stderr, "[cm] final candidates=%lld cache_hits=%lld similar=%lld %.3fs\n",
+                static_cast<long long>(st_.final_candidates), static_cast<long long>(st_.cache_hits),
+                static_cast<long long>(st_.n_similar_pairs), secs(t0, Clock::now()));
     return CM_OK;
 }
 
-
 cm_status Driver::run(cm_result** out) {
     const auto t0 = Clock::now();
+    cmrt::drain_timers(ctx_, true);
+    const bool timer_was_on = ctx_->timer.on;
+    ctx_->timer.on = true;
+    const int64_t l0 = ctx_->timer.launches[0] + ctx_->timer.launches[1];
+    const double k0 = ctx_->timer.secs[0] + ctx_->timer.secs[1];
     cm_status s = al_.init();
     if (s != CM_OK) return s;
     s = load_lengths();
@@ -587,6 +695,10 @@ cm_status Driver::run(cm_result** out) {
     st_.t_final_s = secs(t1, t2);
     st_.t_total_s = secs(t0, t2);
     st_.t_host_s = st_.t_total_s - st_.t_gpu_s;
+    cmrt::drain_timers(ctx_, true);
+    st_.sw_launches = ctx_->timer.launches[0] + ctx_->timer.launches[1] - l0;
+    st_.sw_kernel_s = ctx_->timer.secs[0] + ctx_->timer.secs[1] - k0;
+    ctx_->timer.on = timer_was_on;
     res->stats = st_;
     *out = res;
     return CM_OK;
@@ -682,9 +794,9 @@ cm_status cm_allvsall_count(cm_context* ctx, const uint8_t* seqs, const int64_t*
     if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");
     const int64_t total = static_cast<int64_t>(n_seqs) * (n_seqs - 1) / 2;
     const int64_t chunk = std::min<int64_t>(total, 1 << 23);
-    cmrt::DeviceBuf& d_pairs = ctx->drv[2];
-    cmrt::DeviceBuf& d_sc = ctx->drv[3];
-    cmrt::DeviceBuf& d_cnt = ctx->drv[4];
+    cmrt::DeviceBuf& d_pairs = ctx->drv[5];
+    cmrt::DeviceBuf& d_sc = ctx->drv[6];
+    cmrt::DeviceBuf& d_cnt = ctx->drv[7];
     if (!d_pairs.ensure(chunk * 8) || !d_sc.ensure(chunk * 4) || !d_cnt.ensure(64))
         return cmrt::fail(CM_ENOMEM, "all-vs-all scratch");
     unsigned long long* dcnt = static_cast<unsigned long long*>(d_cnt.ptr);

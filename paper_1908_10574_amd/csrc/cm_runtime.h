@@ -7,6 +7,9 @@
 #include "../../include/cm.h"
 #include "cm_internal.h"
 
+#include <utility>
+#include <vector>
+
 namespace cmrt {
 
 // A growable device allocation owned by a context.
@@ -21,6 +24,16 @@ cm_status fail(cm_status s, const char* fmt, ...);
 cm_status hip_fail(hipError_t e, const char* what);
 cm_status check_matrix(const int32_t* matrix, int8_t* mat8);
 cm_status check_gaps(int32_t go, int32_t ge);
+
+// Optional HIP-event timing of every alignment-kernel launch, per pass.
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;           // begin/end pairs
+    std::vector<std::pair<int, int>> pending;   // (pass, pair index), in stream order
+    size_t next = 0;
+    double secs[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+};
 
 }  // namespace cmrt
 
@@ -37,11 +50,15 @@ struct cm_context {
     int32_t bnd_stride = 0;
     // buffers of the ClusterMerge driver and the screen (released with the context)
     cmrt::DeviceBuf drv[8];
+    cmrt::KernelTimer timer;
     void extra_release() {
         for (auto& b : drv) b.release();
     }
 };
 
 namespace cmrt {
+// accumulate the durations of timed launches that have completed
+// (blocking = wait for all of them)
+void drain_timers(cm_context* ctx, bool blocking);
 cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st);
 }
