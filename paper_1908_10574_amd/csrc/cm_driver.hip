@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -264,7 +265,6 @@ enum EventType : uint8_t { kAbsorb21 = 0, kAbsorb12 = 1, kExchange = 2 };
 struct Event {
     uint8_t type;
     int32_t i, j;             // cluster positions in the first / second set
-    size_t seen1 = 0, seen2 = 0;   // member counts at the last speculative request
 };
 
 struct MergeJob {
@@ -300,6 +300,7 @@ private:
     // apply events until done or blocked on missing scores; true when blocked
     bool replay(MergeJob& job, std::vector<int32_t>& req);
     void request_exchange(const Cluster& c1, const Cluster& c2, std::vector<int32_t>& req);
+    void speculate(MergeJob& job, std::vector<int32_t>& req);
     cm_status align_requests(std::vector<int32_t>& req);
     cm_status final_stage(cm_result* res);
 
@@ -377,6 +378,66 @@ void Driver::simulate(MergeJob& job, const uint8_t* bits) {
         if (!merged2[j]) job.result.push_back(cs2[j]);
 }
 
+// The replay is blocked at event job.next (its own pairs are requested).
+// Walk the remaining events with simulated member lists: full merges add the
+// absorbed members exactly; an exchange adds every member whose score is
+// known similar or not yet known (a superset of what it will add).  Pairs of
+// every later exchange are requested against these lists, so that most of the
+// merge completes after one more wave.
+void Driver::speculate(MergeJob& job, std::vector<int32_t>& req) {
+    const std::vector<int32_t>& cs1 = sets_[job.set1];
+    const std::vector<int32_t>& cs2 = sets_[job.set2];
+    std::unordered_map<int32_t, std::vector<int32_t>> extra;          // simulated additions
+    std::unordered_map<int32_t, std::unordered_set<int32_t>> extra_set;
+    auto has = [&](int32_t cid, int32_t m) {
+        if (cl_[cid].has(m)) return true;
+        auto it = extra_set.find(cid);
+        return it != extra_set.end() && it->second.count(m) != 0;
+    };
+    auto add = [&](int32_t cid, int32_t m) {
+        if (has(cid, m)) return;
+        extra[cid].push_back(m);
+        extra_set[cid].insert(m);
+    };
+    auto members = [&](int32_t cid, std::vector<int32_t>& out) {
+        out = cl_[cid].objs;
+        auto it = extra.find(cid);
+        if (it != extra.end()) out.insert(out.end(), it->second.begin(), it->second.end());
+    };
+    auto want = [&](int32_t m, int32_t rep) {
+        int32_t sc;
+        const uint64_t k = unordered_key(m, rep);
+        if (cache_.find(k, &sc)) return sc >= p_.T;
+        if (!pending_.find(k, &sc)) {
+            pending_.put(k, 0);
+            req.push_back(m);
+            req.push_back(rep);
+        }
+        return true;   // unknown: assume similar
+    };
+    std::vector<int32_t> m1, m2;
+    for (size_t k = job.next; k < job.events.size(); ++k) {
+        const Event& ev = job.events[k];
+        const int32_t a = cs1[ev.i], b = cs2[ev.j];
+        members(a, m1);
+        members(b, m2);
+        if (ev.type == kAbsorb21) {
+            for (int32_t x : m1) add(b, x);
+        } else if (ev.type == kAbsorb12) {
+            for (int32_t x : m2) add(a, x);
+        } else {
+            const int32_t ra = cl_[a].rep, rb = cl_[b].rep;
+            std::vector<int32_t> to_a, to_b;
+            for (int32_t x : m2)
+                if (!has(a, x) && want(x, ra)) to_a.push_back(x);
+            for (int32_t x : m1)
+                if (!has(b, x) && want(x, rb)) to_b.push_back(x);
+            for (int32_t x : to_a) add(a, x);
+            for (int32_t x : to_b) add(b, x);
+        }
+    }
+}
+
 bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
     const std::vector<int32_t>& cs1 = sets_[job.set1];
     const std::vector<int32_t>& cs2 = sets_[job.set2];
@@ -417,21 +478,7 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
             if (s >= p_.T) add2.push_back(m);
         }
         if (missing) {
-            request_exchange(c1, c2, req);
-            ev.seen1 = c1.objs.size();
-            ev.seen2 = c2.objs.size();
-            // speculative requests for the later exchanges, with the member
-            // lists known now; skipped when nothing grew since the last time
-            for (size_t k = job.next + 1; k < job.events.size(); ++k) {
-                Event& e2 = job.events[k];
-                if (e2.type != kExchange) continue;
-                const Cluster& d1 = cl_[cs1[e2.i]];
-                const Cluster& d2 = cl_[cs2[e2.j]];
-                if (d1.objs.size() == e2.seen1 && d2.objs.size() == e2.seen2) continue;
-                request_exchange(d1, d2, req);
-                e2.seen1 = d1.objs.size();
-                e2.seen2 = d2.objs.size();
-            }
+            speculate(job, req);
             return true;
         }
         st_.exchange_alignments += tests;
@@ -504,19 +551,26 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     // exchange waves
     std::vector<int32_t> req;
     int waves = 0;
+    double t_rep = 0, t_al = 0;
+    size_t n_req = 0;
     while (true) {
         bool any_blocked = false;
+        auto q0 = Clock::now();
         for (MergeJob& job : jobs)
             if (!job.done && replay(job, req)) any_blocked = true;
+        auto q1 = Clock::now();
+        t_rep += secs(q0, q1);
         if (!any_blocked) break;
+        n_req += req.size() / 2;
         s = align_requests(req);
         if (s != CM_OK) return s;
+        t_al += secs(q1, Clock::now());
         ++waves;
     }
     const auto t3 = Clock::now();
     if (log_)
-        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs simulate=%.3fs exchange=%.3fs (%d waves)\n",
-                jobs.size(), total, secs(t0, t1), secs(t1, t2), secs(t2, t3), waves);
+        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f align %.3f)\n",
+                jobs.size(), total, secs(t0, t1), secs(t1, t2), secs(t2, t3), waves, n_req, t_rep, t_al);
     return CM_OK;
 }
 
@@ -564,34 +618,54 @@ cm_status Driver::final_stage(cm_result* res) {
     };
     int cur = 0;
     bool inflight = false;      // chunk 1-cur is on the device
+    double t_submit = 0, t_wait = 0, t_consume = 0;
     std::vector<int32_t> out, ys;
     auto ship = [&]() -> cm_status {
         // submit the current chunk, then finish the previous one
         Chunk& c = ch[cur];
+        auto q0 = Clock::now();
         cm_status s = al_.submit(cur, c.gpu.data(), static_cast<int64_t>(c.gpu.size() / 2), false);
         if (s != CM_OK) return s;
+        auto q1 = Clock::now();
+        t_submit += secs(q0, q1);
         if (inflight) {
             s = al_.wait(1 - cur, out);
             if (s != CM_OK) return s;
+            auto q2 = Clock::now();
+            t_wait += secs(q1, q2);
             consume(ch[1 - cur], out);
+            t_consume += secs(q2, Clock::now());
         }
         inflight = true;
         cur = 1 - cur;
         return CM_OK;
     };
+    std::vector<int32_t> tmp;
     for (int32_t x = 0; x < n_; ++x) {
-        ys.clear();
-        for (int32_t k : of[x]) {
-            const std::vector<int32_t>& v = sorted[k];
-            auto it = std::upper_bound(v.begin(), v.end(), x);
-            ys.insert(ys.end(), it, v.end());
-        }
-        if (of[x].size() > 1) {
-            std::sort(ys.begin(), ys.end());
-            ys.erase(std::unique(ys.begin(), ys.end()), ys.end());
+        // y > x sharing a cluster with x: the union of the sorted member
+        // suffixes of x's clusters, merged linearly
+        const int32_t* yb;
+        const int32_t* ye;
+        if (of[x].size() == 1) {
+            const std::vector<int32_t>& v = sorted[of[x][0]];
+            ye = v.data() + v.size();
+            yb = std::upper_bound(v.data(), ye, x);
+        } else {
+            ys.clear();
+            for (int32_t k : of[x]) {
+                const std::vector<int32_t>& v = sorted[k];
+                const int32_t* b = std::upper_bound(v.data(), v.data() + v.size(), x);
+                tmp.resize(ys.size() + static_cast<size_t>(v.data() + v.size() - b));
+                auto e = std::set_union(ys.begin(), ys.end(), b, v.data() + v.size(), tmp.begin());
+                tmp.resize(static_cast<size_t>(e - tmp.begin()));
+                ys.swap(tmp);
+            }
+            yb = ys.data();
+            ye = ys.data() + ys.size();
         }
         Chunk& c = ch[cur];
-        for (int32_t y : ys) {
+        for (const int32_t* py = yb; py != ye; ++py) {
+            const int32_t y = *py;
             ++st_.final_candidates;
             int32_t sc;
             c.cx.push_back(x);
@@ -625,9 +699,9 @@ cm_status Driver::final_stage(cm_result* res) {
     }
     st_.n_clusters = static_cast<int64_t>(fin.size());
     if (log_)
-        fprintf(stderr, "[cm] final candidates=%lld cache_hits=%lld similar=%lld %.3fs\n",
+        fprintf(stderr, "[cm] final candidates=%lld cache_hits=%lld similar=%lld %.3fs (submit %.3f wait %.3f consume %.3f)\n",
                 static_cast<long long>(st_.final_candidates), static_cast<long long>(st_.cache_hits),
-                static_cast<long long>(st_.n_similar_pairs), secs(t0, Clock::now()));
+                static_cast<long long>(st_.n_similar_pairs), secs(t0, Clock::now()), t_submit, t_wait, t_consume);
     return CM_OK;
 }
 
