@@ -191,6 +191,45 @@ cm_status cm_allvsall_count(cm_context* ctx, const uint8_t* seqs, const int64_t*
                             int32_t n_seqs, const int32_t* matrix, int32_t gap_open,
                             int32_t gap_extend, int32_t T, int64_t* count, double* cells);
 
+
+/* ---------------------------------------------------------------------------
+ * Learned pair screen (not in the paper: a pre-filter in front of the exact
+ * similarity function of Section 4).  A candidate pair is aligned only if the
+ * screen's logit is >= tau; the alignment score still decides similarity.
+ *
+ * Features: per protein, counts of its 3-mers (code = 400 a_p + 20 a_{p+1} +
+ * a_{p+2}) hashed into 1024 buckets (top 10 bits of code * 2654435761 mod
+ * 2^32), divided by 8, stored as bf16 bit patterns [n_seqs][1024].
+ * Network: x = [|f_a - f_b|, f_a * f_b] (2048, bf16), z = W3 relu(W2 relu(W1 x
+ * + b1) + b2) + b3 with W1 512x2048, W2 512x512, W3 1x512 in bf16 on MFMA,
+ * fp32 accumulation, hidden activations rounded to bf16.  Training: mean
+ * binary cross-entropy on logits, Adam (beta 0.9/0.999, eps 1e-8) on fp32
+ * master weights.  The fp32 master vector is W1, b1, W2, b2, W3, b3
+ * (cm_screen_num_params() values, row-major).
+ * ------------------------------------------------------------------------- */
+cm_status cm_kmer_features(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                           uint16_t* feat /* device [n_seqs][1024] */, void* stream);
+int64_t   cm_screen_num_params(void);
+/* New screen with Kaiming-uniform weights drawn from `seed`, zero biases. */
+cm_status cm_screen_create(cm_context* ctx, uint64_t seed, cm_screen** out);
+void      cm_screen_destroy(cm_screen* s);
+cm_status cm_screen_set_weights(cm_screen* s, const float* host_fp32_master);   /* also resets Adam */
+/* host_bf16 (nullable) receives the bf16 W1, W2, W3 the network uses, concatenated. */
+cm_status cm_screen_get_weights(const cm_screen* s, float* host_fp32_master, uint16_t* host_bf16);
+/* Logits of pair rows (device i32 [n][2]) into device fp32 [n]; enqueued on stream. */
+cm_status cm_screen_infer(const cm_screen* s, const uint16_t* feat, const int32_t* pairs, int64_t n_pairs,
+                          float* logits, void* stream);
+/* Synchronous: gradients of the mean loss over the batch (labels device u8 [n],
+ * 1 = similar) into host fp32 [num_params]; loss (host, nullable). n <= 2^20. */
+cm_status cm_screen_grads(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                          int64_t n_pairs, float* host_grads, float* loss);
+/* Synchronous: one Adam step on the batch; loss (host, nullable) is the batch's
+ * mean loss before the update. */
+cm_status cm_screen_train_step(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                               int64_t n_pairs, float lr, float* loss);
+cm_status cm_screen_save(const cm_screen* s, const char* path);       /* weights + Adam state */
+cm_status cm_screen_load(cm_context* ctx, const char* path, cm_screen** out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -290,3 +290,122 @@ def allvsall_count(residues, offsets, matrix, T=120, gap_open=-11, gap_extend=-1
                                   offsets.data_ptr(), offsets.numel() - 1, m.ctypes.data, int(gap_open),
                                   int(gap_extend), int(T), ctypes.byref(cnt), ctypes.byref(cells)))
     return cnt.value, cells.value
+
+
+# ---------------------------------------------------------------------------
+# learned pair screen
+# ---------------------------------------------------------------------------
+_lib.cm_kmer_features.restype = _i32
+_lib.cm_kmer_features.argtypes = [_P, _P, _P, _i32, _P, _P]
+_lib.cm_screen_num_params.restype = _i64
+_lib.cm_screen_num_params.argtypes = []
+_lib.cm_screen_create.restype = _i32
+_lib.cm_screen_create.argtypes = [_P, _u64, ctypes.POINTER(_P)]
+_lib.cm_screen_destroy.restype = None
+_lib.cm_screen_destroy.argtypes = [_P]
+_lib.cm_screen_set_weights.restype = _i32
+_lib.cm_screen_set_weights.argtypes = [_P, _P]
+_lib.cm_screen_get_weights.restype = _i32
+_lib.cm_screen_get_weights.argtypes = [_P, _P, _P]
+_lib.cm_screen_infer.restype = _i32
+_lib.cm_screen_infer.argtypes = [_P, _P, _P, _i64, _P, _P]
+_lib.cm_screen_grads.restype = _i32
+_lib.cm_screen_grads.argtypes = [_P, _P, _P, _P, _i64, _P, ctypes.POINTER(_f32)]
+_lib.cm_screen_train_step.restype = _i32
+_lib.cm_screen_train_step.argtypes = [_P, _P, _P, _P, _i64, _f32, ctypes.POINTER(_f32)]
+_lib.cm_screen_save.restype = _i32
+_lib.cm_screen_save.argtypes = [_P, ctypes.c_char_p]
+_lib.cm_screen_load.restype = _i32
+_lib.cm_screen_load.argtypes = [_P, ctypes.c_char_p, ctypes.POINTER(_P)]
+
+SCREEN_PARAMS = int(_lib.cm_screen_num_params())
+
+
+def kmer_features(residues, offsets, ctx: Context | None = None, stream=None):
+    """Hashed 3-mer count features, bf16 CUDA tensor [n_seqs][1024]."""
+    import torch
+    ctx = ctx or context()
+    residues = _dev(residues, torch.uint8, "residues")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    n = offsets.numel() - 1
+    feat = torch.empty((max(n, 0), 1024), dtype=torch.bfloat16, device=offsets.device)
+    _check(_lib.cm_kmer_features(ctx.handle, residues.data_ptr() if residues.numel() else None,
+                                 offsets.data_ptr(), n, feat.data_ptr(), _stream_ptr(stream)))
+    return feat
+
+
+class Screen:
+    """The MLP pair screen (weights, Adam state and workspace on the device)."""
+
+    def __init__(self, seed: int = 0, ctx: Context | None = None, _handle=None):
+        self.ctx = ctx or context()
+        if _handle is None:
+            h = _P()
+            _check(_lib.cm_screen_create(self.ctx.handle, int(seed), ctypes.byref(h)))
+            _handle = h
+        self.handle = _handle
+
+    @classmethod
+    def load(cls, path: str, ctx: Context | None = None) -> "Screen":
+        ctx = ctx or context()
+        h = _P()
+        _check(_lib.cm_screen_load(ctx.handle, str(path).encode(), ctypes.byref(h)))
+        return cls(ctx=ctx, _handle=h)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.cm_screen_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def save(self, path: str):
+        _check(_lib.cm_screen_save(self.handle, str(path).encode()))
+
+    def set_weights(self, master):
+        m = np.ascontiguousarray(np.asarray(master, dtype=np.float32).reshape(-1))
+        if m.size != SCREEN_PARAMS:
+            raise ValueError(f"expected {SCREEN_PARAMS} parameters, got {m.size}")
+        _check(_lib.cm_screen_set_weights(self.handle, m.ctypes.data))
+
+    def get_weights(self):
+        """(fp32 master [num_params], bf16 bit patterns of W1|W2|W3 as uint16)."""
+        m = np.zeros(SCREEN_PARAMS, np.float32)
+        b = np.zeros(512 * 2048 + 512 * 512 + 512, np.uint16)
+        _check(_lib.cm_screen_get_weights(self.handle, m.ctypes.data, b.ctypes.data))
+        return m, b
+
+    def infer(self, feat, pairs, stream=None):
+        import torch
+        pairs = _dev(pairs, torch.int32, "pairs")
+        n = pairs.numel() // 2
+        out = torch.empty(n, dtype=torch.float32, device=pairs.device)
+        if n:
+            _check(_lib.cm_screen_infer(self.handle, feat.data_ptr(), pairs.data_ptr(), n, out.data_ptr(),
+                                        _stream_ptr(stream)))
+        return out
+
+    def grads(self, feat, pairs, labels):
+        import torch
+        torch.cuda.current_stream().synchronize()
+        pairs = _dev(pairs, torch.int32, "pairs")
+        labels = _dev(labels, torch.uint8, "labels")
+        g = np.zeros(SCREEN_PARAMS, np.float32)
+        loss = _f32()
+        _check(_lib.cm_screen_grads(self.handle, feat.data_ptr(), pairs.data_ptr(), labels.data_ptr(),
+                                    pairs.numel() // 2, g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, feat, pairs, labels, lr: float = 1e-3) -> float:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        pairs = _dev(pairs, torch.int32, "pairs")
+        labels = _dev(labels, torch.uint8, "labels")
+        loss = _f32()
+        _check(_lib.cm_screen_train_step(self.handle, feat.data_ptr(), pairs.data_ptr(), labels.data_ptr(),
+                                         pairs.numel() // 2, float(lr), ctypes.byref(loss)))
+        return loss.value

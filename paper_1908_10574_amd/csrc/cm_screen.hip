@@ -1,0 +1,325 @@
+// cm_screen.hip -- host side of the learned pair screen (C ABI in include/cm.h).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/cm.h"
+#include "cm_runtime.h"
+#include "screen_internal.h"
+
+using cmrt::DeviceBuf;
+using cmrt::fail;
+using cmrt::hip_fail;
+
+struct cm_screen {
+    cm_context* ctx = nullptr;
+    hipStream_t st = nullptr;
+    DeviceBuf master, mom, vel, grad;      // fp32 [kParams]
+    DeviceBuf w1, w2, w2t, w3;             // bf16 copies
+    // per-batch workspace, sized for cap rows
+    DeviceBuf h1, h1t, h2, z, dz, loss, dh2, dh2t, dh1t, xt;
+    int cap = 0;
+    int step = 0;
+};
+
+namespace {
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+cm_status chk(hipError_t e, const char* what) { return e == hipSuccess ? CM_OK : hip_fail(e, what); }
+
+cm_status alloc_params(cm_screen* s) {
+    const size_t pf = cms::kParams * sizeof(float);
+    if (!s->master.ensure(pf) || !s->mom.ensure(pf) || !s->vel.ensure(pf) || !s->grad.ensure(pf) ||
+        !s->w1.ensure(cms::kW1 * 2) || !s->w2.ensure(cms::kW2 * 2) || !s->w2t.ensure(cms::kW2 * 2) ||
+        !s->w3.ensure(cms::kHidden * 2))
+        return fail(CM_ENOMEM, "screen parameters");
+    return CM_OK;
+}
+
+cm_status ensure_workspace(cm_screen* s, int mb, bool training) {
+    if (mb <= s->cap && (!training || s->xt.ptr)) return CM_OK;
+    const int c = mb > s->cap ? mb : s->cap;
+    const size_t hb = static_cast<size_t>(c) * cms::kHidden * 2;
+    bool ok = s->z.ensure(static_cast<size_t>(c) * 4);
+    if (training)
+        ok = ok && s->h1.ensure(hb) && s->h1t.ensure(hb) && s->h2.ensure(hb) && s->dz.ensure(c * 4) &&
+             s->loss.ensure(c * 4) && s->dh2.ensure(hb) && s->dh2t.ensure(hb) && s->dh1t.ensure(hb) &&
+             s->xt.ensure(static_cast<size_t>(c) * cms::kIn * 2);
+    if (!ok) return fail(CM_ENOMEM, "screen workspace for %d rows", c);
+    s->cap = c;
+    return CM_OK;
+}
+
+cms::FwdArgs fwd_args(const cm_screen* s, const uint16_t* feat, const int32_t* pairs, int n, float* z) {
+    cms::FwdArgs a{};
+    a.feat = feat;
+    a.pairs = pairs;
+    a.n = n;
+    a.w1 = static_cast<const uint16_t*>(s->w1.ptr);
+    a.w2 = static_cast<const uint16_t*>(s->w2.ptr);
+    a.w3 = static_cast<const uint16_t*>(s->w3.ptr);
+    const float* m = static_cast<const float*>(s->master.ptr);
+    a.b1 = m + cms::kOffB1;
+    a.b2 = m + cms::kOffB2;
+    a.b3 = m + cms::kOffB3;
+    a.z = z;
+    return a;
+}
+
+// forward + backward of the mean BCE on one batch; gradients in s->grad
+cm_status forward_backward(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels, int n,
+                           float* loss_out) {
+    const int mb = static_cast<int>(round_up(n, 64));
+    cm_status r = ensure_workspace(s, mb, true);
+    if (r != CM_OK) return r;
+    hipStream_t st = s->st;
+    uint16_t* h1 = static_cast<uint16_t*>(s->h1.ptr);
+    uint16_t* h1t = static_cast<uint16_t*>(s->h1t.ptr);
+    uint16_t* h2 = static_cast<uint16_t*>(s->h2.ptr);
+    uint16_t* dh2 = static_cast<uint16_t*>(s->dh2.ptr);
+    uint16_t* dh2t = static_cast<uint16_t*>(s->dh2t.ptr);
+    uint16_t* dh1t = static_cast<uint16_t*>(s->dh1t.ptr);
+    uint16_t* xt = static_cast<uint16_t*>(s->xt.ptr);
+    float* g = static_cast<float*>(s->grad.ptr);
+    cms::FwdArgs a = fwd_args(s, feat, pairs, n, static_cast<float*>(s->z.ptr));
+    a.h1 = h1;
+    a.h1t = h1t;
+    a.h2 = h2;
+    a.ld_t = mb;
+    if ((r = chk(cms::launch_fwd(a, mb, st), "screen forward")) != CM_OK) return r;
+    if ((r = chk(cms::launch_pair_xt(feat, pairs, n, mb, xt, st), "pair inputs")) != CM_OK) return r;
+    if ((r = chk(cms::launch_backward_tail(static_cast<float*>(s->z.ptr), labels, n, mb, h2,
+                                           static_cast<uint16_t*>(s->w3.ptr), static_cast<float*>(s->dz.ptr),
+                                           static_cast<float*>(s->loss.ptr), dh2, dh2t, g + cms::kOffW3,
+                                           g + cms::kOffB3, st),
+                 "layer-3 backward")) != CM_OK)
+        return r;
+    cms::GemmArgs q{};
+    // dW2[i][j] = sum_m dH2[m][i] H1[m][j]
+    q = {};
+    q.A = dh2t; q.B = h1t; q.M = cms::kHidden; q.N = cms::kHidden; q.K = mb; q.lda = mb; q.ldb = mb;
+    q.Cf = g + cms::kOffW2; q.ldc = cms::kHidden;
+    if ((r = chk(cms::launch_gemm(q, cms::kEpiF32, st), "dW2")) != CM_OK) return r;
+    // dH1^T[j][m] = (sum_i dH2[m][i] W2[i][j]) * [h1[m][j] > 0]
+    q = {};
+    q.A = dh2; q.B = static_cast<const uint16_t*>(s->w2t.ptr); q.M = mb; q.N = cms::kHidden; q.K = cms::kHidden;
+    q.lda = cms::kHidden; q.ldb = cms::kHidden; q.Cb = dh1t; q.ldc = mb; q.mask = h1; q.ldm = cms::kHidden;
+    if ((r = chk(cms::launch_gemm(q, cms::kEpiMaskT, st), "dH1")) != CM_OK) return r;
+    // dW1[i][k] = sum_m dH1[m][i] X[m][k]
+    q = {};
+    q.A = dh1t; q.B = xt; q.M = cms::kHidden; q.N = cms::kIn; q.K = mb; q.lda = mb; q.ldb = mb;
+    q.Cf = g + cms::kOffW1; q.ldc = cms::kIn;
+    if ((r = chk(cms::launch_gemm(q, cms::kEpiF32, st), "dW1")) != CM_OK) return r;
+    if ((r = chk(cms::launch_rowsum(dh2t, cms::kHidden, mb, g + cms::kOffB2, st), "db2")) != CM_OK) return r;
+    if ((r = chk(cms::launch_rowsum(dh1t, cms::kHidden, mb, g + cms::kOffB1, st), "db1")) != CM_OK) return r;
+    if (loss_out) {
+        std::vector<float> lv(n);
+        if ((r = chk(hipMemcpyAsync(lv.data(), s->loss.ptr, n * 4, hipMemcpyDeviceToHost, st), "loss")) != CM_OK)
+            return r;
+        if ((r = chk(hipStreamSynchronize(st), "screen step")) != CM_OK) return r;
+        double t = 0;
+        for (float v : lv) t += v;
+        *loss_out = static_cast<float>(t / n);
+    }
+    return CM_OK;
+}
+
+uint64_t splitmix(uint64_t& x) {
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+cm_status upload_master(cm_screen* s, const float* host) {
+    cm_status r = chk(hipMemcpyAsync(s->master.ptr, host, cms::kParams * 4, hipMemcpyHostToDevice, s->st), "weights");
+    if (r != CM_OK) return r;
+    r = chk(cms::launch_pack(static_cast<const float*>(s->master.ptr), static_cast<uint16_t*>(s->w1.ptr),
+                             static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
+                             static_cast<uint16_t*>(s->w3.ptr), s->st),
+            "pack");
+    if (r != CM_OK) return r;
+    return chk(hipStreamSynchronize(s->st), "upload");
+}
+
+cm_status reset_adam(cm_screen* s) {
+    s->step = 0;
+    cm_status r = chk(hipMemsetAsync(s->mom.ptr, 0, cms::kParams * 4, s->st), "adam state");
+    if (r == CM_OK) r = chk(hipMemsetAsync(s->vel.ptr, 0, cms::kParams * 4, s->st), "adam state");
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+cm_status cm_kmer_features(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                           uint16_t* feat, void* stream) {
+    if (!ctx || !offsets || !feat || n_seqs < 0) return fail(CM_EINVAL, "bad argument");
+    if (n_seqs == 0) return CM_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
+    return chk(cms::launch_kmer(seqs ? seqs : ctx->dummy, offsets, n_seqs, feat, ctx->err_flag,
+                                static_cast<hipStream_t>(stream)),
+               "features");
+}
+
+cm_status cm_screen_create(cm_context* ctx, uint64_t seed, cm_screen** out) {
+    if (!ctx || !out) return fail(CM_EINVAL, "bad argument");
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
+    cm_screen* s = new cm_screen();
+    s->ctx = ctx;
+    cm_status r = chk(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking), "stream");
+    if (r == CM_OK) r = alloc_params(s);
+    if (r != CM_OK) { cm_screen_destroy(s); return r; }
+    // Kaiming-uniform weights (bound sqrt(6 / fan_in)), zero biases
+    std::vector<float> w(cms::kParams, 0.f);
+    uint64_t x = seed;
+    auto fill = [&](int64_t off, int64_t count, int fan_in) {
+        const double bound = std::sqrt(6.0 / fan_in);
+        for (int64_t i = 0; i < count; ++i) {
+            const double u = static_cast<double>(splitmix(x) >> 11) * (1.0 / 9007199254740992.0);
+            w[off + i] = static_cast<float>((2.0 * u - 1.0) * bound);
+        }
+    };
+    fill(cms::kOffW1, cms::kW1, cms::kIn);
+    fill(cms::kOffW2, cms::kW2, cms::kHidden);
+    fill(cms::kOffW3, cms::kHidden, cms::kHidden);
+    r = upload_master(s, w.data());
+    if (r == CM_OK) r = reset_adam(s);
+    if (r == CM_OK) r = chk(hipStreamSynchronize(s->st), "screen init");
+    if (r != CM_OK) { cm_screen_destroy(s); return r; }
+    *out = s;
+    return CM_OK;
+}
+
+void cm_screen_destroy(cm_screen* s) {
+    if (!s) return;
+    if (s->st) { (void)hipStreamSynchronize(s->st); (void)hipStreamDestroy(s->st); }
+    for (DeviceBuf* b : {&s->master, &s->mom, &s->vel, &s->grad, &s->w1, &s->w2, &s->w2t, &s->w3, &s->h1, &s->h1t,
+                         &s->h2, &s->z, &s->dz, &s->loss, &s->dh2, &s->dh2t, &s->dh1t, &s->xt})
+        b->release();
+    delete s;
+}
+
+int64_t cm_screen_num_params(void) { return cms::kParams; }
+
+cm_status cm_screen_set_weights(cm_screen* s, const float* host_fp32_master) {
+    if (!s || !host_fp32_master) return fail(CM_EINVAL, "bad argument");
+    cm_status r = upload_master(s, host_fp32_master);
+    if (r == CM_OK) r = reset_adam(s);
+    if (r == CM_OK) r = chk(hipStreamSynchronize(s->st), "set weights");
+    return r;
+}
+
+cm_status cm_screen_get_weights(const cm_screen* s, float* host_fp32_master, uint16_t* host_bf16) {
+    if (!s) return fail(CM_EINVAL, "bad argument");
+    if (host_fp32_master) {
+        cm_status r = chk(hipMemcpy(host_fp32_master, s->master.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "get");
+        if (r != CM_OK) return r;
+    }
+    if (host_bf16) {
+        // W1, W2, W3 bf16 copies, concatenated
+        cm_status r = chk(hipMemcpy(host_bf16, s->w1.ptr, cms::kW1 * 2, hipMemcpyDeviceToHost), "get");
+        if (r == CM_OK) r = chk(hipMemcpy(host_bf16 + cms::kW1, s->w2.ptr, cms::kW2 * 2, hipMemcpyDeviceToHost), "get");
+        if (r == CM_OK)
+            r = chk(hipMemcpy(host_bf16 + cms::kW1 + cms::kW2, s->w3.ptr, cms::kHidden * 2, hipMemcpyDeviceToHost),
+                    "get");
+        if (r != CM_OK) return r;
+    }
+    return CM_OK;
+}
+
+cm_status cm_screen_infer(const cm_screen* s_, const uint16_t* feat, const int32_t* pairs, int64_t n_pairs,
+                          float* logits, void* stream) {
+    cm_screen* s = const_cast<cm_screen*>(s_);
+    if (!s || !feat || !pairs || !logits || n_pairs < 0) return fail(CM_EINVAL, "bad argument");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t chunk = 1 << 20;
+    for (int64_t first = 0; first < n_pairs; first += chunk) {
+        const int n = static_cast<int>(n_pairs - first < chunk ? n_pairs - first : chunk);
+        const int mb = static_cast<int>(round_up(n, 32));
+        cms::FwdArgs a = fwd_args(s, feat, pairs + 2 * first, n, logits + first);
+        cm_status r = chk(cms::launch_fwd(a, mb, st), "screen inference");
+        if (r != CM_OK) return r;
+    }
+    return CM_OK;
+}
+
+cm_status cm_screen_grads(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                          int64_t n_pairs, float* host_grads, float* loss) {
+    if (!s || !feat || !pairs || !labels || n_pairs <= 0 || n_pairs > (1 << 20)) return fail(CM_EINVAL, "bad argument");
+    cm_status r = forward_backward(s, feat, pairs, labels, static_cast<int>(n_pairs), loss);
+    if (r != CM_OK) return r;
+    if (host_grads) r = chk(hipMemcpy(host_grads, s->grad.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "grads");
+    return r;
+}
+
+cm_status cm_screen_train_step(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                               int64_t n_pairs, float lr, float* loss) {
+    if (!s || !feat || !pairs || !labels || n_pairs <= 0 || n_pairs > (1 << 20) || !(lr > 0.f))
+        return fail(CM_EINVAL, "bad argument");
+    cm_status r = forward_backward(s, feat, pairs, labels, static_cast<int>(n_pairs), loss);
+    if (r != CM_OK) return r;
+    s->step += 1;
+    r = chk(cms::launch_adam(static_cast<float*>(s->master.ptr), static_cast<const float*>(s->grad.ptr),
+                             static_cast<float*>(s->mom.ptr), static_cast<float*>(s->vel.ptr), cms::kParams, lr, 0.9f,
+                             0.999f, 1e-8f, s->step, s->st),
+            "adam");
+    if (r != CM_OK) return r;
+    r = chk(cms::launch_pack(static_cast<const float*>(s->master.ptr), static_cast<uint16_t*>(s->w1.ptr),
+                             static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
+                             static_cast<uint16_t*>(s->w3.ptr), s->st),
+            "pack");
+    if (r != CM_OK) return r;
+    return chk(hipStreamSynchronize(s->st), "train step");
+}
+
+cm_status cm_screen_save(const cm_screen* s, const char* path) {
+    if (!s || !path) return fail(CM_EINVAL, "bad argument");
+    std::vector<float> buf(3 * cms::kParams);
+    cm_status r = chk(hipMemcpy(buf.data(), s->master.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "save");
+    if (r == CM_OK) r = chk(hipMemcpy(buf.data() + cms::kParams, s->mom.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "save");
+    if (r == CM_OK)
+        r = chk(hipMemcpy(buf.data() + 2 * cms::kParams, s->vel.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "save");
+    if (r != CM_OK) return r;
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(CM_EINVAL, "cannot open %s", path);
+    const char magic[8] = {'C', 'M', 'S', 'C', 'R', 'N', '0', '1'};
+    const int64_t hdr[2] = {cms::kParams, s->step};
+    bool ok = fwrite(magic, 1, 8, f) == 8 && fwrite(hdr, 8, 2, f) == 2 &&
+              fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? CM_OK : fail(CM_EINVAL, "write failed: %s", path);
+}
+
+cm_status cm_screen_load(cm_context* ctx, const char* path, cm_screen** out) {
+    if (!ctx || !path || !out) return fail(CM_EINVAL, "bad argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(CM_EINVAL, "cannot open %s", path);
+    char magic[8];
+    int64_t hdr[2];
+    std::vector<float> buf(3 * cms::kParams);
+    const bool ok = fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CMSCRN01", 8) == 0 &&
+                    fread(hdr, 8, 2, f) == 2 && hdr[0] == cms::kParams &&
+                    fread(buf.data(), 4, buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return fail(CM_EINVAL, "not a screen file: %s", path);
+    cm_screen* s = nullptr;
+    cm_status r = cm_screen_create(ctx, 0, &s);
+    if (r != CM_OK) return r;
+    r = upload_master(s, buf.data());
+    if (r == CM_OK)
+        r = chk(hipMemcpy(s->mom.ptr, buf.data() + cms::kParams, cms::kParams * 4, hipMemcpyHostToDevice), "load");
+    if (r == CM_OK)
+        r = chk(hipMemcpy(s->vel.ptr, buf.data() + 2 * cms::kParams, cms::kParams * 4, hipMemcpyHostToDevice), "load");
+    if (r != CM_OK) { cm_screen_destroy(s); return r; }
+    s->step = static_cast<int>(hdr[1]);
+    *out = s;
+    return CM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+"""GPU screen (features, bf16-MFMA MLP forward/backward, Adam) vs the CPU reference.
+
+Weights are drawn on the CPU (oracle.screen.init_params) and loaded into the
+GPU screen, so neither side's inputs come from the other.
+"""
+import numpy as np
+import pytest
+
+import cmgen
+from oracle import screen as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cm():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1908_10574_amd as cm
+    return cm
+
+
+@pytest.fixture(scope="module")
+def data(cm):
+    ds = cmgen.allvsall_small()
+    res = torch.from_numpy(ds.residues).cuda()
+    off = torch.from_numpy(ds.offsets).cuda()
+    feat = cm.kmer_features(res, off)
+    cm.sync()
+    return ds, res, off, feat
+
+
+def feat_bits(feat):
+    return feat.view(torch.int16).cpu().numpy().view(np.uint16)
+
+
+def test_features_bit_exact(cm, data):
+    ds, res, off, feat = data
+    assert np.array_equal(feat_bits(feat), S.features(ds.residues, ds.offsets))
+    long = cmgen.uniform_pool(40, 0, 5000, 9)
+    f2 = cm.kmer_features(torch.from_numpy(long.residues).cuda(), torch.from_numpy(long.offsets).cuda())
+    cm.sync()
+    assert np.array_equal(feat_bits(f2), S.features(long.residues, long.offsets))
+
+
+def test_logits_within_tolerance(cm, data):
+    ds, res, off, feat = data
+    w = S.init_params(11)
+    scr = cm.Screen(0)
+    scr.set_weights(w)
+    m, b = scr.get_weights()
+    assert np.array_equal(m, w)
+    assert np.array_equal(b[:512 * 2048], S.bf16_bits(w[:512 * 2048]))
+    rng = np.random.default_rng(12)
+    pairs = cmgen.random_pairs(rng, ds.n, 777)
+    z = scr.infer(feat, torch.from_numpy(pairs).cuda()).cpu().numpy()
+    zr, _ = S.forward(w, S.pair_input(feat_bits(feat), pairs))
+    err = np.abs(z - zr).max()
+    assert err < 2e-2, err
+    print("max |logit diff|", err, "logit std", zr.std())
+
+
+def _batch(ds, n, seed):
+    from oracle import sw_batch
+    rng = np.random.default_rng(seed)
+    fam_pairs = []
+    for _ in range(n // 2):
+        f = rng.integers(0, 10)
+        idx = np.flatnonzero(ds.family == f)
+        a, b = rng.choice(idx, 2, replace=False)
+        fam_pairs.append((a, b))
+    pairs = np.concatenate([np.array(fam_pairs), cmgen.random_pairs(rng, ds.n, n - n // 2)]).astype(np.int32)
+    y = (sw_batch(ds.residues, ds.offsets, pairs, ds.matrix, with_end=False) >= 120).astype(np.uint8)
+    return pairs, y
+
+
+def test_gradients_match_reference(cm, data):
+    ds, res, off, feat = data
+    w = S.init_params(13)
+    scr = cm.Screen(0)
+    scr.set_weights(w)
+    pairs, y = _batch(ds, 300, 14)
+    g, loss = scr.grads(feat, torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda())
+    z, cache = S.forward(w, S.pair_input(feat_bits(feat), pairs))
+    gr = S.backward(z, y, cache)
+    assert abs(loss - S.bce(z, y)) < 1e-3
+    gp, rp = S.unflatten(g), S.unflatten(gr)
+    for name, _ in S.SHAPES:
+        rel = np.linalg.norm(gp[name] - rp[name]) / max(np.linalg.norm(rp[name]), 1e-30)
+        assert rel < 1e-2, (name, rel)
+
+
+def test_training_reduces_loss_and_adam_matches(cm, data):
+    ds, res, off, feat = data
+    w = S.init_params(15)
+    scr = cm.Screen(0)
+    scr.set_weights(w)
+    pairs, y = _batch(ds, 512, 16)
+    tp, ty = torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda()
+    g, _ = scr.grads(feat, tp, ty)
+    first = scr.train_step(feat, tp, ty, lr=1e-3)
+    m1, _ = scr.get_weights()
+    want, _, _ = S.adam(w, g, np.zeros_like(w), np.zeros_like(w), 1, lr=1e-3)
+    assert np.abs(m1 - want).max() < 1e-6
+    losses = [scr.train_step(feat, tp, ty, lr=1e-3) for _ in range(40)]
+    assert losses[-1] < 0.5 * first, (first, losses[-1])
+
+
+def test_save_load_roundtrip(cm, data, tmp_path):
+    ds, res, off, feat = data
+    scr = cm.Screen(7)
+    pairs = torch.from_numpy(cmgen.random_pairs(np.random.default_rng(1), ds.n, 100)).cuda()
+    z1 = scr.infer(feat, pairs).cpu().numpy()
+    p = tmp_path / "s.bin"
+    scr.save(str(p))
+    s2 = cm.Screen.load(str(p))
+    z2 = s2.infer(feat, pairs).cpu().numpy()
+    assert np.array_equal(z1, z2)
