@@ -65,6 +65,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-throughput", action="store_true")
+    ap.add_argument("--no-screen", action="store_true")
+    ap.add_argument("--screen-pairs", type=int, default=2000000)
+    ap.add_argument("--screen-epochs", type=int, default=5)
+    ap.add_argument("--screen-keep", type=float, default=0.999)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -132,6 +136,41 @@ def main():
         out["clustermerge"].update(truth_pairs=truth, recall=s["n_similar_pairs"] / max(truth, 1),
                                    allvsall_s=tt, allvsall_gcups=tcells / tt / 1e9)
         log(f"all-vs-all truth {truth} in {tt:.1f} s")
+
+    if not args.no_screen:
+        from paper_1908_10574_amd import screen_train
+        t = time.perf_counter()
+        tr = cmgen.screen_training(seed=404, n_pairs=args.screen_pairs)
+        gen_s = time.perf_counter() - t
+        scr, tau, info = screen_train.train_on_dataset(tr, epochs=args.screen_epochs, seed=1,
+                                                       keep_recall=args.screen_keep, log=log)
+        del tr
+        g = cm.clustermerge_run(res, off, M, screen=scr, screen_tau=tau)   # warm
+        sstats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g = cm.clustermerge_run(res, off, M, screen=scr, screen_tau=tau)
+            sstats.append(g["stats"])
+        torch.cuda.synchronize()
+        ss_step = (time.perf_counter() - t0) / args.steps
+        ss = sstats[-1]
+        scr_out = dict(
+            time_s=ss_step, speedup_vs_plain=step_s / ss_step, tau=tau, stages="representative and exchange",
+            n_similar_pairs=ss["n_similar_pairs"], screened_out=ss["screened_out"],
+            aligned_cells=ss["aligned_cells"], aligned_pairs=ss["aligned_pairs"],
+            similar_pairs_vs_plain=ss["n_similar_pairs"] / max(s["n_similar_pairs"], 1),
+            training=dict(workload=f"screen-train: separate 20,000-protein family set (seed 404), "
+                                   f"{args.screen_pairs} pairs (half within-family), labels from the GPU "
+                                   f"Smith-Waterman (score >= 120), {args.screen_epochs} epochs, batch 4096, "
+                                   f"Adam lr 1e-3", gen_s=gen_s, **info))
+        if "truth_pairs" in out["clustermerge"]:
+            truth = out["clustermerge"]["truth_pairs"]
+            scr_out["recall"] = ss["n_similar_pairs"] / max(truth, 1)
+            scr_out["recall_vs_plain"] = scr_out["recall"] / out["clustermerge"]["recall"]
+        out["screened"] = scr_out
+        log(f"screened: {ss_step:.2f} s/step ({step_s / ss_step:.2f}x), similar pairs "
+            f"{ss['n_similar_pairs']} vs {s['n_similar_pairs']}")
+        scr.close()
 
     if not args.no_throughput:
         tp = cmgen.throughput_pool(n_pairs=args.throughput_pairs)

@@ -235,3 +235,42 @@ def recall(found, truth):
     f = {(x, y) for x, y, *_ in found}
     t = {(x, y) for x, y, *_ in truth}
     return len(f & t) / len(t) if t else 1.0
+
+
+# ---------------------------------------------------------------------------
+# screened variant: a pre-filter decides which candidate pairs are aligned
+# ---------------------------------------------------------------------------
+STAGE_REP, STAGE_EXCHANGE, STAGE_FINAL = 1, 2, 4
+
+
+class ScreenedProteinJudge(ProteinJudge):
+    """similar'(x, y) = (stage not screened or keep(x, y)) and score >= T."""
+
+    def __init__(self, residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1):
+        super().__init__(residues, offsets, M, T, mT, mU, go, ge)
+        self.keep = keep
+        self.stages = stages
+
+    def rep_test(self, r1, r2):
+        if (self.stages & STAGE_REP) and not self.keep(r1, r2):
+            return (False, False, False)
+        return super().rep_test(r1, r2)
+
+    def member_similar(self, m, rep):
+        if (self.stages & STAGE_EXCHANGE) and not self.keep(m, rep):
+            return False
+        return super().member_similar(m, rep)
+
+
+def clustermerge_screened(residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1):
+    n = len(offsets) - 1
+    judge = ScreenedProteinJudge(residues, offsets, M, keep, stages, T, mT, mU, go, ge)
+    clusters, stats = bottom_up_merge(n, judge)
+    out = []
+    for x, y in cluster_pairs(clusters):
+        if (stages & STAGE_FINAL) and not keep(x, y):
+            continue
+        s = judge.score(x, y)
+        if s >= T:
+            out.append((x, y, s))
+    return clusters, out, stats

@@ -147,6 +147,7 @@ struct Aligner {
         bool spans = false;
         double cells = 0;
     } slot[2];
+    Pinned sh_pairs, sh_out;   // screen staging (separate from the in-flight slots)
 
     cm_status init() {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(CM_EDEVICE, "stream");
@@ -235,6 +236,29 @@ struct Aligner {
         return CM_OK;
     }
 
+    // Screen logits for np pairs (flat a,b) -> keep[k] = logit >= tau.  Synchronous.
+    cm_status screen(const cm_screen* scr, const uint16_t* feat, float tau, const int32_t* pairs, int64_t np,
+                     std::vector<uint8_t>& keep) {
+        keep.assign(static_cast<size_t>(np), 1);
+        if (np == 0) return CM_OK;
+        cmrt::DeviceBuf& d_pairs = ctx->drv[8];
+        cmrt::DeviceBuf& d_z = ctx->drv[9];
+        if (!d_pairs.ensure(np * 8) || !d_z.ensure(np * 4) || !sh_pairs.ensure(np * 8) || !sh_out.ensure(np * 4))
+            return fail(CM_ENOMEM, "screen staging");
+        std::memcpy(sh_pairs.ptr, pairs, np * 8);
+        hipError_t e = hipMemcpyAsync(d_pairs.ptr, sh_pairs.ptr, np * 8, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "screen upload");
+        cm_status s = cm_screen_infer(scr, feat, static_cast<const int32_t*>(d_pairs.ptr), np,
+                                      static_cast<float*>(d_z.ptr), st);
+        if (s != CM_OK) return s;
+        e = hipMemcpyAsync(sh_out.ptr, d_z.ptr, np * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "screen inference");
+        const float* z = static_cast<const float*>(sh_out.ptr);
+        for (int64_t k = 0; k < np; ++k) keep[k] = z[k] >= tau;
+        return CM_OK;
+    }
+
     cm_status run(const int32_t* pairs, int64_t np, bool spans, std::vector<int32_t>& out) {
         cm_status s = submit(0, pairs, np, spans);
         if (s != CM_OK) return s;
@@ -278,8 +302,9 @@ struct MergeJob {
 
 class Driver {
 public:
-    Driver(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n, const cm_params* p)
-        : ctx_(ctx), n_(n), p_(*p) {
+    Driver(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n, const cm_params* p,
+           const cm_screen* scr)
+        : ctx_(ctx), n_(n), p_(*p), scr_(scr) {
         al_.ctx = ctx;
         al_.seqs = seqs;
         al_.offsets = offsets;
@@ -304,11 +329,33 @@ private:
     cm_status align_requests(std::vector<int32_t>& req);
     cm_status final_stage(cm_result* res);
 
-    bool score_of(int32_t x, int32_t y, int32_t* s) const { return cache_.find(unordered_key(x, y), s); }
+    // Screen decision for an exchange pair: 1 keep, 0 dropped, -1 not yet
+    // screened (always 1 when the exchange stage is not screened)
+    int decision(uint64_t k) const {
+        if (!screened(CM_STAGE_EXCHANGE)) return 1;
+        int32_t d;
+        return decisions_.find(k, &d) ? d : -1;
+    }
+    // Score of a member-vs-representative pair as the replay sees it: -1 for
+    // a pair the screen dropped (never aligned, not similar)
+    bool score_of(int32_t x, int32_t y, int32_t* s) const {
+        const uint64_t k = unordered_key(x, y);
+        const int d = decision(k);
+        if (d < 0) return false;
+        if (d == 0) { *s = -1; return true; }
+        return cache_.find(k, s);
+    }
+    bool screened(uint32_t stage) const { return scr_ && (p_.screen_stages & stage); }
+    // split a request list into screen-kept pairs (returned in place) and
+    // dropped pairs (recorded); no-op when the stage is not screened
+    cm_status apply_screen(uint32_t stage, std::vector<int32_t>& pairs, std::vector<uint8_t>* keep_out);
 
     cm_context* ctx_;
     int32_t n_;
     cm_params p_;
+    const cm_screen* scr_ = nullptr;
+    cmrt::DeviceBuf* feat_ = nullptr;  // store features when screening
+    PairMap decisions_;                // exchange-stage screen decisions
     Aligner al_;
     cm_stats st_{};
     bool log_ = false;
@@ -336,7 +383,8 @@ void Driver::request_exchange(const Cluster& c1, const Cluster& c2, std::vector<
     auto want = [&](int32_t m, int32_t rep) {
         int32_t s;
         const uint64_t k = unordered_key(m, rep);
-        if (cache_.find(k, &s) || pending_.find(k, &s)) return;
+        const int d = decision(k);
+        if (d == 0 || (d == 1 && cache_.find(k, &s)) || pending_.find(k, &s)) return;
         pending_.put(k, 0);
         req.push_back(m);
         req.push_back(rep);
@@ -407,7 +455,9 @@ void Driver::speculate(MergeJob& job, std::vector<int32_t>& req) {
     auto want = [&](int32_t m, int32_t rep) {
         int32_t sc;
         const uint64_t k = unordered_key(m, rep);
-        if (cache_.find(k, &sc)) return sc >= p_.T;
+        const int d = decision(k);
+        if (d == 0) return false;
+        if (d == 1 && cache_.find(k, &sc)) return sc >= p_.T;
         if (!pending_.find(k, &sc)) {
             pending_.put(k, 0);
             req.push_back(m);
@@ -491,7 +541,46 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
     return false;
 }
 
+cm_status Driver::apply_screen(uint32_t stage, std::vector<int32_t>& pairs, std::vector<uint8_t>* keep_out) {
+    if (!screened(stage)) {
+        if (keep_out) keep_out->assign(pairs.size() / 2, 1);
+        return CM_OK;
+    }
+    std::vector<uint8_t> keep;
+    cm_status s = al_.screen(scr_, static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau, pairs.data(),
+                             static_cast<int64_t>(pairs.size() / 2), keep);
+    if (s != CM_OK) return s;
+    size_t w = 0;
+    for (size_t k = 0; k < keep.size(); ++k) {
+        if (stage == CM_STAGE_EXCHANGE)
+            decisions_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), keep[k] ? 1 : 0);
+        if (keep[k]) {
+            pairs[2 * w] = pairs[2 * k];
+            pairs[2 * w + 1] = pairs[2 * k + 1];
+            ++w;
+        } else {
+            ++st_.screened_out;
+        }
+    }
+    pairs.resize(2 * w);
+    if (keep_out) keep_out->swap(keep);
+    return CM_OK;
+}
+
 cm_status Driver::align_requests(std::vector<int32_t>& req) {
+    cm_status s0 = apply_screen(CM_STAGE_EXCHANGE, req, nullptr);
+    if (s0 != CM_OK) return s0;
+    {   // kept pairs whose score is already known need no alignment
+        size_t w = 0;
+        int32_t sc;
+        for (size_t k = 0; k < req.size() / 2; ++k)
+            if (!cache_.find(unordered_key(req[2 * k], req[2 * k + 1]), &sc)) {
+                req[2 * w] = req[2 * k];
+                req[2 * w + 1] = req[2 * k + 1];
+                ++w;
+            }
+        req.resize(2 * w);
+    }
     std::vector<int32_t> out;
     cm_status s = al_.run(req.data(), static_cast<int64_t>(req.size() / 2), false, out);
     if (s != CM_OK) return s;
@@ -522,14 +611,22 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
             }
         }
     }
+    // the screen (when it covers this stage) decides which pairs are aligned
+    std::vector<uint8_t> keep;
+    std::vector<int32_t> kept(pairs);
+    cm_status s = apply_screen(CM_STAGE_REP, kept, &keep);
+    if (s != CM_OK) return s;
     std::vector<int32_t> out;
-    cm_status s = al_.run(pairs.data(), static_cast<int64_t>(total), true, out);
+    const size_t nk = kept.size() / 2;
+    s = al_.run(kept.data(), static_cast<int64_t>(nk), true, out);
     if (s != CM_OK) return s;
     const auto t1 = Clock::now();
-    std::vector<uint8_t> bits(total);
+    std::vector<uint8_t> bits(total, 0);
+    size_t q = 0;
     for (size_t k = 0; k < total; ++k) {
+        if (!keep[k]) continue;                 // dropped by the screen: not similar
         const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
-        const int32_t sc = out[k];
+        const int32_t sc = out[q];
         uint8_t b = 0;
         if (sc >= p_.T) {
             b |= kSim;
@@ -537,14 +634,15 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
             cache_.put(unordered_key(r1, r2), sc);
         }
         if (sc > p_.mT) {
-            const int32_t ea = out[total + k], eb = out[2 * total + k];
-            const int32_t sa = out[3 * total + k], sb = out[4 * total + k];
+            const int32_t ea = out[nk + q], eb = out[2 * nk + q];
+            const int32_t sa = out[3 * nk + q], sb = out[4 * nk + q];
             const int32_t u1 = len_[r1] - (ea - sa + 1);
             const int32_t u2 = len_[r2] - (eb - sb + 1);
             if (u1 < p_.mU) b |= kT21;   // cluster2's rep covers nearly all of rep1
             if (u2 < p_.mU) b |= kT12;
         }
         bits[k] = b;
+        ++q;
     }
     for (MergeJob& job : jobs) simulate(job, bits.data() + job.rep_off);
     const auto t2 = Clock::now();
@@ -602,7 +700,7 @@ cm_status Driver::final_stage(cm_result* res) {
     auto consume = [&](Chunk& c, const std::vector<int32_t>& out) {
         size_t g = 0;
         for (size_t k = 0; k < c.cx.size(); ++k) {
-            const int32_t sc = c.cs[k] >= 0 ? c.cs[k] : out[g++];
+            const int32_t sc = c.cs[k] >= 0 ? c.cs[k] : (c.cs[k] == -1 ? out[g++] : -1);
             if (sc >= p_.T) {
                 ++st_.n_similar_pairs;
                 hash += mixp((static_cast<uint64_t>(c.cx[k]) << 32 | static_cast<uint32_t>(c.cy[k])) ^
@@ -624,6 +722,19 @@ cm_status Driver::final_stage(cm_result* res) {
         // submit the current chunk, then finish the previous one
         Chunk& c = ch[cur];
         auto q0 = Clock::now();
+        if (screened(CM_STAGE_FINAL)) {
+            // every candidate of the chunk is screened, known scores included
+            std::vector<int32_t> all(2 * c.cx.size());
+            for (size_t k = 0; k < c.cx.size(); ++k) { all[2 * k] = c.cx[k]; all[2 * k + 1] = c.cy[k]; }
+            std::vector<uint8_t> keep;
+            cm_status s0 = apply_screen(CM_STAGE_FINAL, all, &keep);
+            if (s0 != CM_OK) return s0;
+            c.gpu.clear();
+            for (size_t k = 0; k < c.cs.size(); ++k) {
+                if (!keep[k]) { c.cs[k] = -2; continue; }            // -2: dropped, not similar
+                if (c.cs[k] == -1) { c.gpu.push_back(c.cx[k]); c.gpu.push_back(c.cy[k]); }
+            }
+        }
         cm_status s = al_.submit(cur, c.gpu.data(), static_cast<int64_t>(c.gpu.size() / 2), false);
         if (s != CM_OK) return s;
         auto q1 = Clock::now();
@@ -716,6 +827,13 @@ cm_status Driver::run(cm_result** out) {
     if (s != CM_OK) return s;
     s = load_lengths();
     if (s != CM_OK) return s;
+    if (scr_ && p_.screen_stages && n_ > 0) {
+        feat_ = &ctx_->drv[10];
+        if (!feat_->ensure(static_cast<size_t>(n_) * 1024 * 2)) return fail(CM_ENOMEM, "store features");
+        s = cm_kmer_features(ctx_, al_.seqs, al_.offsets, n_, static_cast<uint16_t*>(feat_->ptr), al_.st);
+        if (s != CM_OK) return s;
+        if (hipStreamSynchronize(al_.st) != hipSuccess) return fail(CM_EDEVICE, "features");
+    }
     // Algorithm 2: singleton sets 0..n-1, FIFO merge order, grouped by tree level
     cl_.resize(n_);
     sets_.assign(n_, {});
@@ -818,7 +936,6 @@ cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_
                               const cm_params* params, const cm_screen* screen, cm_result** out) {
     if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
     if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
-    if (screen) return cmrt::fail(CM_EUNSUPPORTED, "screen not available in this build");
     *out = nullptr;
     cm_status s = cmrt::check_gaps(params->gap_open, params->gap_extend);
     if (s != CM_OK) return s;
@@ -828,7 +945,7 @@ cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_
     if (params->T < 1 || params->mT < 0 || params->mU < 0 || params->max_result_pairs < 0)
         return cmrt::fail(CM_EINVAL, "T must be >= 1; mT, mU and max_result_pairs >= 0");
     if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");
-    cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params);
+    cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params, screen);
     return drv.run(out);
 }
 

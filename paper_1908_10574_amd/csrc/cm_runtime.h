@@ -49,7 +49,7 @@ struct cm_context {
     cmrt::DeviceBuf bnd;                // boundary rows between strips
     int32_t bnd_stride = 0;
     // buffers of the ClusterMerge driver and the screen (released with the context)
-    cmrt::DeviceBuf drv[8];
+    cmrt::DeviceBuf drv[12];
     cmrt::KernelTimer timer;
     void extra_release() {
         for (auto& b : drv) b.release();

@@ -129,3 +129,49 @@ def test_full_scale_20k_properties(cm):
     print({k: s[k] for k in ("rep_comparisons", "exchange_alignments", "full_merges", "exchanges", "rounds",
                              "waves", "aligned_pairs", "aligned_cells", "n_clusters", "n_similar_pairs",
                              "t_total_s", "t_gpu_s", "t_host_s")})
+
+
+def _oracle_logit_table(ds, w):
+    from oracle import screen as S
+    f = S.features(ds.residues, ds.offsets)
+    a, b = np.triu_indices(ds.n, k=1)
+    pairs = np.stack([a, b], 1)
+    z = np.concatenate([S.forward(w, S.pair_input(f, pairs[k:k + 4000]))[0] for k in range(0, len(pairs), 4000)])
+    tab = np.full((ds.n, ds.n), np.nan)
+    tab[a, b] = z
+    tab[b, a] = z
+    return tab, z
+
+
+def ternary_weights(seed):
+    """Weights in {-1, 0, 1}, zero biases: with features that are multiples of
+    1/8, every input, hidden value and logit is a multiple of 1/64 small enough
+    to be exact in fp32, so both sides compute identical logits."""
+    from oracle import screen as S
+    rng = np.random.default_rng(seed)
+    w = rng.choice(np.array([-1.0, 0.0, 1.0], np.float32), size=S.n_params(), p=[0.2, 0.6, 0.2])
+    p = S.unflatten(w)
+    for b in ("b1", "b2", "b3"):
+        p[b][...] = 0
+    return S.flatten(p).astype(np.float32)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3, 7])
+def test_screened_exact_vs_oracle_replay(cm, stages):
+    """Same weights (drawn on the CPU) on both sides; keep decisions from each side's own MLP."""
+    ds = cmgen.clustermerge_families(n_seqs=160, n_families=20, seed=213, median=100, hi=300)
+    w = ternary_weights(21)
+    tab, z = _oracle_logit_table(ds, w)
+    assert np.array_equal(z * 64, np.round(z * 64))        # exact multiples of 1/64
+    tau = float(np.median(z)) + 1.0 / 128
+    scr = cm.Screen(0)
+    scr.set_weights(w)
+    res, off = dev_store(ds)
+    a, b = np.triu_indices(ds.n, k=1)
+    zg = scr.infer(cm.kmer_features(res, off), torch.from_numpy(np.stack([a, b], 1).astype(np.int32)).cuda())
+    assert np.array_equal(zg.cpu().numpy(), z.astype(np.float32))
+    g = cm.clustermerge_run(res, off, ds.matrix, screen=scr, screen_stages=stages, screen_tau=tau)
+    keep = lambda x, y: tab[x, y] >= tau  # noqa: E731
+    clusters, pairs, st = ocm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, keep, stages)
+    assert_same(g, clusters, pairs, st)
+    assert g["stats"]["screened_out"] > 0

@@ -117,3 +117,27 @@ def test_save_load_roundtrip(cm, data, tmp_path):
     s2 = cm.Screen.load(str(p))
     z2 = s2.infer(feat, pairs).cpu().numpy()
     assert np.array_equal(z1, z2)
+
+
+def test_trained_screen_quality_and_screened_recall(cm):
+    """Train on GPU-labelled pairs of one family set; screen ClusterMerge on another."""
+    from paper_1908_10574_amd import screen_train as st
+    ds = cmgen.screen_training(seed=404, n_seqs=4000, n_families=400, n_pairs=200000)
+    scr, tau, info = st.train_on_dataset(ds, epochs=3, seed=3)
+    print(info)
+    assert info["loss_per_epoch"][-1] < info["loss_per_epoch"][0]
+    assert info["holdout_auc"] > 0.97
+    assert info["holdout_pos_kept"] >= 0.99
+    test = cmgen.clustermerge_families(n_seqs=2000, n_families=200, seed=222)
+    res, off = torch.from_numpy(test.residues).cuda(), torch.from_numpy(test.offsets).cuda()
+    plain = cm.clustermerge_run(res, off, test.matrix)
+    scr_run = cm.clustermerge_run(res, off, test.matrix, screen=scr, screen_tau=tau)
+    ps, ss = plain["stats"], scr_run["stats"]
+    print({k: (ps[k], ss[k]) for k in ("n_similar_pairs", "aligned_pairs", "aligned_cells", "screened_out",
+                                      "t_total_s")})
+    assert ss["screened_out"] > 0
+    assert ss["aligned_cells"] < ps["aligned_cells"]
+    assert ss["n_similar_pairs"] >= 0.99 * ps["n_similar_pairs"]
+    # screened output is still exact: every reported pair is a true similar pair
+    found = {(int(x), int(y)) for x, y in plain["pairs"]}
+    assert all((int(x), int(y)) in found for x, y in scr_run["pairs"][:: max(1, len(scr_run["pairs"]) // 5000)])
