@@ -1,0 +1,42 @@
+"""The C-ABI library loads on the CPU and exports every function include/cm.h declares.
+
+No compute call is made (there may be no GPU here).
+"""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cm.h")
+LIB = os.path.join(ROOT, "paper_1908_10574_amd", "libcm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+\**\s*(cm_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("cm_sw_score_batch", "cm_sw_span_batch", "cm_clustermerge_run", "cm_allvsall_count",
+                     "cm_kmer_features", "cm_screen_infer", "cm_screen_train_step", "cm_context_create"):
+        assert required in names
+    assert len(names) >= 25
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "libcm.so not built (run __graft_entry__.build())"
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings_without_device():
+    lib = ctypes.CDLL(LIB)
+    lib.cm_status_str.restype = ctypes.c_char_p
+    assert lib.cm_status_str(0) == b"ok"
+    assert lib.cm_status_str(-2) == b"input data out of range"
+    lib.cm_screen_num_params.restype = ctypes.c_int64
+    assert lib.cm_screen_num_params() == 1312257
