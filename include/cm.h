@@ -76,7 +76,32 @@ cm_status cm_context_sync(cm_context* ctx);
 #define CM_PASS_SCORE_END 1
 #define CM_PASS_SPAN      2
 cm_status cm_context_set_timing(cm_context* ctx, int on);
+/* When on, cm_clustermerge_run replays each GPU wave as a captured hipGraph
+ * (one per power-of-two capacity; the live pair count is read from device
+ * memory); alignment-kernel timing is then not collected.  Off by default. */
+cm_status cm_context_set_graphs(cm_context* ctx, int on);
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
+
+/* Launch plan of the alignment kernels, per pass: the most query rows a lane
+ * holds (8, 12 or 16; strips are 16 x that many rows) and the persistent
+ * blocks per CU (1 .. occupancy limit).  Results never depend on the plan.
+ * A context starts from (16, occupancy limit) and, when the environment
+ * variable CM_AUTOTUNE_CACHE names a plan file written by cm_plan_save for the
+ * same GPU architecture and HIP runtime, from the plans recorded there (a
+ * missing, foreign or corrupt file is ignored). */
+cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* rmax, int32_t* blocks_per_cu,
+                      int32_t* max_blocks_per_cu);
+cm_status cm_plan_set(cm_context* ctx, int pass, int32_t rmax, int32_t blocks_per_cu);
+cm_status cm_plan_save(const cm_context* ctx, const char* path);
+cm_status cm_plan_load(cm_context* ctx, const char* path);
+/* Autotuner: times every candidate plan of `pass` (CM_PASS_SCORE or
+ * CM_PASS_SCORE_END) on the given pair sample (device pointers as in
+ * cm_sw_score_batch), fails with CM_EDEVICE if two candidates disagree on any
+ * output, and keeps the fastest.  table (host, nullable) receives up to 9 rows
+ * of (rmax, blocks_per_cu, milliseconds); *n_rows their count.  Synchronous. */
+cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                      const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
+                      int32_t gap_extend, int pass, double* table, int32_t* n_rows);
 
 /* Smith-Waterman scores of a batch of pairs (Section 4: f(i, j) is the local
  * alignment score; Section 6.1: the similar-pair test).

@@ -35,8 +35,21 @@ _lib.cm_context_sync.restype = _i32
 _lib.cm_context_sync.argtypes = [_P]
 _lib.cm_context_set_timing.restype = _i32
 _lib.cm_context_set_timing.argtypes = [_P, ctypes.c_int]
+_lib.cm_context_set_graphs.restype = _i32
+_lib.cm_context_set_graphs.argtypes = [_P, ctypes.c_int]
 _lib.cm_context_kernel_time.restype = _i32
 _lib.cm_context_kernel_time.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
+_lib.cm_plan_get.restype = _i32
+_lib.cm_plan_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.cm_plan_set.restype = _i32
+_lib.cm_plan_set.argtypes = [_P, ctypes.c_int, _i32, _i32]
+_lib.cm_plan_save.restype = _i32
+_lib.cm_plan_save.argtypes = [_P, ctypes.c_char_p]
+_lib.cm_plan_load.restype = _i32
+_lib.cm_plan_load.argtypes = [_P, ctypes.c_char_p]
+_lib.cm_autotune.restype = _i32
+_lib.cm_autotune.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)]
 _lib.cm_sw_score_batch.restype = _i32
 _lib.cm_sw_score_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P, _P, _P, _P]
 _lib.cm_sw_span_batch.restype = _i32
@@ -120,8 +133,44 @@ class Context:
     def sync(self):
         _check(_lib.cm_context_sync(self.handle))
 
+    def set_graphs(self, on: bool):
+        """Replay ClusterMerge waves as captured hipGraphs."""
+        _check(_lib.cm_context_set_graphs(self.handle, int(bool(on))))
+
     def set_timing(self, on: bool):
         _check(_lib.cm_context_set_timing(self.handle, int(bool(on))))
+
+    def get_plan(self, pass_: int):
+        """(rmax, blocks_per_cu, max_blocks_per_cu) of a pass (0 score, 1 score+end, 2 span)."""
+        r, b, m = _i32(), _i32(), _i32()
+        _check(_lib.cm_plan_get(self.handle, int(pass_), ctypes.byref(r), ctypes.byref(b), ctypes.byref(m)))
+        return r.value, b.value, m.value
+
+    def set_plan(self, pass_: int, rmax: int, blocks_per_cu: int):
+        _check(_lib.cm_plan_set(self.handle, int(pass_), int(rmax), int(blocks_per_cu)))
+
+    def save_plans(self, path: str):
+        _check(_lib.cm_plan_save(self.handle, str(path).encode()))
+
+    def load_plans(self, path: str):
+        _check(_lib.cm_plan_load(self.handle, str(path).encode()))
+
+    def autotune(self, residues, offsets, pairs, matrix, pass_: int = 0, gap_open: int = -11,
+                 gap_extend: int = -1):
+        """Time every candidate plan on a pair sample; keeps the fastest.  Returns rows
+        (rmax, blocks_per_cu, ms)."""
+        import torch
+        residues = _dev(residues, torch.uint8, "residues")
+        offsets = _dev(offsets, torch.int64, "offsets")
+        pairs = _dev(pairs, torch.int32, "pairs")
+        torch.cuda.current_stream().synchronize()
+        tab = (ctypes.c_double * 27)()
+        n = _i32()
+        m = _matrix_host(matrix)
+        _check(_lib.cm_autotune(self.handle, residues.data_ptr() if residues.numel() else None,
+                                offsets.data_ptr(), offsets.numel() - 1, pairs.data_ptr(), pairs.numel() // 2,
+                                m.ctypes.data, int(gap_open), int(gap_extend), int(pass_), tab, ctypes.byref(n)))
+        return [(int(tab[3 * k]), int(tab[3 * k + 1]), float(tab[3 * k + 2])) for k in range(n.value)]
 
     def kernel_time(self, pass_: int):
         """(launches, seconds) of alignment-kernel launches timed so far for a pass

@@ -87,6 +87,7 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     if (e != hipSuccess) return hip_fail(e, "sort size query");
     if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
 
+    a.rmax = ctx->plan[static_cast<int>(pass)].rmax;
     a.ctr = ctx->counters;
     a.err = ctx->err_flag;
     a.dummy = ctx->dummy;
@@ -102,7 +103,9 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     if (e != hipSuccess) return hip_fail(e, "sort");
     a.keys = static_cast<const uint32_t*>(ctx->keys_alt.ptr);
     a.order = static_cast<const int32_t*>(ctx->vals_alt.ptr);
-    const int grid = ctx->grid[static_cast<int>(pass)];
+    const cm_context::Plan& plan = ctx->plan[static_cast<int>(pass)];
+    a.rmax = plan.rmax;
+    const int grid = ctx->n_cu * plan.blocks_per_cu;
     KernelTimer& kt = ctx->timer;
     int pair = -1;
     if (kt.on) {
@@ -143,6 +146,117 @@ void drain_timers(cm_context* ctx, bool blocking) {
     if (kt.pending.empty()) kt.next = 0;
 }
 
+// Plan cache: text lines "<arch> <runtime> <pass> <rmax> <blocks_per_cu>".
+// Entries for another architecture or runtime, or out of range, are ignored.
+cm_status load_plans(cm_context* ctx, const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(CM_EINVAL, "cannot open %s", path);
+    char arch[64];
+    int rt, pass, rmax, bpc, used = 0;
+    while (fscanf(f, "%63s %d %d %d %d", arch, &rt, &pass, &rmax, &bpc) == 5) {
+        if (std::strcmp(arch, ctx->arch) != 0 || rt != ctx->runtime_version || pass < 0 || pass > 2) continue;
+        int k = -1;
+        for (int q = 0; q < cmk::kNumRMax; ++q)
+            if (cmk::kRMaxChoice[q] == rmax) k = q;
+        if (k < 0 || bpc < 1 || bpc > ctx->occ[pass][k]) continue;
+        ctx->plan[pass].rmax = rmax;
+        ctx->plan[pass].blocks_per_cu = bpc;
+        ++used;
+    }
+    fclose(f);
+    return used ? CM_OK : fail(CM_EINVAL, "no usable plan in %s", path);
+}
+
+cm_status save_plans(const cm_context* ctx, const char* path) {
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(CM_EINVAL, "cannot write %s", path);
+    for (int p = 0; p < 3; ++p)
+        fprintf(f, "%s %d %d %d %d\n", ctx->arch, ctx->runtime_version, p, ctx->plan[p].rmax,
+                ctx->plan[p].blocks_per_cu);
+    return fclose(f) == 0 ? CM_OK : fail(CM_EINVAL, "cannot write %s", path);
+}
+
+// make plan/sort scratch large enough for n pairs (no allocation later)
+cm_status reserve(cm_context* ctx, int64_t n) {
+    const size_t m = static_cast<size_t>(n);
+    if (!ctx->keys.ensure(m * 4) || !ctx->keys_alt.ensure(m * 4) || !ctx->vals.ensure(m * 4) ||
+        !ctx->vals_alt.ensure(m * 4))
+        return fail(CM_ENOMEM, "cannot allocate %zu plan entries", m);
+    size_t tmp = 0;
+    hipError_t e = hipcub::DeviceRadixSort::SortPairs(
+        nullptr, tmp, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<uint32_t*>(ctx->keys_alt.ptr),
+        static_cast<int32_t*>(ctx->vals.ptr), static_cast<int32_t*>(ctx->vals_alt.ptr), static_cast<int>(m), 0, 32,
+        nullptr);
+    if (e != hipSuccess) return hip_fail(e, "sort size query");
+    if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
+    return CM_OK;
+}
+
+cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                      const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                      int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                      hipStream_t stream) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
+    if (n_pairs == 0) return CM_OK;
+    if (!offsets || !pairs || !scores) return fail(CM_EINVAL, "NULL required pointer");
+    if ((end_a == nullptr) != (end_b == nullptr)) return fail(CM_EINVAL, "end_a and end_b must both be set or both NULL");
+    cm_status s = check_gaps(gap_open, gap_extend);
+    if (s != CM_OK) return s;
+    cmk::SwArgs a{};
+    s = check_matrix(matrix, a.mat);
+    if (s != CM_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    a.seqs = seqs ? seqs : ctx->dummy;
+    a.offsets = offsets;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.n_live = n_live;
+    a.n_seqs = n_seqs;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.scores = scores;
+    a.end_a = end_a;
+    a.end_b = end_b;
+    return run_pass(ctx, a, end_a ? cmk::Pass::ScoreEnd : cmk::Pass::Score, stream);
+}
+
+cm_status span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                     const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, const int32_t* scores, const int32_t* end_a,
+                     const int32_t* end_b, int32_t min_score, int32_t* start_a, int32_t* start_b,
+                     hipStream_t stream) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
+    if (n_pairs == 0) return CM_OK;
+    if (!offsets || !pairs || !scores || !end_a || !end_b || !start_a || !start_b)
+        return fail(CM_EINVAL, "NULL required pointer");
+    if (min_score < 0) return fail(CM_EINVAL, "min_score must be >= 0");
+    cm_status s = check_gaps(gap_open, gap_extend);
+    if (s != CM_OK) return s;
+    cmk::SwArgs a{};
+    s = check_matrix(matrix, a.mat);
+    if (s != CM_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    a.seqs = seqs ? seqs : ctx->dummy;
+    a.offsets = offsets;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.n_live = n_live;
+    a.n_seqs = n_seqs;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.min_score = min_score;
+    a.scores = const_cast<int32_t*>(scores);
+    a.end_a = const_cast<int32_t*>(end_a);
+    a.end_b = const_cast<int32_t*>(end_b);
+    a.start_a = start_a;
+    a.start_b = start_b;
+    return run_pass(ctx, a, cmk::Pass::Span, stream);
+}
+
 }  // namespace cmrt
 
 using namespace cmrt;
@@ -179,8 +293,18 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     e = hipGetDeviceProperties(&prop, device_ordinal);
     if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipGetDeviceProperties"); }
     ctx->n_cu = prop.multiProcessorCount;
-    for (int p = 0; p < 3; ++p)
-        ctx->grid[p] = ctx->n_cu * cmk::sw_blocks_per_cu(static_cast<cmk::Pass>(p));
+    std::snprintf(ctx->arch, sizeof(ctx->arch), "%s", prop.gcnArchName);
+    (void)hipRuntimeGetVersion(&ctx->runtime_version);
+    int gmax = 1;
+    for (int p = 0; p < 3; ++p) {
+        for (int k = 0; k < cmk::kNumRMax; ++k) {
+            ctx->occ[p][k] = cmk::sw_blocks_per_cu(static_cast<cmk::Pass>(p), cmk::kRMaxChoice[k]);
+            gmax = ctx->occ[p][k] > gmax ? ctx->occ[p][k] : gmax;
+        }
+        ctx->plan[p].rmax = 16;
+        ctx->plan[p].blocks_per_cu = ctx->occ[p][cmk::kNumRMax - 1];
+    }
+    gmax *= ctx->n_cu;
     void* small = nullptr;
     e = hipMalloc(&small, 4096);
     if (e != hipSuccess) { delete ctx; return hip_fail(e, "context scratch"); }
@@ -190,8 +314,6 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     ctx->err_flag = reinterpret_cast<uint32_t*>(static_cast<char*>(small) + 1024);
     ctx->dummy = reinterpret_cast<const uint8_t*>(static_cast<char*>(small) + 2048);
     // boundary rows: one slot per group of the largest persistent grid
-    int gmax = ctx->grid[0];
-    for (int p = 1; p < 3; ++p) gmax = ctx->grid[p] > gmax ? ctx->grid[p] : gmax;
     ctx->bnd_stride = CM_MAX_LEN + 64;
     const size_t bnd_bytes = static_cast<size_t>(gmax) * cmk::kPairsPerWave * ctx->bnd_stride * sizeof(int2);
     if (!ctx->bnd.ensure(bnd_bytes)) {
@@ -201,6 +323,8 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     }
     e = hipDeviceSynchronize();
     if (e != hipSuccess) { cm_context_destroy(ctx); return hip_fail(e, "context init"); }
+    const char* cache = getenv("CM_AUTOTUNE_CACHE");
+    if (cache && *cache) (void)load_plans(ctx, cache);   // a missing or corrupt cache keeps the defaults
     *out = ctx;
     return CM_OK;
 }
@@ -249,6 +373,12 @@ cm_status cm_context_set_timing(cm_context* ctx, int on) {
     return CM_OK;
 }
 
+cm_status cm_context_set_graphs(cm_context* ctx, int on) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    ctx->graphs = on != 0;
+    return CM_OK;
+}
+
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds) {
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
     drain_timers(ctx, true);
@@ -257,67 +387,56 @@ cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, d
     return CM_OK;
 }
 
+cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* rmax, int32_t* blocks_per_cu, int32_t* max_blocks_per_cu) {
+    if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
+    if (rmax) *rmax = ctx->plan[pass].rmax;
+    if (blocks_per_cu) *blocks_per_cu = ctx->plan[pass].blocks_per_cu;
+    if (max_blocks_per_cu) {
+        int k = 0;
+        for (int q = 0; q < cmk::kNumRMax; ++q)
+            if (cmk::kRMaxChoice[q] == ctx->plan[pass].rmax) k = q;
+        *max_blocks_per_cu = ctx->occ[pass][k];
+    }
+    return CM_OK;
+}
+
+cm_status cm_plan_set(cm_context* ctx, int pass, int32_t rmax, int32_t blocks_per_cu) {
+    if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
+    int k = -1;
+    for (int q = 0; q < cmk::kNumRMax; ++q)
+        if (cmk::kRMaxChoice[q] == rmax) k = q;
+    if (k < 0) return fail(CM_EINVAL, "rmax must be 8, 12 or 16");
+    if (blocks_per_cu < 1 || blocks_per_cu > ctx->occ[pass][k])
+        return fail(CM_EINVAL, "blocks_per_cu must be in [1, %d]", ctx->occ[pass][k]);
+    drain_timers(ctx, true);
+    ctx->plan[pass].rmax = rmax;
+    ctx->plan[pass].blocks_per_cu = blocks_per_cu;
+    return CM_OK;
+}
+
+cm_status cm_plan_save(const cm_context* ctx, const char* path) {
+    if (!ctx || !path) return fail(CM_EINVAL, "bad argument");
+    return save_plans(ctx, path);
+}
+
+cm_status cm_plan_load(cm_context* ctx, const char* path) {
+    if (!ctx || !path) return fail(CM_EINVAL, "bad argument");
+    return load_plans(ctx, path);
+}
+
 cm_status cm_sw_score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
-                            const int32_t* pairs, int64_t n_pairs, const int32_t* matrix,
-                            int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a,
-                            int32_t* end_b, void* stream) {
-    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
-    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
-    if (n_pairs == 0) return CM_OK;
-    if (!offsets || !pairs || !scores) return fail(CM_EINVAL, "NULL required pointer");
-    if ((end_a == nullptr) != (end_b == nullptr)) return fail(CM_EINVAL, "end_a and end_b must both be set or both NULL");
-    cm_status s = check_gaps(gap_open, gap_extend);
-    if (s != CM_OK) return s;
-    cmk::SwArgs a{};
-    s = check_matrix(matrix, a.mat);
-    if (s != CM_OK) return s;
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    a.seqs = seqs ? seqs : ctx->dummy;
-    a.offsets = offsets;
-    a.pairs = pairs;
-    a.n_pairs = n_pairs;
-    a.n_seqs = n_seqs;
-    a.go = gap_open;
-    a.ge = gap_extend;
-    a.scores = scores;
-    a.end_a = end_a;
-    a.end_b = end_b;
-    return run_pass(ctx, a, end_a ? cmk::Pass::ScoreEnd : cmk::Pass::Score, static_cast<hipStream_t>(stream));
+                            const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
+                            int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b, void* stream) {
+    return score_batch(ctx, seqs, offsets, n_seqs, pairs, n_pairs, nullptr, matrix, gap_open, gap_extend, scores,
+                       end_a, end_b, static_cast<hipStream_t>(stream));
 }
 
 cm_status cm_sw_span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                            const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
-                           int32_t gap_extend, const int32_t* scores, const int32_t* end_a,
-                           const int32_t* end_b, int32_t min_score, int32_t* start_a, int32_t* start_b,
-                           void* stream) {
-    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
-    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
-    if (n_pairs == 0) return CM_OK;
-    if (!offsets || !pairs || !scores || !end_a || !end_b || !start_a || !start_b)
-        return fail(CM_EINVAL, "NULL required pointer");
-    if (min_score < 0) return fail(CM_EINVAL, "min_score must be >= 0");
-    cm_status s = check_gaps(gap_open, gap_extend);
-    if (s != CM_OK) return s;
-    cmk::SwArgs a{};
-    s = check_matrix(matrix, a.mat);
-    if (s != CM_OK) return s;
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    a.seqs = seqs ? seqs : ctx->dummy;
-    a.offsets = offsets;
-    a.pairs = pairs;
-    a.n_pairs = n_pairs;
-    a.n_seqs = n_seqs;
-    a.go = gap_open;
-    a.ge = gap_extend;
-    a.min_score = min_score;
-    a.scores = const_cast<int32_t*>(scores);
-    a.end_a = const_cast<int32_t*>(end_a);
-    a.end_b = const_cast<int32_t*>(end_b);
-    a.start_a = start_a;
-    a.start_b = start_b;
-    return run_pass(ctx, a, cmk::Pass::Span, static_cast<hipStream_t>(stream));
+                           int32_t gap_extend, const int32_t* scores, const int32_t* end_a, const int32_t* end_b,
+                           int32_t min_score, int32_t* start_a, int32_t* start_b, void* stream) {
+    return span_batch(ctx, seqs, offsets, n_seqs, pairs, n_pairs, nullptr, matrix, gap_open, gap_extend, scores,
+                      end_a, end_b, min_score, start_a, start_b, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -144,9 +144,20 @@ struct Aligner {
         Pinned h_pairs, h_out, h_err;
         hipEvent_t e0 = nullptr, e1 = nullptr, done = nullptr;
         int64_t np = 0;
+        int64_t stride = 0;     // distance between output planes (np, or the capacity)
         bool spans = false;
         double cells = 0;
     } slot[2];
+    // captured launch sequences, per (slot, capacity, spans); valid while the
+    // buffers they reference stay where they were at capture
+    struct Graph {
+        int k;
+        int64_t cap;
+        bool spans;
+        hipGraphExec_t exec;
+        std::vector<void*> ptrs;
+    };
+    std::vector<Graph> graphs;
     Pinned sh_pairs, sh_out;   // screen staging (separate from the in-flight slots)
 
     cm_status init() {
@@ -158,6 +169,7 @@ struct Aligner {
         return CM_OK;
     }
     ~Aligner() {
+        for (Graph& g : graphs) (void)hipGraphExecDestroy(g.exec);
         for (Slot& sl : slot) {
             if (sl.e0) (void)hipEventDestroy(sl.e0);
             if (sl.e1) (void)hipEventDestroy(sl.e1);
@@ -172,9 +184,15 @@ struct Aligner {
     cm_status submit(int k, const int32_t* pairs, int64_t np, bool spans) {
         Slot& sl = slot[k];
         sl.np = np;
+        sl.stride = np;
         sl.spans = spans;
         sl.cells = 0;
         if (np == 0) return CM_OK;
+        double cells = 0;
+        for (int64_t q = 0; q < np; ++q)
+            cells += static_cast<double>((*len)[pairs[2 * q]]) * (*len)[pairs[2 * q + 1]];
+        sl.cells = cells;
+        if (ctx->graphs) return submit_graph(k, pairs, np, spans);
         const size_t pb = static_cast<size_t>(np) * 8, ob = static_cast<size_t>(np) * 4;
         cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
         cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
@@ -206,10 +224,75 @@ struct Aligner {
         e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "flag download");
         (void)hipEventRecord(sl.done, st);
-        double cells = 0;
-        for (int64_t q = 0; q < np; ++q)
-            cells += static_cast<double>((*len)[pairs[2 * q]]) * (*len)[pairs[2 * q + 1]];
-        sl.cells = cells;
+        return CM_OK;
+    }
+
+    // Same sequence as a replayed hipGraph: fixed capacity (a power of two),
+    // live pair count read from device memory by the plan kernel.
+    cm_status submit_graph(int k, const int32_t* pairs, int64_t np, bool spans) {
+        Slot& sl = slot[k];
+        int64_t cap = 1024;
+        while (cap < np) cap *= 2;
+        sl.stride = cap;
+        const size_t pb = static_cast<size_t>(cap) * 8, ob = static_cast<size_t>(cap) * 4;
+        cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
+        cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
+        if (!d_pairs.ensure(pb) || !d_out.ensure(ob * 5 + 64) || !sl.h_pairs.ensure(pb) || !sl.h_out.ensure(ob * 5) ||
+            !sl.h_err.ensure(16))
+            return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(cap));
+        cm_status s = cmrt::reserve(ctx, cap);
+        if (s != CM_OK) return s;
+        int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
+        int64_t* d_live = reinterpret_cast<int64_t*>(dsc + 5 * cap);
+        int64_t* h_live = reinterpret_cast<int64_t*>(static_cast<char*>(sl.h_err.ptr) + 8);
+        const std::vector<void*> ptrs = {d_pairs.ptr, d_out.ptr, ctx->keys.ptr, ctx->keys_alt.ptr, ctx->vals.ptr,
+                                         ctx->vals_alt.ptr, ctx->sort_tmp.ptr, sl.h_pairs.ptr, sl.h_out.ptr,
+                                         sl.h_err.ptr, ctx->bnd.ptr};
+        Graph* g = nullptr;
+        for (size_t q = 0; q < graphs.size(); ++q) {
+            if (graphs[q].ptrs != ptrs) {        // stale: a referenced buffer moved
+                (void)hipGraphExecDestroy(graphs[q].exec);
+                graphs.erase(graphs.begin() + static_cast<long>(q));
+                --q;
+                continue;
+            }
+            if (graphs[q].k == k && graphs[q].cap == cap && graphs[q].spans == spans) g = &graphs[q];
+        }
+        if (!g) {
+            const bool timed = ctx->timer.on;
+            ctx->timer.on = false;               // no timing events inside a captured sequence
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { ctx->timer.on = timed; return hip_fail(e, "begin capture"); }
+            (void)hipMemcpyAsync(d_live, h_live, 8, hipMemcpyHostToDevice, st);
+            (void)hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
+            s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
+                                  p->matrix, p->gap_open, p->gap_extend, dsc, spans ? dsc + cap : nullptr,
+                                  spans ? dsc + 2 * cap : nullptr, st);
+            if (s == CM_OK && spans)
+                s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
+                                     p->matrix, p->gap_open, p->gap_extend, dsc, dsc + cap, dsc + 2 * cap, p->mT,
+                                     dsc + 3 * cap, dsc + 4 * cap, st);
+            (void)hipMemcpyAsync(sl.h_out.ptr, dsc, ob * (spans ? 5 : 1), hipMemcpyDeviceToHost, st);
+            (void)hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            ctx->timer.on = timed;
+            if (s != CM_OK) { if (graph) (void)hipGraphDestroy(graph); return s; }
+            if (e != hipSuccess) return hip_fail(e, "end capture");
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "instantiate");
+            graphs.push_back(Graph{k, cap, spans, exec, ptrs});
+            g = &graphs.back();
+        }
+        *h_live = np;
+        std::memcpy(sl.h_pairs.ptr, pairs, static_cast<size_t>(np) * 8);
+        (void)hipEventRecord(sl.e0, st);
+        hipError_t e = hipGraphLaunch(g->exec, st);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+        (void)hipEventRecord(sl.e1, st);
+        (void)hipEventRecord(sl.done, st);
         return CM_OK;
     }
 
@@ -226,7 +309,10 @@ struct Aligner {
             cm_status s = cm_context_sync(ctx);   // clears the flag and describes it
             return s != CM_OK ? s : fail(CM_ERANGE, "device flagged bad input");
         }
-        std::memcpy(out.data(), sl.h_out.ptr, out.size() * 4);
+        const int planes = sl.spans ? 5 : 1;
+        for (int q = 0; q < planes; ++q)
+            std::memcpy(out.data() + q * sl.np, static_cast<const int32_t*>(sl.h_out.ptr) + q * sl.stride,
+                        static_cast<size_t>(sl.np) * 4);
         cmrt::drain_timers(ctx, false);
         stats->t_gpu_s += ms * 1e-3;
         stats->waves += 1;

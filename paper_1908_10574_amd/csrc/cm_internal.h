@@ -9,12 +9,14 @@ namespace cmk {
 
 constexpr int kGroup = 16;          // lanes that cooperate on one pair (one DPP row)
 constexpr int kPairsPerWave = 4;    // 64-lane wavefront = 4 groups
-constexpr int kRMax = 16;           // query rows held per lane
-constexpr int kStripRows = kGroup * kRMax;
+constexpr int kRMax = 16;           // most query rows a lane can hold
+constexpr int kNumRMax = 3;         // plan choices for the per-lane row limit
+constexpr int kRMaxChoice[kNumRMax] = {8, 12, 16};
 constexpr int kNRes = 21;           // 20 residues + sentinel
 constexpr int kSent = 20;           // sentinel residue code (padding rows / columns)
 constexpr int kMatStride = 24;      // bytes per row of the int8 matrix in LDS
-constexpr int kProfBytesPerGroup = kNRes * kGroup * 16;   // [c][lane][16 bytes]
+// query-profile bytes per row slot: R rows padded to 4, 8 or 16 bytes
+constexpr int prof_row_bytes(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 16); }
 constexpr uint32_t kSkipKey = 0xffffffffu;
 
 // Error bits raised by kernels (reported by cm_context_sync).
@@ -34,11 +36,13 @@ struct SwArgs {
     const uint8_t* seqs;
     const int64_t* offsets;
     const int32_t* pairs;
-    int64_t n_pairs;
+    int64_t n_pairs;            // rows of the pair buffer
+    const int64_t* n_live;      // nullable: rows at or past *n_live are padding (captured launches)
     int32_t n_seqs;
     int32_t go, ge;
     int32_t min_score;          // span pass: only pairs with score > min_score
     int32_t zero;               // always 0 (see the kernel's clamp)
+    int32_t rmax;               // plan: most query rows per lane (8, 12 or 16)
     const uint32_t* keys;       // sorted plan keys (R, strips, columns)
     const int32_t* order;       // pair index per sorted position
     Counters* ctr;
@@ -59,7 +63,7 @@ enum class Pass : int { Score = 0, ScoreEnd = 1, Span = 2 };
 // Host launchers (sw_kernels.hip).
 hipError_t launch_plan(const SwArgs& a, Pass pass, uint32_t* keys_out, int32_t* vals_out,
                        hipStream_t s);
-hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s);
-int sw_blocks_per_cu(Pass pass);
+hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s);   // uses a.rmax
+int sw_blocks_per_cu(Pass pass, int rmax);
 
 }  // namespace cmk

@@ -40,7 +40,12 @@ struct KernelTimer {
 struct cm_context {
     int device = 0;
     int n_cu = 0;
-    int grid[3] = {0, 0, 0};            // persistent grid per pass (score, score+end, span)
+    // launch plan per pass (score, score+end, span): rows-per-lane limit and
+    // persistent blocks per CU; occ = occupancy limit per (pass, rmax choice)
+    struct Plan { int rmax = 16; int blocks_per_cu = 1; } plan[3];
+    int occ[3][cmk::kNumRMax] = {};
+    char arch[64] = {0};
+    int runtime_version = 0;
     void* small = nullptr;              // counters, error flag, dummy bytes
     cmk::Counters* counters = nullptr;
     uint32_t* err_flag = nullptr;
@@ -51,6 +56,7 @@ struct cm_context {
     // buffers of the ClusterMerge driver and the screen (released with the context)
     cmrt::DeviceBuf drv[12];
     cmrt::KernelTimer timer;
+    bool graphs = false;                // capture per-wave launch sequences in hipGraphs
     void extra_release() {
         for (auto& b : drv) b.release();
     }
@@ -61,4 +67,18 @@ namespace cmrt {
 // (blocking = wait for all of them)
 void drain_timers(cm_context* ctx, bool blocking);
 cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st);
+cm_status load_plans(cm_context* ctx, const char* path);
+cm_status reserve(cm_context* ctx, int64_t n);
+// batch entry points with an optional device-resident live count (rows at or
+// past *n_live are padding); the public C functions pass nullptr
+cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                      const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                      int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                      hipStream_t stream);
+cm_status span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                     const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, const int32_t* scores, const int32_t* end_a,
+                     const int32_t* end_b, int32_t min_score, int32_t* start_a, int32_t* start_b,
+                     hipStream_t stream);
+cm_status save_plans(const cm_context* ctx, const char* path);
 }

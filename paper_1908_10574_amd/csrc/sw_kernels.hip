@@ -97,13 +97,14 @@ __device__ __forceinline__ int wave_max4(int v) {
     return max(max(a, b), max(c, d));
 }
 
-// rows per lane for a query of m rows: fewest strips, then fewest rows per
-// lane, rounded up to an even count (the kernel is instantiated for even R)
-__device__ __forceinline__ void shape_for(int m, int& R, int& strips) {
-    strips = (m + kStripRows - 1) / kStripRows;
+// rows per lane for a query of m rows under a per-lane limit rmax: fewest
+// strips, then fewest rows per lane, rounded up to an even count (the kernel
+// is instantiated for even R)
+__device__ __forceinline__ void shape_for(int m, int rmax, int& R, int& strips) {
+    strips = (m + kGroup * rmax - 1) / (kGroup * rmax);
     R = (m + kGroup * strips - 1) / (kGroup * strips);
     R += R & 1;
-    if (R > kRMax) R = kRMax;
+    if (R > rmax) R = rmax;
 }
 
 // ---------------------------------------------------------------------------
@@ -118,6 +119,11 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
     if (p >= a.n_pairs) return;
     const Pass P = static_cast<Pass>(pass);
     uint32_t key = kSkipKey;
+    if (a.n_live && p >= *a.n_live) {      // padding row of a fixed-capacity launch
+        keys[p] = key;
+        vals[p] = static_cast<int32_t>(p);
+        return;
+    }
     const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
     int m = 0, n = 0;
     bool trivial = true;
@@ -152,7 +158,7 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
         }
     } else {
         int R, strips;
-        shape_for(m, R, strips);
+        shape_for(m, a.rmax, R, strips);
         key = (static_cast<uint32_t>(kRMax - R) << 24) |
               (static_cast<uint32_t>(127 - strips) << 16) |
               static_cast<uint32_t>(65535 - n);
@@ -165,7 +171,7 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
 // ---------------------------------------------------------------------------
 // one wavefront item: four pairs of the same rows-per-lane class
 // ---------------------------------------------------------------------------
-template <int R, Pass P>
+template <int R, Pass P, int RMAXT>
 __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
                                                    const int8_t* __restrict__ s_mat,
                                                    uint8_t* __restrict__ s_prof) {
@@ -201,7 +207,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
     }
     const int S = (m + kRows - 1) / kRows;
     const int s_max = wave_max4(S);
-    uint8_t* prof = s_prof + g * kProfBytesPerGroup;
+    uint8_t* prof = s_prof + g * (kNRes * kGroup * prof_row_bytes(RMAXT));
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
 
     bool bad = false;
@@ -365,6 +371,9 @@ __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
                     const int feedR2 = dpp_shl1_any(feedR);
                     const int cn = dpp_shr1(feedR2, c);
                     pwB = load_prof<W>(prof, cn, gl);
+                    // keep the read ahead of this step's cells: the scheduler
+                    // would otherwise sink it next to its use a step later
+                    __builtin_amdgcn_sched_barrier(0);
                     cells(t, HA, HB, pwA);
                     boundary(t, false);
                     feedR = feedR2;
@@ -381,6 +390,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
                     }
                     const int cn = dpp_shr1(feedR2, c);
                     pwA = load_prof<W>(prof, cn, gl);
+                    __builtin_amdgcn_sched_barrier(0);
                     cells(t + 1, HB, HA, pwB);
                     boundary(t + 1, chunk_end);
                     feedR = feedR2;
@@ -433,10 +443,11 @@ __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
     if (bad) atomicOr(a.err, kErrResidue);
 }
 
-template <Pass P>
+template <Pass P, int RMAXT>
 __global__ __launch_bounds__(64) void k_sw(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
-    __shared__ __attribute__((aligned(16))) uint8_t s_prof[kPairsPerWave * kProfBytesPerGroup];
+    __shared__ __attribute__((aligned(16))) uint8_t
+        s_prof[kPairsPerWave * kNRes * kGroup * prof_row_bytes(RMAXT)];
     for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
     __syncthreads();
     const int n_work = a.ctr->n_work;
@@ -448,15 +459,17 @@ __global__ __launch_bounds__(64) void k_sw(SwArgs a) {
         if (item >= n_items) break;
         const uint32_t key = a.keys[static_cast<int64_t>(item) * kPairsPerWave];
         const int R = kRMax - static_cast<int>(key >> 24);
-        switch (R) {
-            case 2:  run_item<2, P>(a, item, n_work, s_mat, s_prof); break;
-            case 4:  run_item<4, P>(a, item, n_work, s_mat, s_prof); break;
-            case 6:  run_item<6, P>(a, item, n_work, s_mat, s_prof); break;
-            case 8:  run_item<8, P>(a, item, n_work, s_mat, s_prof); break;
-            case 10: run_item<10, P>(a, item, n_work, s_mat, s_prof); break;
-            case 12: run_item<12, P>(a, item, n_work, s_mat, s_prof); break;
-            case 14: run_item<14, P>(a, item, n_work, s_mat, s_prof); break;
-            default: run_item<16, P>(a, item, n_work, s_mat, s_prof); break;
+        if (R <= 2) run_item<2, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R <= 4) run_item<4, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R <= 6) run_item<6, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R <= 8 || RMAXT == 8) run_item<8, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if constexpr (RMAXT >= 12) {
+            if (R <= 10) run_item<10, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+            else if (R <= 12 || RMAXT == 12) run_item<12, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+            else if constexpr (RMAXT >= 16) {
+                if (R <= 14) run_item<14, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+                else run_item<16, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+            }
         }
     }
 }
@@ -474,25 +487,42 @@ hipError_t launch_plan(const SwArgs& a, Pass pass, uint32_t* keys, int32_t* vals
     return hipGetLastError();
 }
 
-hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s) {
-    switch (pass) {
-        case Pass::Score:    hipLaunchKernelGGL(k_sw<Pass::Score>, dim3(grid), dim3(64), 0, s, a); break;
-        case Pass::ScoreEnd: hipLaunchKernelGGL(k_sw<Pass::ScoreEnd>, dim3(grid), dim3(64), 0, s, a); break;
-        case Pass::Span:     hipLaunchKernelGGL(k_sw<Pass::Span>, dim3(grid), dim3(64), 0, s, a); break;
+template <Pass P>
+static hipError_t launch_pass(const SwArgs& a, int grid, hipStream_t s) {
+    switch (a.rmax) {
+        case 8:  hipLaunchKernelGGL((k_sw<P, 8>), dim3(grid), dim3(64), 0, s, a); break;
+        case 12: hipLaunchKernelGGL((k_sw<P, 12>), dim3(grid), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sw<P, 16>), dim3(grid), dim3(64), 0, s, a); break;
     }
     return hipGetLastError();
 }
 
-int sw_blocks_per_cu(Pass pass) {
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
+hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s) {
     switch (pass) {
-        case Pass::Score:    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::Score>, 64, 0); break;
-        case Pass::ScoreEnd: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::ScoreEnd>, 64, 0); break;
-        case Pass::Span:     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<Pass::Span>, 64, 0); break;
+        case Pass::Score:    return launch_pass<Pass::Score>(a, grid, s);
+        case Pass::ScoreEnd: return launch_pass<Pass::ScoreEnd>(a, grid, s);
+        default:             return launch_pass<Pass::Span>(a, grid, s);
     }
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+}
+
+template <Pass P>
+static int occupancy(int rmax) {
+    int nb = 0;
+    hipError_t e;
+    switch (rmax) {
+        case 8:  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 8>, 64, 0); break;
+        case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 12>, 64, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 16>, 64, 0); break;
+    }
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+int sw_blocks_per_cu(Pass pass, int rmax) {
+    switch (pass) {
+        case Pass::Score:    return occupancy<Pass::Score>(rmax);
+        case Pass::ScoreEnd: return occupancy<Pass::ScoreEnd>(rmax);
+        default:             return occupancy<Pass::Span>(rmax);
+    }
 }
 
 }  // namespace cmk

@@ -175,3 +175,32 @@ def test_screened_exact_vs_oracle_replay(cm, stages):
     clusters, pairs, st = ocm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, keep, stages)
     assert_same(g, clusters, pairs, st)
     assert g["stats"]["screened_out"] > 0
+
+
+def test_graph_replay_exact(cm):
+    """Waves replayed as captured hipGraphs give the oracle's result, run after run."""
+    ds = cmgen.clustermerge_families(n_seqs=500, n_families=50, seed=212, median=120, hi=400)
+    ctx = cm.Context(0)
+    ctx.set_graphs(True)
+    res, off = dev_store(ds)
+    clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    for _ in range(3):
+        g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+        assert_same(g, clusters, pairs, st)
+    ctx.close()
+
+
+def test_graph_replay_matches_eager_20k(cm):
+    ds = cmgen.clustermerge_families()
+    res, off = dev_store(ds)
+    eager = cm.clustermerge_run(res, off, ds.matrix)
+    ctx = cm.Context(0)
+    ctx.set_graphs(True)
+    for _ in range(2):
+        g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+        for k in ("pair_set_hash", "n_similar_pairs", "rep_comparisons", "exchange_alignments", "full_merges",
+                  "exchanges", "n_clusters", "aligned_pairs"):
+            assert g["stats"][k] == eager["stats"][k], k
+        assert all(r1 == r2 and np.array_equal(m1, m2) for (r1, m1), (r2, m2) in zip(g["clusters"], eager["clusters"]))
+    print("graph", g["stats"]["t_total_s"], "eager", eager["stats"]["t_total_s"])
+    ctx.close()
