@@ -33,6 +33,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the forward alignment kernel from the committed
+    PMC summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "k_sw_traffic_clustermerge_20k.txt")
+    src = os.path.join(ROOT, "paper_1908_10574_amd", "csrc", "sw_kernels.hip")
+    if not os.path.exists(prof):
+        return None
+    kv = dict(line.split("=", 1) for line in open(prof).read().splitlines() if "=" in line and not line.startswith("#"))
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256", "").strip() != digest:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(ds, n_sample, T=120, mT=166, mU=15):
     """The CPU oracle (scalar C Smith-Waterman + sequential Algorithms 1-2 in
     Python) on the first n_sample proteins of the same store."""
@@ -66,9 +81,13 @@ def main():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-throughput", action="store_true")
     ap.add_argument("--no-screen", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--screen-pairs", type=int, default=2000000)
     ap.add_argument("--screen-epochs", type=int, default=5)
     ap.add_argument("--screen-keep", type=float, default=0.999)
+    ap.add_argument("--screen-min-product", type=int, default=64,
+                    help="representative pairs of clusters whose sizes multiply to at least this bypass the screen")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -88,6 +107,14 @@ def main():
     ctx = cm.context()
     torch.cuda.synchronize()
     log(f"store: {ds.n} proteins, {len(ds.residues)} residues")
+
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for w in range(args.warmup):
         g = cm.clustermerge_run(res, off, M)
@@ -110,7 +137,7 @@ def main():
     k_cells = sum(x["aligned_cells"] for x in stats)
     achieved = OPS_PER_CELL * k_cells / k_sec
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12, unit="TOP/s",
-                    frac=achieved / PEAK_INT32_OPS, traffic=None,
+                    frac=achieved / PEAK_INT32_OPS, traffic=measured_traffic(),
                     kernel="k_sw (forward Smith-Waterman, score / score+end)",
                     launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
                     ops_per_launch=OPS_PER_CELL * k_cells / max(k_launch, 1))
@@ -145,17 +172,19 @@ def main():
         scr, tau, info = screen_train.train_on_dataset(tr, epochs=args.screen_epochs, seed=1,
                                                        keep_recall=args.screen_keep, log=log)
         del tr
-        g = cm.clustermerge_run(res, off, M, screen=scr, screen_tau=tau)   # warm
+        kw = dict(screen=scr, screen_tau=tau, screen_min_product=args.screen_min_product)
+        g = cm.clustermerge_run(res, off, M, **kw)   # warm
         sstats = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            g = cm.clustermerge_run(res, off, M, screen=scr, screen_tau=tau)
+            g = cm.clustermerge_run(res, off, M, **kw)
             sstats.append(g["stats"])
         torch.cuda.synchronize()
         ss_step = (time.perf_counter() - t0) / args.steps
         ss = sstats[-1]
         scr_out = dict(
             time_s=ss_step, speedup_vs_plain=step_s / ss_step, tau=tau, stages="representative and exchange",
+            min_product=args.screen_min_product, screen_s=ss["t_screen_s"], screened_pairs=ss["screened_pairs"],
             n_similar_pairs=ss["n_similar_pairs"], screened_out=ss["screened_out"],
             aligned_cells=ss["aligned_cells"], aligned_pairs=ss["aligned_pairs"],
             similar_pairs_vs_plain=ss["n_similar_pairs"] / max(s["n_similar_pairs"], 1),

@@ -163,6 +163,9 @@ typedef struct {
     float screen_tau;               /* keep a candidate pair iff logit >= screen_tau */
     int64_t max_result_pairs;       /* keep at most this many similar pairs in the result
                                        (counts and the set hash always cover all) */
+    int64_t screen_min_product;     /* when > 0: representative pairs whose clusters' member
+                                       counts (at the start of the merge) multiply to at least
+                                       this are aligned without consulting the screen */
 } cm_params;
 
 #define CM_STAGE_REP       1u       /* representative vs representative */
@@ -187,6 +190,8 @@ typedef struct {
     int64_t sw_launches;            /* forward alignment-kernel launches (timed) */
     double  sw_kernel_s;            /* their summed device time; aligned_cells / sw_kernel_s
                                        is the forward kernel's cell rate */
+    double  t_screen_s;             /* wall time of screen inference calls */
+    int64_t screened_pairs;         /* candidate pairs the screen evaluated */
 } cm_stats;
 
 typedef struct cm_result cm_result;

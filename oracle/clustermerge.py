@@ -149,6 +149,8 @@ def exchange_similar(c1, c2, judge, stats):
 
 def merge(cs1, cs2, judge, stats):
     """Algorithm 1 on two ordered cluster lists; returns the new ordered list."""
+    if hasattr(judge, "begin_merge"):
+        judge.begin_merge(cs1, cs2)
     out = []
     for c1 in cs1:
         for c2 in cs2:
@@ -246,13 +248,22 @@ STAGE_REP, STAGE_EXCHANGE, STAGE_FINAL = 1, 2, 4
 class ScreenedProteinJudge(ProteinJudge):
     """similar'(x, y) = (stage not screened or keep(x, y)) and score >= T."""
 
-    def __init__(self, residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1):
+    def __init__(self, residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1,
+                 min_product=0):
         super().__init__(residues, offsets, M, T, mT, mU, go, ge)
         self.keep = keep
         self.stages = stages
+        self.min_product = min_product
+        self._size = {}
+
+    def begin_merge(self, cs1, cs2):
+        # member counts at the start of the merge decide which representative
+        # pairs bypass the screen
+        self._size = {c.rep: len(c.objs) for c in list(cs1) + list(cs2)}
 
     def rep_test(self, r1, r2):
-        if (self.stages & STAGE_REP) and not self.keep(r1, r2):
+        guarded = self.min_product > 0 and self._size.get(r1, 1) * self._size.get(r2, 1) >= self.min_product
+        if (self.stages & STAGE_REP) and not guarded and not self.keep(r1, r2):
             return (False, False, False)
         return super().rep_test(r1, r2)
 
@@ -262,9 +273,10 @@ class ScreenedProteinJudge(ProteinJudge):
         return super().member_similar(m, rep)
 
 
-def clustermerge_screened(residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1):
+def clustermerge_screened(residues, offsets, M, keep, stages, T=120, mT=166, mU=15, go=-11, ge=-1,
+                          min_product=0):
     n = len(offsets) - 1
-    judge = ScreenedProteinJudge(residues, offsets, M, keep, stages, T, mT, mU, go, ge)
+    judge = ScreenedProteinJudge(residues, offsets, M, keep, stages, T, mT, mU, go, ge, min_product)
     clusters, stats = bottom_up_merge(n, judge)
     out = []
     for x, y in cluster_pairs(clusters):

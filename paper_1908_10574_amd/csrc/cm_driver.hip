@@ -633,9 +633,12 @@ cm_status Driver::apply_screen(uint32_t stage, std::vector<int32_t>& pairs, std:
         return CM_OK;
     }
     std::vector<uint8_t> keep;
+    const auto t0 = Clock::now();
     cm_status s = al_.screen(scr_, static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau, pairs.data(),
                              static_cast<int64_t>(pairs.size() / 2), keep);
     if (s != CM_OK) return s;
+    st_.t_screen_s += secs(t0, Clock::now());
+    st_.screened_pairs += static_cast<int64_t>(pairs.size() / 2);
     size_t w = 0;
     for (size_t k = 0; k < keep.size(); ++k) {
         if (stage == CM_STAGE_EXCHANGE)
@@ -697,11 +700,38 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
             }
         }
     }
-    // the screen (when it covers this stage) decides which pairs are aligned
-    std::vector<uint8_t> keep;
-    std::vector<int32_t> kept(pairs);
-    cm_status s = apply_screen(CM_STAGE_REP, kept, &keep);
-    if (s != CM_OK) return s;
+    // the screen (when it covers this stage) decides which pairs are aligned;
+    // pairs of large clusters (member-count product >= screen_min_product)
+    // are always aligned
+    std::vector<uint8_t> keep(total, 1);
+    std::vector<int32_t> kept;
+    cm_status s = CM_OK;
+    if (screened(CM_STAGE_REP)) {
+        std::vector<int32_t> cand;
+        std::vector<size_t> cand_idx;
+        for (const MergeJob& job : jobs) {
+            size_t k = job.rep_off;
+            for (int32_t a : sets_[job.set1])
+                for (int32_t b : sets_[job.set2]) {
+                    const int64_t prod = static_cast<int64_t>(cl_[a].objs.size()) * cl_[b].objs.size();
+                    if (p_.screen_min_product <= 0 || prod < p_.screen_min_product) {
+                        cand.push_back(pairs[2 * k]);
+                        cand.push_back(pairs[2 * k + 1]);
+                        cand_idx.push_back(k);
+                    }
+                    ++k;
+                }
+        }
+        std::vector<uint8_t> ck;
+        s = apply_screen(CM_STAGE_REP, cand, &ck);
+        if (s != CM_OK) return s;
+        for (size_t q = 0; q < cand_idx.size(); ++q) keep[cand_idx[q]] = ck[q];
+        kept.reserve(pairs.size());
+        for (size_t k = 0; k < total; ++k)
+            if (keep[k]) { kept.push_back(pairs[2 * k]); kept.push_back(pairs[2 * k + 1]); }
+    } else {
+        kept = pairs;
+    }
     std::vector<int32_t> out;
     const size_t nk = kept.size() / 2;
     s = al_.run(kept.data(), static_cast<int64_t>(nk), true, out);

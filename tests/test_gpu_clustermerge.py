@@ -156,8 +156,8 @@ def ternary_weights(seed):
     return S.flatten(p).astype(np.float32)
 
 
-@pytest.mark.parametrize("stages", [1, 2, 3, 7])
-def test_screened_exact_vs_oracle_replay(cm, stages):
+@pytest.mark.parametrize("stages,min_product", [(1, 0), (2, 0), (3, 0), (7, 0), (3, 4), (1, 2)])
+def test_screened_exact_vs_oracle_replay(cm, stages, min_product):
     """Same weights (drawn on the CPU) on both sides; keep decisions from each side's own MLP."""
     ds = cmgen.clustermerge_families(n_seqs=160, n_families=20, seed=213, median=100, hi=300)
     w = ternary_weights(21)
@@ -170,9 +170,11 @@ def test_screened_exact_vs_oracle_replay(cm, stages):
     a, b = np.triu_indices(ds.n, k=1)
     zg = scr.infer(cm.kmer_features(res, off), torch.from_numpy(np.stack([a, b], 1).astype(np.int32)).cuda())
     assert np.array_equal(zg.cpu().numpy(), z.astype(np.float32))
-    g = cm.clustermerge_run(res, off, ds.matrix, screen=scr, screen_stages=stages, screen_tau=tau)
+    g = cm.clustermerge_run(res, off, ds.matrix, screen=scr, screen_stages=stages, screen_tau=tau,
+                            screen_min_product=min_product)
     keep = lambda x, y: tab[x, y] >= tau  # noqa: E731
-    clusters, pairs, st = ocm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, keep, stages)
+    clusters, pairs, st = ocm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, keep, stages,
+                                                    min_product=min_product)
     assert_same(g, clusters, pairs, st)
     assert g["stats"]["screened_out"] > 0
 

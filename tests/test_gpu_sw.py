@@ -198,3 +198,23 @@ def test_error_paths(cm):
     out = cm.sw_score_batch(res, off, pr, ds.matrix)
     cm.sync()
     assert out.cpu().numpy()[0] == sw_batch(ds.residues, ds.offsets, np.array([[0, 1]], np.int32), ds.matrix, with_end=False)[0]
+
+
+def test_throughput_full_size_sampled(cm):
+    """The full 1,000,000-pair batch as timed by the benchmark: a seeded sample of
+    outputs checked one by one against the oracle, and run-to-run identity."""
+    ds = cmgen.throughput_pool()
+    res, off, pr = to_dev(ds, ds.pairs)
+    a = cm.sw_score_batch(res, off, pr, ds.matrix)
+    b = cm.sw_score_batch(res, off, pr, ds.matrix)
+    sc, ea, eb = cm.sw_score_batch(res, off, pr, ds.matrix, return_end=True)
+    cm.sync()
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.array_equal(a, b) and np.array_equal(a, sc.cpu().numpy())
+    rng = np.random.default_rng(7)
+    L = ds.lengths()
+    cost = L[ds.pairs[:, 0]].astype(np.float64) * L[ds.pairs[:, 1]]
+    pick = np.concatenate([rng.choice(len(a), 300, replace=False), np.argsort(cost)[-20:], np.argsort(cost)[:20]])
+    osc, oea, oeb = sw_batch(ds.residues, ds.offsets, ds.pairs[pick], ds.matrix)
+    assert np.array_equal(a[pick], osc)
+    assert np.array_equal(ea.cpu().numpy()[pick], oea) and np.array_equal(eb.cpu().numpy()[pick], oeb)

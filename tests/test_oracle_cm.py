@@ -108,3 +108,23 @@ def test_precision_and_recall_small_families():
         assert c.rep in c.objs and len(set(c.objs)) == len(c.objs)
         members.update(c.objs)
     assert members == set(range(ds.n))
+
+
+def test_screened_replay_special_cases():
+    """A screen that keeps everything, or a size guard every pair passes, is plain
+    ClusterMerge; a screen that drops every representative pair leaves singletons."""
+    ds = cmgen.allvsall_small()
+    ref_c, ref_p, ref_s = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+
+    def same(c, p, s):
+        assert [(x.rep, x.objs) for x in c] == [(x.rep, x.objs) for x in ref_c]
+        assert p == ref_p and s == ref_s
+
+    same(*cm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, lambda x, y: True, 7))
+    never = lambda x, y: False  # noqa: E731
+    same(*cm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, never, cm.STAGE_REP, min_product=1))
+    for mp in (0, 2):   # every merge starts from singletons, so a guard of 2 never fires
+        c, p, s = cm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, never, cm.STAGE_REP,
+                                           min_product=mp)
+        assert len(c) == ds.n and p == [] and s.full_merges == 0 and s.exchanges == 0
+        assert s.rep_comparisons == ds.n * (ds.n - 1) // 2
