@@ -9,11 +9,13 @@ sequence store already resident in HBM.  Every alignment is Smith-Waterman
 (Gotoh, gap open -11, extend -1, seeded 20x20 matrix), int32, bit-exact.
 
 Printed (rank 0, one JSON line): whole-step throughput in GCUPS (aligned
-cells / wall time of the step), the forward alignment kernel's achieved
-int32 op rate against the VALU roofline (HIP events around every launch in
-the timed region), ClusterMerge time and pair recall (found / all-vs-all
-truth count), a throughput leg on 1,000,000 random pairs of a 200,000-protein
-pool, and the CPU oracle's rate on a bounded sample of the same workload.
+cells / wall time of the step), the score kernel's achieved op rate against
+its VALU roofline (HIP events around every launch in the timed region; the
+packed 16-bit kernel against the packed 16-bit peak, and the same cell rate
+against the int32 formulation's peak), ClusterMerge time and pair recall
+(found / all-vs-all truth count), a throughput leg on 1,000,000 random pairs
+of a 200,000-protein pool, and the CPU oracle's rate on a bounded sample of
+the same workload.
 """
 import argparse
 import json
@@ -25,8 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SW GCUPS (bit-exact int32); ClusterMerge time + pair recall, learned vs plain"
-OPS_PER_CELL = 8                       # add, max3, max, add, add, max3, add, max3
+OPS_PER_CELL = 8                       # int32: add, max3, max, add, add, max3, add, max3
 PEAK_INT32_OPS = 256 * 64 * 2.4e9      # CUs x lanes/clk x clock (MI355X)
+# packed 16-bit kernel, per cell: saturating add, max, max, saturating subtract
+# (open), subtract + max (E), subtract + max (F), max (best)
+PK_OPS_PER_CELL = 9
+PEAK_PK16_OPS = 256 * 64 * 2 * 2.4e9   # CUs x lanes/clk x 16-bit halves x clock
 
 
 def log(msg):
@@ -135,12 +141,18 @@ def main():
     k_launch = sum(x["sw_launches"] for x in stats)
     k_sec = sum(x["sw_kernel_s"] for x in stats)
     k_cells = sum(x["aligned_cells"] for x in stats)
-    achieved = OPS_PER_CELL * k_cells / k_sec
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12, unit="TOP/s",
-                    frac=achieved / PEAK_INT32_OPS, traffic=measured_traffic(),
-                    kernel="k_sw (forward Smith-Waterman, score / score+end)",
-                    launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
-                    ops_per_launch=OPS_PER_CELL * k_cells / max(k_launch, 1))
+    packed = ctx.get_plan(0)[0] == 1
+    opc, peak = (PK_OPS_PER_CELL, PEAK_PK16_OPS) if packed else (OPS_PER_CELL, PEAK_INT32_OPS)
+    achieved = opc * k_cells / k_sec
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
+                    unit="TOP/s (16-bit packed)" if packed else "TOP/s (int32)",
+                    frac=achieved / peak, traffic=measured_traffic(),
+                    kernel=("k_sw_pk (packed 16-bit Smith-Waterman score kernel; saturated pairs re-run in int32)"
+                            if packed else "k_sw (int32 Smith-Waterman score kernel)"),
+                    ops_per_cell=opc, launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
+                    ops_per_launch=opc * k_cells / max(k_launch, 1),
+                    cell_rate_gcups=k_cells / k_sec / 1e9,
+                    int32_formulation_frac=OPS_PER_CELL * k_cells / k_sec / PEAK_INT32_OPS)
 
     out = dict(metric=METRIC, value=value, unit="GCUPS", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=1e3 * step_s, higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -154,7 +166,8 @@ def main():
         time_s=step_s, aligned_cells=cells, aligned_pairs=s["aligned_pairs"], rep_comparisons=s["rep_comparisons"],
         exchange_alignments=s["exchange_alignments"], full_merges=s["full_merges"], exchanges=s["exchanges"],
         n_clusters=s["n_clusters"], n_similar_pairs=s["n_similar_pairs"], waves=s["waves"],
-        gpu_s=s["t_gpu_s"], host_s=s["t_host_s"], merge_s=s["t_merge_s"], final_s=s["t_final_s"])
+        gpu_s=s["t_gpu_s"], host_s=s["t_host_s"], merge_s=s["t_merge_s"], final_s=s["t_final_s"],
+        score_kernel_s=s["sw_kernel_s"], end_kernel_s=s["end_kernel_s"], end_pairs=s["end_pairs"])
 
     if not args.no_recall:
         t = time.perf_counter()
@@ -226,7 +239,8 @@ def main():
         out["sw_throughput"] = dict(
             workload=f"throughput-{args.throughput_pairs}: random pairs of a 200,000-protein pool, 80% "
                      "lognormal(300, 0.6) / 20% U[1000,5000]", cells=tcells, batch_s=bt, gcups=tcells / bt / 1e9,
-            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
+            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=opc * tcells / ks / peak,
+            int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
         log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
         del r2, o2, p2
 

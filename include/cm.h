@@ -82,23 +82,29 @@ cm_status cm_context_set_timing(cm_context* ctx, int on);
 cm_status cm_context_set_graphs(cm_context* ctx, int on);
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
 
-/* Launch plan of the alignment kernels, per pass: the most query rows a lane
- * holds (8, 12 or 16; strips are 16 x that many rows) and the persistent
- * blocks per CU (1 .. occupancy limit).  Results never depend on the plan.
- * A context starts from (16, occupancy limit) and, when the environment
- * variable CM_AUTOTUNE_CACHE names a plan file written by cm_plan_save for the
- * same GPU architecture and HIP runtime, from the plans recorded there (a
- * missing, foreign or corrupt file is ignored). */
-cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* rmax, int32_t* blocks_per_cu,
+/* Launch plan of the alignment kernels, per pass: the kernel (packed = 1: the
+ * packed 16-bit kernel, two pairs per register, score pass only, with pairs
+ * whose score reaches 32767 recomputed by the int32 kernel; packed = 0: the
+ * int32 kernel), the most query rows a lane holds (int32: 8, 12 or 16; packed:
+ * 4 or 8; strips are 16 x that many rows) and the persistent blocks per CU
+ * (1 .. occupancy limit).  Results never depend on the plan.  A context starts
+ * from (packed, 8, occupancy limit) for the score pass and (int32, 16,
+ * occupancy limit) for the others and, when the environment variable
+ * CM_AUTOTUNE_CACHE names a plan file written by cm_plan_save for the same GPU
+ * architecture and HIP runtime, from the plans recorded there (a missing,
+ * foreign or corrupt file is ignored).  cm_plan_set fails with CM_EINVAL on a
+ * plan that is not valid for the pass. */
+cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t* rmax, int32_t* blocks_per_cu,
                       int32_t* max_blocks_per_cu);
-cm_status cm_plan_set(cm_context* ctx, int pass, int32_t rmax, int32_t blocks_per_cu);
+cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, int32_t blocks_per_cu);
 cm_status cm_plan_save(const cm_context* ctx, const char* path);
 cm_status cm_plan_load(cm_context* ctx, const char* path);
 /* Autotuner: times every candidate plan of `pass` (CM_PASS_SCORE or
  * CM_PASS_SCORE_END) on the given pair sample (device pointers as in
  * cm_sw_score_batch), fails with CM_EDEVICE if two candidates disagree on any
- * output, and keeps the fastest.  table (host, nullable) receives up to 9 rows
- * of (rmax, blocks_per_cu, milliseconds); *n_rows their count.  Synchronous. */
+ * output, and keeps the fastest.  table (host, nullable) receives up to 16 rows
+ * of (packed, rmax, blocks_per_cu, milliseconds); *n_rows their count.
+ * Synchronous. */
 cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                       const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
                       int32_t gap_extend, int pass, double* table, int32_t* n_rows);
@@ -187,9 +193,12 @@ typedef struct {
     int64_t n_similar_pairs;        /* pairs reported (score >= T) */
     uint64_t pair_set_hash;         /* order-independent hash of the reported (x, y, score) */
     double  t_total_s, t_merge_s, t_final_s, t_gpu_s, t_host_s;
-    int64_t sw_launches;            /* forward alignment-kernel launches (timed) */
+    int64_t sw_launches;            /* score-kernel launches (timed; every aligned pair) */
     double  sw_kernel_s;            /* their summed device time; aligned_cells / sw_kernel_s
-                                       is the forward kernel's cell rate */
+                                       is the score kernel's cell rate */
+    double  end_kernel_s;           /* device time of the end-cell and start-cell kernels, which
+                                       realign the representative pairs scoring above mT */
+    int64_t end_pairs;              /* pairs realigned for end and start cells */
     double  t_screen_s;             /* wall time of screen inference calls */
     int64_t screened_pairs;         /* candidate pairs the screen evaluated */
 } cm_stats;

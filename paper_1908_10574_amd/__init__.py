@@ -40,9 +40,10 @@ _lib.cm_context_set_graphs.argtypes = [_P, ctypes.c_int]
 _lib.cm_context_kernel_time.restype = _i32
 _lib.cm_context_kernel_time.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
 _lib.cm_plan_get.restype = _i32
-_lib.cm_plan_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.cm_plan_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i32)]
 _lib.cm_plan_set.restype = _i32
-_lib.cm_plan_set.argtypes = [_P, ctypes.c_int, _i32, _i32]
+_lib.cm_plan_set.argtypes = [_P, ctypes.c_int, _i32, _i32, _i32]
 _lib.cm_plan_save.restype = _i32
 _lib.cm_plan_save.argtypes = [_P, ctypes.c_char_p]
 _lib.cm_plan_load.restype = _i32
@@ -70,6 +71,7 @@ class CMStats(ctypes.Structure):
                 ("n_similar_pairs", _i64), ("pair_set_hash", _u64), ("t_total_s", ctypes.c_double),
                 ("t_merge_s", ctypes.c_double), ("t_final_s", ctypes.c_double), ("t_gpu_s", ctypes.c_double),
                 ("t_host_s", ctypes.c_double), ("sw_launches", _i64), ("sw_kernel_s", ctypes.c_double),
+                ("end_kernel_s", ctypes.c_double), ("end_pairs", _i64),
                 ("t_screen_s", ctypes.c_double), ("screened_pairs", _i64)]
 
 
@@ -142,13 +144,14 @@ class Context:
         _check(_lib.cm_context_set_timing(self.handle, int(bool(on))))
 
     def get_plan(self, pass_: int):
-        """(rmax, blocks_per_cu, max_blocks_per_cu) of a pass (0 score, 1 score+end, 2 span)."""
-        r, b, m = _i32(), _i32(), _i32()
-        _check(_lib.cm_plan_get(self.handle, int(pass_), ctypes.byref(r), ctypes.byref(b), ctypes.byref(m)))
-        return r.value, b.value, m.value
+        """(packed, rmax, blocks_per_cu, max_blocks_per_cu) of a pass (0 score, 1 score+end, 2 span)."""
+        k, r, b, m = _i32(), _i32(), _i32(), _i32()
+        _check(_lib.cm_plan_get(self.handle, int(pass_), ctypes.byref(k), ctypes.byref(r), ctypes.byref(b),
+                                ctypes.byref(m)))
+        return k.value, r.value, b.value, m.value
 
-    def set_plan(self, pass_: int, rmax: int, blocks_per_cu: int):
-        _check(_lib.cm_plan_set(self.handle, int(pass_), int(rmax), int(blocks_per_cu)))
+    def set_plan(self, pass_: int, packed: int, rmax: int, blocks_per_cu: int):
+        _check(_lib.cm_plan_set(self.handle, int(pass_), int(packed), int(rmax), int(blocks_per_cu)))
 
     def save_plans(self, path: str):
         _check(_lib.cm_plan_save(self.handle, str(path).encode()))
@@ -159,19 +162,20 @@ class Context:
     def autotune(self, residues, offsets, pairs, matrix, pass_: int = 0, gap_open: int = -11,
                  gap_extend: int = -1):
         """Time every candidate plan on a pair sample; keeps the fastest.  Returns rows
-        (rmax, blocks_per_cu, ms)."""
+        (packed, rmax, blocks_per_cu, ms)."""
         import torch
         residues = _dev(residues, torch.uint8, "residues")
         offsets = _dev(offsets, torch.int64, "offsets")
         pairs = _dev(pairs, torch.int32, "pairs")
         torch.cuda.current_stream().synchronize()
-        tab = (ctypes.c_double * 27)()
+        tab = (ctypes.c_double * 64)()
         n = _i32()
         m = _matrix_host(matrix)
         _check(_lib.cm_autotune(self.handle, residues.data_ptr() if residues.numel() else None,
                                 offsets.data_ptr(), offsets.numel() - 1, pairs.data_ptr(), pairs.numel() // 2,
                                 m.ctypes.data, int(gap_open), int(gap_extend), int(pass_), tab, ctypes.byref(n)))
-        return [(int(tab[3 * k]), int(tab[3 * k + 1]), float(tab[3 * k + 2])) for k in range(n.value)]
+        return [(int(tab[4 * k]), int(tab[4 * k + 1]), int(tab[4 * k + 2]), float(tab[4 * k + 3]))
+                for k in range(n.value)]
 
     def kernel_time(self, pass_: int):
         """(launches, seconds) of alignment-kernel launches timed so far for a pass

@@ -87,7 +87,18 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     if (e != hipSuccess) return hip_fail(e, "sort size query");
     if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
 
-    a.rmax = ctx->plan[static_cast<int>(pass)].rmax;
+    const cm_context::Plan& plan = ctx->plan[static_cast<int>(pass)];
+    const bool packed = pass == cmk::Pass::Score && plan.packed;
+    if (packed) {
+        if (!ctx->over.ensure(n * 4)) return fail(CM_ENOMEM, "cannot allocate %zu saturation slots", n);
+        a.packed = 1;
+        a.over = static_cast<int32_t*>(ctx->over.ptr);
+        const uint32_t go = static_cast<uint32_t>(-static_cast<int64_t>(a.go) < 65535 ? -a.go : 65535);
+        const uint32_t ge = static_cast<uint32_t>(-static_cast<int64_t>(a.ge) < 65535 ? -a.ge : 65535);
+        a.go_pk = go * 0x10001u;
+        a.ge_pk = ge * 0x10001u;
+    }
+    a.rmax = plan.rmax;
     a.ctr = ctx->counters;
     a.err = ctx->err_flag;
     a.dummy = ctx->dummy;
@@ -103,8 +114,6 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     if (e != hipSuccess) return hip_fail(e, "sort");
     a.keys = static_cast<const uint32_t*>(ctx->keys_alt.ptr);
     a.order = static_cast<const int32_t*>(ctx->vals_alt.ptr);
-    const cm_context::Plan& plan = ctx->plan[static_cast<int>(pass)];
-    a.rmax = plan.rmax;
     const int grid = ctx->n_cu * plan.blocks_per_cu;
     KernelTimer& kt = ctx->timer;
     int pair = -1;
@@ -119,7 +128,7 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
         pair = static_cast<int>(kt.next++);
         (void)hipEventRecord(kt.pool[2 * pair], st);
     }
-    e = cmk::launch_sw(a, pass, grid, st);
+    e = packed ? cmk::launch_sw_pk(a, grid, ctx->n_cu * ctx->occ_over, st) : cmk::launch_sw(a, pass, grid, st);
     if (e != hipSuccess) return hip_fail(e, "alignment launch");
     if (pair >= 0) {
         (void)hipEventRecord(kt.pool[2 * pair + 1], st);
@@ -146,19 +155,31 @@ void drain_timers(cm_context* ctx, bool blocking) {
     if (kt.pending.empty()) kt.next = 0;
 }
 
-// Plan cache: text lines "<arch> <runtime> <pass> <rmax> <blocks_per_cu>".
+int plan_limit(const cm_context* ctx, int pass, int packed, int rmax) {
+    if (pass < 0 || pass > 2) return 0;
+    if (packed) {
+        if (pass != CM_PASS_SCORE) return 0;
+        for (int q = 0; q < cmk::kNumRMaxPk; ++q)
+            if (cmk::kRMaxChoicePk[q] == rmax) return ctx->occ_pk[q];
+        return 0;
+    }
+    for (int q = 0; q < cmk::kNumRMax; ++q)
+        if (cmk::kRMaxChoice[q] == rmax) return ctx->occ[pass][q];
+    return 0;
+}
+
+// Plan cache: text lines "<arch> <runtime> <pass> <packed> <rmax> <blocks_per_cu>".
 // Entries for another architecture or runtime, or out of range, are ignored.
 cm_status load_plans(cm_context* ctx, const char* path) {
     FILE* f = fopen(path, "r");
     if (!f) return fail(CM_EINVAL, "cannot open %s", path);
     char arch[64];
-    int rt, pass, rmax, bpc, used = 0;
-    while (fscanf(f, "%63s %d %d %d %d", arch, &rt, &pass, &rmax, &bpc) == 5) {
-        if (std::strcmp(arch, ctx->arch) != 0 || rt != ctx->runtime_version || pass < 0 || pass > 2) continue;
-        int k = -1;
-        for (int q = 0; q < cmk::kNumRMax; ++q)
-            if (cmk::kRMaxChoice[q] == rmax) k = q;
-        if (k < 0 || bpc < 1 || bpc > ctx->occ[pass][k]) continue;
+    int rt, pass, packed, rmax, bpc, used = 0;
+    while (fscanf(f, "%63s %d %d %d %d %d", arch, &rt, &pass, &packed, &rmax, &bpc) == 6) {
+        if (std::strcmp(arch, ctx->arch) != 0 || rt != ctx->runtime_version) continue;
+        const int lim = plan_limit(ctx, pass, packed != 0, rmax);
+        if (lim < 1 || bpc < 1 || bpc > lim) continue;
+        ctx->plan[pass].packed = packed != 0;
         ctx->plan[pass].rmax = rmax;
         ctx->plan[pass].blocks_per_cu = bpc;
         ++used;
@@ -171,8 +192,8 @@ cm_status save_plans(const cm_context* ctx, const char* path) {
     FILE* f = fopen(path, "w");
     if (!f) return fail(CM_EINVAL, "cannot write %s", path);
     for (int p = 0; p < 3; ++p)
-        fprintf(f, "%s %d %d %d %d\n", ctx->arch, ctx->runtime_version, p, ctx->plan[p].rmax,
-                ctx->plan[p].blocks_per_cu);
+        fprintf(f, "%s %d %d %d %d %d\n", ctx->arch, ctx->runtime_version, p, ctx->plan[p].packed,
+                ctx->plan[p].rmax, ctx->plan[p].blocks_per_cu);
     return fclose(f) == 0 ? CM_OK : fail(CM_EINVAL, "cannot write %s", path);
 }
 
@@ -180,7 +201,7 @@ cm_status save_plans(const cm_context* ctx, const char* path) {
 cm_status reserve(cm_context* ctx, int64_t n) {
     const size_t m = static_cast<size_t>(n);
     if (!ctx->keys.ensure(m * 4) || !ctx->keys_alt.ensure(m * 4) || !ctx->vals.ensure(m * 4) ||
-        !ctx->vals_alt.ensure(m * 4))
+        !ctx->vals_alt.ensure(m * 4) || !ctx->over.ensure(m * 4))
         return fail(CM_ENOMEM, "cannot allocate %zu plan entries", m);
     size_t tmp = 0;
     hipError_t e = hipcub::DeviceRadixSort::SortPairs(
@@ -220,6 +241,38 @@ cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offse
     a.end_a = end_a;
     a.end_b = end_b;
     return run_pass(ctx, a, end_a ? cmk::Pass::ScoreEnd : cmk::Pass::Score, stream);
+}
+
+cm_status end_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                    const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                    int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                    int32_t min_score, hipStream_t stream) {
+    if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
+    if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
+    if (n_pairs == 0) return CM_OK;
+    if (!offsets || !pairs || !scores || !end_a || !end_b) return fail(CM_EINVAL, "NULL required pointer");
+    if (min_score < 0) return fail(CM_EINVAL, "min_score must be >= 0");
+    cm_status s = check_gaps(gap_open, gap_extend);
+    if (s != CM_OK) return s;
+    cmk::SwArgs a{};
+    s = check_matrix(matrix, a.mat);
+    if (s != CM_OK) return s;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    a.seqs = seqs ? seqs : ctx->dummy;
+    a.offsets = offsets;
+    a.pairs = pairs;
+    a.n_pairs = n_pairs;
+    a.n_live = n_live;
+    a.n_seqs = n_seqs;
+    a.go = gap_open;
+    a.ge = gap_extend;
+    a.min_score = min_score;
+    a.end_filter = 1;
+    a.scores = scores;
+    a.end_a = end_a;
+    a.end_b = end_b;
+    return run_pass(ctx, a, cmk::Pass::ScoreEnd, stream);
 }
 
 cm_status span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
@@ -304,6 +357,16 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
         ctx->plan[p].rmax = 16;
         ctx->plan[p].blocks_per_cu = ctx->occ[p][cmk::kNumRMax - 1];
     }
+    for (int k = 0; k < cmk::kNumRMaxPk; ++k) {
+        ctx->occ_pk[k] = cmk::sw_pk_blocks_per_cu(cmk::kRMaxChoicePk[k]);
+        gmax = ctx->occ_pk[k] > gmax ? ctx->occ_pk[k] : gmax;
+    }
+    ctx->occ_over = cmk::sw_over_blocks_per_cu();
+    gmax = ctx->occ_over > gmax ? ctx->occ_over : gmax;
+    // the score pass defaults to the packed kernel with up to 8 rows per lane
+    ctx->plan[CM_PASS_SCORE].packed = 1;
+    ctx->plan[CM_PASS_SCORE].rmax = cmk::kRMaxChoicePk[cmk::kNumRMaxPk - 1];
+    ctx->plan[CM_PASS_SCORE].blocks_per_cu = ctx->occ_pk[cmk::kNumRMaxPk - 1];
     gmax *= ctx->n_cu;
     void* small = nullptr;
     e = hipMalloc(&small, 4096);
@@ -339,6 +402,7 @@ void cm_context_destroy(cm_context* ctx) {
     ctx->vals_alt.release();
     ctx->sort_tmp.release();
     ctx->bnd.release();
+    ctx->over.release();
     ctx->extra_release();
     for (hipEvent_t ev : ctx->timer.pool) (void)hipEventDestroy(ev);
     if (ctx->small) (void)hipFree(ctx->small);
@@ -387,28 +451,26 @@ cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, d
     return CM_OK;
 }
 
-cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* rmax, int32_t* blocks_per_cu, int32_t* max_blocks_per_cu) {
+cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t* rmax, int32_t* blocks_per_cu,
+                      int32_t* max_blocks_per_cu) {
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
-    if (rmax) *rmax = ctx->plan[pass].rmax;
-    if (blocks_per_cu) *blocks_per_cu = ctx->plan[pass].blocks_per_cu;
-    if (max_blocks_per_cu) {
-        int k = 0;
-        for (int q = 0; q < cmk::kNumRMax; ++q)
-            if (cmk::kRMaxChoice[q] == ctx->plan[pass].rmax) k = q;
-        *max_blocks_per_cu = ctx->occ[pass][k];
-    }
+    const cm_context::Plan& pl = ctx->plan[pass];
+    if (packed) *packed = pl.packed;
+    if (rmax) *rmax = pl.rmax;
+    if (blocks_per_cu) *blocks_per_cu = pl.blocks_per_cu;
+    if (max_blocks_per_cu) *max_blocks_per_cu = plan_limit(ctx, pass, pl.packed, pl.rmax);
     return CM_OK;
 }
 
-cm_status cm_plan_set(cm_context* ctx, int pass, int32_t rmax, int32_t blocks_per_cu) {
+cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, int32_t blocks_per_cu) {
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
-    int k = -1;
-    for (int q = 0; q < cmk::kNumRMax; ++q)
-        if (cmk::kRMaxChoice[q] == rmax) k = q;
-    if (k < 0) return fail(CM_EINVAL, "rmax must be 8, 12 or 16");
-    if (blocks_per_cu < 1 || blocks_per_cu > ctx->occ[pass][k])
-        return fail(CM_EINVAL, "blocks_per_cu must be in [1, %d]", ctx->occ[pass][k]);
+    if (packed && pass != CM_PASS_SCORE) return fail(CM_EINVAL, "the packed kernel serves the score pass only");
+    const int lim = plan_limit(ctx, pass, packed != 0, rmax);
+    if (lim < 1) return fail(CM_EINVAL, packed ? "packed rmax must be 4 or 8" : "rmax must be 8, 12 or 16");
+    if (blocks_per_cu < 1 || blocks_per_cu > lim)
+        return fail(CM_EINVAL, "blocks_per_cu must be in [1, %d]", lim);
     drain_timers(ctx, true);
+    ctx->plan[pass].packed = packed != 0;
     ctx->plan[pass].rmax = rmax;
     ctx->plan[pass].blocks_per_cu = blocks_per_cu;
     return CM_OK;

@@ -208,11 +208,15 @@ struct Aligner {
         hipError_t e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
         (void)hipEventRecord(sl.e0, st);
+        // scores of every pair; end and start cells only where the coverage
+        // test can use them (score above mT)
         cm_status s = cm_sw_score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np,
-                                        p->matrix, p->gap_open, p->gap_extend, dsc, spans ? dea : nullptr,
-                                        spans ? deb : nullptr, st);
+                                        p->matrix, p->gap_open, p->gap_extend, dsc, nullptr, nullptr, st);
         if (s != CM_OK) return s;
         if (spans) {
+            s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np, nullptr,
+                                p->matrix, p->gap_open, p->gap_extend, dsc, dea, deb, p->mT, st);
+            if (s != CM_OK) return s;
             s = cm_sw_span_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np, p->matrix,
                                  p->gap_open, p->gap_extend, dsc, dea, deb, p->mT, dsa, dsb, st);
             if (s != CM_OK) return s;
@@ -247,7 +251,7 @@ struct Aligner {
         int64_t* h_live = reinterpret_cast<int64_t*>(static_cast<char*>(sl.h_err.ptr) + 8);
         const std::vector<void*> ptrs = {d_pairs.ptr, d_out.ptr, ctx->keys.ptr, ctx->keys_alt.ptr, ctx->vals.ptr,
                                          ctx->vals_alt.ptr, ctx->sort_tmp.ptr, sl.h_pairs.ptr, sl.h_out.ptr,
-                                         sl.h_err.ptr, ctx->bnd.ptr};
+                                         sl.h_err.ptr, ctx->bnd.ptr, ctx->over.ptr};
         Graph* g = nullptr;
         for (size_t q = 0; q < graphs.size(); ++q) {
             if (graphs[q].ptrs != ptrs) {        // stale: a referenced buffer moved
@@ -266,8 +270,10 @@ struct Aligner {
             (void)hipMemcpyAsync(d_live, h_live, 8, hipMemcpyHostToDevice, st);
             (void)hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
             s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
-                                  p->matrix, p->gap_open, p->gap_extend, dsc, spans ? dsc + cap : nullptr,
-                                  spans ? dsc + 2 * cap : nullptr, st);
+                                  p->matrix, p->gap_open, p->gap_extend, dsc, nullptr, nullptr, st);
+            if (s == CM_OK && spans)
+                s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
+                                    p->matrix, p->gap_open, p->gap_extend, dsc, dsc + cap, dsc + 2 * cap, p->mT, st);
             if (s == CM_OK && spans)
                 s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
                                      p->matrix, p->gap_open, p->gap_extend, dsc, dsc + cap, dsc + 2 * cap, p->mT,
@@ -750,6 +756,7 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
             cache_.put(unordered_key(r1, r2), sc);
         }
         if (sc > p_.mT) {
+            ++st_.end_pairs;
             const int32_t ea = out[nk + q], eb = out[2 * nk + q];
             const int32_t sa = out[3 * nk + q], sb = out[4 * nk + q];
             const int32_t u1 = len_[r1] - (ea - sa + 1);
@@ -937,8 +944,9 @@ cm_status Driver::run(cm_result** out) {
     cmrt::drain_timers(ctx_, true);
     const bool timer_was_on = ctx_->timer.on;
     ctx_->timer.on = true;
-    const int64_t l0 = ctx_->timer.launches[0] + ctx_->timer.launches[1];
-    const double k0 = ctx_->timer.secs[0] + ctx_->timer.secs[1];
+    const int64_t l0 = ctx_->timer.launches[0];
+    const double k0 = ctx_->timer.secs[0];
+    const double e0 = ctx_->timer.secs[1] + ctx_->timer.secs[2];
     cm_status s = al_.init();
     if (s != CM_OK) return s;
     s = load_lengths();
@@ -1004,8 +1012,9 @@ cm_status Driver::run(cm_result** out) {
     st_.t_total_s = secs(t0, t2);
     st_.t_host_s = st_.t_total_s - st_.t_gpu_s;
     cmrt::drain_timers(ctx_, true);
-    st_.sw_launches = ctx_->timer.launches[0] + ctx_->timer.launches[1] - l0;
-    st_.sw_kernel_s = ctx_->timer.secs[0] + ctx_->timer.secs[1] - k0;
+    st_.sw_launches = ctx_->timer.launches[0] - l0;
+    st_.sw_kernel_s = ctx_->timer.secs[0] - k0;
+    st_.end_kernel_s = ctx_->timer.secs[1] + ctx_->timer.secs[2] - e0;
     ctx_->timer.on = timer_was_on;
     res->stats = st_;
     *out = res;

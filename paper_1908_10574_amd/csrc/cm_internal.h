@@ -14,6 +14,12 @@ constexpr int kNumRMax = 3;         // plan choices for the per-lane row limit
 constexpr int kRMaxChoice[kNumRMax] = {8, 12, 16};
 constexpr int kNRes = 21;           // 20 residues + sentinel
 constexpr int kSent = 20;           // sentinel residue code (padding rows / columns)
+// packed 16-bit score kernel: two pairs per group (one per 16-bit half of
+// every register), eight pairs per wavefront
+constexpr int kPairsPerWavePk = 8;
+constexpr int kNumRMaxPk = 2;
+constexpr int kRMaxChoicePk[kNumRMaxPk] = {4, 8};
+constexpr int kPkSaturated = 32767; // a packed score this high may have saturated
 constexpr int kMatStride = 24;      // bytes per row of the int8 matrix in LDS
 // query-profile bytes per row slot: R rows padded to 4, 8 or 16 bytes
 constexpr int prof_row_bytes(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 16); }
@@ -29,7 +35,9 @@ constexpr uint32_t kErrCell = 8u;        // span input end cell outside its sequ
 struct Counters {
     int32_t n_work;      // pairs that need the DP (after the plan kernel)
     int32_t ticket;      // persistent-queue ticket
-    int32_t pad[14];
+    int32_t n_over;      // pairs the packed kernel handed to the int32 kernel
+    int32_t ticket_over; // ticket of the int32 re-run over those pairs
+    int32_t pad[12];
 };
 
 struct SwArgs {
@@ -42,7 +50,11 @@ struct SwArgs {
     int32_t go, ge;
     int32_t min_score;          // span pass: only pairs with score > min_score
     int32_t zero;               // always 0 (see the kernel's clamp)
-    int32_t rmax;               // plan: most query rows per lane (8, 12 or 16)
+    int32_t rmax;               // plan: most query rows per lane (8, 12 or 16; packed: 4 or 8)
+    int32_t packed;             // score pass: run the packed 16-bit kernel
+    int32_t end_filter;         // score+end pass: only pairs whose known score > min_score
+    uint32_t go_pk, ge_pk;      // packed kernel: -gap_open, -gap_extend (capped at 65535) in both halves
+    int32_t* over;              // packed kernel: indices of saturated pairs (capacity n_pairs)
     const uint32_t* keys;       // sorted plan keys (R, strips, columns)
     const int32_t* order;       // pair index per sorted position
     Counters* ctr;
@@ -65,5 +77,9 @@ hipError_t launch_plan(const SwArgs& a, Pass pass, uint32_t* keys_out, int32_t* 
                        hipStream_t s);
 hipError_t launch_sw(const SwArgs& a, Pass pass, int grid, hipStream_t s);   // uses a.rmax
 int sw_blocks_per_cu(Pass pass, int rmax);
+// packed score kernel followed by the int32 re-run of saturated pairs
+hipError_t launch_sw_pk(const SwArgs& a, int grid, int grid_over, hipStream_t s);   // uses a.rmax
+int sw_pk_blocks_per_cu(int rmax);
+int sw_over_blocks_per_cu();
 
 }  // namespace cmk

@@ -40,10 +40,14 @@ struct KernelTimer {
 struct cm_context {
     int device = 0;
     int n_cu = 0;
-    // launch plan per pass (score, score+end, span): rows-per-lane limit and
-    // persistent blocks per CU; occ = occupancy limit per (pass, rmax choice)
-    struct Plan { int rmax = 16; int blocks_per_cu = 1; } plan[3];
+    // launch plan per pass (score, score+end, span): kernel (packed 16-bit,
+    // score pass only, or int32), rows-per-lane limit and persistent blocks per
+    // CU; occ = occupancy limit per (pass, rmax choice), occ_pk per packed rmax
+    // choice, occ_over of the int32 re-run of saturated packed pairs
+    struct Plan { int packed = 0; int rmax = 16; int blocks_per_cu = 1; } plan[3];
     int occ[3][cmk::kNumRMax] = {};
+    int occ_pk[cmk::kNumRMaxPk] = {};
+    int occ_over = 1;
     char arch[64] = {0};
     int runtime_version = 0;
     void* small = nullptr;              // counters, error flag, dummy bytes
@@ -52,6 +56,7 @@ struct cm_context {
     const uint8_t* dummy = nullptr;
     cmrt::DeviceBuf keys, keys_alt, vals, vals_alt, sort_tmp;
     cmrt::DeviceBuf bnd;                // boundary rows between strips
+    cmrt::DeviceBuf over;               // saturated pairs of the packed kernel
     int32_t bnd_stride = 0;
     // buffers of the ClusterMerge driver and the screen (released with the context)
     cmrt::DeviceBuf drv[12];
@@ -81,4 +86,12 @@ cm_status span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offset
                      const int32_t* end_b, int32_t min_score, int32_t* start_a, int32_t* start_b,
                      hipStream_t stream);
 cm_status save_plans(const cm_context* ctx, const char* path);
+// occupancy limit of a plan (0 if the plan is not valid for the pass)
+int plan_limit(const cm_context* ctx, int pass, int packed, int rmax);
+// score+end of the pairs whose known score (scores[], kept) exceeds min_score;
+// the others get end cell (-1, -1)
+cm_status end_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                    const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                    int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                    int32_t min_score, hipStream_t stream);
 }

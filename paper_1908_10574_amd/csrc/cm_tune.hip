@@ -1,6 +1,7 @@
 // cm_tune.hip -- autotuner for the alignment launch plan.
 //
-// A plan is (rows-per-lane limit, persistent blocks per CU).  The limit trades
+// A plan is (kernel, rows-per-lane limit, persistent blocks per CU); the score
+// pass can run the packed 16-bit kernel or the int32 kernel.  The limit trades
 // LDS footprint and occupancy against strip count: 8 rows per lane keeps two
 // times more wavefronts resident but splits queries longer than 128 residues
 // into more strips (more ramp steps, more boundary traffic); 16 does the
@@ -25,6 +26,7 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
     const cm_context::Plan saved = ctx->plan[pass];
     const bool with_end = pass == CM_PASS_SCORE_END;
+    constexpr int kMaxRows = 16;
     int32_t* d = nullptr;
     hipError_t e = hipMalloc(&d, static_cast<size_t>(n_pairs) * 12);
     if (e != hipSuccess) return hip_fail(e, "tuner buffers");
@@ -39,13 +41,21 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     cm_context::Plan best = saved;
     int rows = 0;
     cm_status st = CM_OK;
-    for (int k = 0; k < cmk::kNumRMax && st == CM_OK; ++k) {
-        const int occ = ctx->occ[pass][k];
-        int cands[3] = {occ, (occ * 3) / 4, occ / 2};
+    // candidates: (kernel, rows-per-lane limit); the packed kernel serves the score pass only
+    struct Cand { int packed, rmax; };
+    std::vector<Cand> cands;
+    if (pass == CM_PASS_SCORE)
+        for (int k = 0; k < cmk::kNumRMaxPk; ++k) cands.push_back({1, cmk::kRMaxChoicePk[k]});
+    for (int k = 0; k < cmk::kNumRMax; ++k) cands.push_back({0, cmk::kRMaxChoice[k]});
+    for (const Cand& cd : cands) {
+        if (st != CM_OK) break;
+        const int occ = cmrt::plan_limit(ctx, pass, cd.packed, cd.rmax);
+        int bpcs[3] = {occ, (occ * 3) / 4, occ / 2};
         for (int c = 0; c < 3 && st == CM_OK; ++c) {
-            const int bpc = cands[c];
-            if (bpc < 1 || (c > 0 && bpc == cands[c - 1]) || (c > 1 && bpc == cands[c - 2])) continue;
-            ctx->plan[pass].rmax = cmk::kRMaxChoice[k];
+            const int bpc = bpcs[c];
+            if (bpc < 1 || (c > 0 && bpc == bpcs[c - 1]) || (c > 1 && bpc == bpcs[c - 2])) continue;
+            ctx->plan[pass].packed = cd.packed;
+            ctx->plan[pass].rmax = cd.rmax;
             ctx->plan[pass].blocks_per_cu = bpc;
             double ms = 1e300;
             for (int rep = 0; rep < 3 && st == CM_OK; ++rep) {
@@ -68,12 +78,13 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
                 break;
             }
             if (ref.empty()) ref = cur;
-            else if (ref != cur) { st = fail(CM_EDEVICE, "launch plans disagree (rmax %d, %d blocks/CU)",
-                                             cmk::kRMaxChoice[k], bpc); break; }
-            if (table && rows < 9) {
-                table[3 * rows] = cmk::kRMaxChoice[k];
-                table[3 * rows + 1] = bpc;
-                table[3 * rows + 2] = ms;
+            else if (ref != cur) { st = fail(CM_EDEVICE, "launch plans disagree (%s, rmax %d, %d blocks/CU)",
+                                             cd.packed ? "packed" : "int32", cd.rmax, bpc); break; }
+            if (table && rows < kMaxRows) {
+                table[4 * rows] = cd.packed;
+                table[4 * rows + 1] = cd.rmax;
+                table[4 * rows + 2] = bpc;
+                table[4 * rows + 3] = ms;
             }
             ++rows;
             if (ms < best_ms) { best_ms = ms; best = ctx->plan[pass]; }
@@ -83,6 +94,6 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     (void)hipEventDestroy(t1);
     (void)hipFree(d);
     ctx->plan[pass] = st == CM_OK ? best : saved;
-    if (n_rows) *n_rows = rows < 9 ? rows : 9;
+    if (n_rows) *n_rows = rows < kMaxRows ? rows : kMaxRows;
     return st;
 }

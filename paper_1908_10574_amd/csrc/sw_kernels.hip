@@ -98,12 +98,12 @@ __device__ __forceinline__ int wave_max4(int v) {
 }
 
 // rows per lane for a query of m rows under a per-lane limit rmax: fewest
-// strips, then fewest rows per lane, rounded up to an even count (the kernel
-// is instantiated for even R)
-__device__ __forceinline__ void shape_for(int m, int rmax, int& R, int& strips) {
+// strips, then fewest rows per lane (rounded up to an even count for the int32
+// kernel, which is instantiated for even R; the packed kernel takes any R)
+__device__ __forceinline__ void shape_for(int m, int rmax, bool even, int& R, int& strips) {
     strips = (m + kGroup * rmax - 1) / (kGroup * rmax);
     R = (m + kGroup * strips - 1) / (kGroup * strips);
-    R += R & 1;
+    if (even) R += R & 1;
     if (R > rmax) R = rmax;
 }
 
@@ -111,7 +111,7 @@ __device__ __forceinline__ void shape_for(int m, int rmax, int& R, int& strips) 
 // plan: validate, write trivial results, build sort keys
 // ---------------------------------------------------------------------------
 __global__ void k_zero_counters(Counters* c) {
-    if (threadIdx.x == 0) { c->n_work = 0; c->ticket = 0; }
+    if (threadIdx.x == 0) { c->n_work = 0; c->ticket = 0; c->n_over = 0; c->ticket_over = 0; }
 }
 
 __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
@@ -127,6 +127,7 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
     const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
     int m = 0, n = 0;
     bool trivial = true;
+    bool keep_score = false;   // filtered score+end pass: the known score stays
     if (x < 0 || x >= a.n_seqs || y < 0 || y >= a.n_seqs) {
         atomicOr(a.err, kErrIndex);
     } else {
@@ -144,6 +145,8 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
                     m = ea + 1; n = eb + 1; trivial = false;
                 }
             }
+        } else if (P == Pass::ScoreEnd && a.end_filter && a.scores[p] <= a.min_score) {
+            keep_score = true;
         } else {
             m = static_cast<int>(lx); n = static_cast<int>(ly);
             trivial = (m == 0 || n == 0);
@@ -153,14 +156,14 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
         if (P == Pass::Span) {
             a.start_a[p] = -1; a.start_b[p] = -1;
         } else {
-            a.scores[p] = 0;
+            if (!keep_score) a.scores[p] = 0;
             if (a.end_a) { a.end_a[p] = -1; a.end_b[p] = -1; }
         }
     } else {
         int R, strips;
-        shape_for(m, a.rmax, R, strips);
+        shape_for(m, a.rmax, !a.packed, R, strips);
         key = (static_cast<uint32_t>(kRMax - R) << 24) |
-              (static_cast<uint32_t>(127 - strips) << 16) |
+              (static_cast<uint32_t>(255 - min(strips, 255)) << 16) |
               static_cast<uint32_t>(65535 - n);
         atomicAdd(&a.ctr->n_work, 1);
     }
@@ -172,9 +175,9 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
 // one wavefront item: four pairs of the same rows-per-lane class
 // ---------------------------------------------------------------------------
 template <int R, Pass P, int RMAXT>
-__device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
-                                                   const int8_t* __restrict__ s_mat,
-                                                   uint8_t* __restrict__ s_prof) {
+__device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restrict__ order, int item,
+                                         int n_work, const int8_t* __restrict__ s_mat,
+                                         uint8_t* __restrict__ s_prof) {
     constexpr int RP = R <= 4 ? 4 : (R <= 8 ? 8 : 16);
     constexpr int W = RP / 4;
     constexpr int kRows = kGroup * R;
@@ -193,7 +196,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, int item, int n_work,
     const uint8_t* A = a.seqs;
     const uint8_t* B = a.seqs;
     if (has) {
-        p = a.order[pos];
+        p = order[pos];
         const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
         A = a.seqs + a.offsets[x];
         B = a.seqs + a.offsets[y];
@@ -459,18 +462,394 @@ __global__ __launch_bounds__(64) void k_sw(SwArgs a) {
         if (item >= n_items) break;
         const uint32_t key = a.keys[static_cast<int64_t>(item) * kPairsPerWave];
         const int R = kRMax - static_cast<int>(key >> 24);
-        if (R <= 2) run_item<2, P, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R <= 4) run_item<4, P, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R <= 6) run_item<6, P, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R <= 8 || RMAXT == 8) run_item<8, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+        if (R <= 2) run_item<2, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R <= 4) run_item<4, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R <= 6) run_item<6, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R <= 8 || RMAXT == 8) run_item<8, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
         else if constexpr (RMAXT >= 12) {
-            if (R <= 10) run_item<10, P, RMAXT>(a, item, n_work, s_mat, s_prof);
-            else if (R <= 12 || RMAXT == 12) run_item<12, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+            if (R <= 10) run_item<10, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
+            else if (R <= 12 || RMAXT == 12) run_item<12, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
             else if constexpr (RMAXT >= 16) {
-                if (R <= 14) run_item<14, P, RMAXT>(a, item, n_work, s_mat, s_prof);
-                else run_item<16, P, RMAXT>(a, item, n_work, s_mat, s_prof);
+                if (R <= 14) run_item<14, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
+                else run_item<16, P, RMAXT>(a, a.order, item, n_work, s_mat, s_prof);
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// packed 16-bit score kernel
+//
+// The same strip / skew / DPP decomposition as run_item, but every register
+// holds two pairs: the low 16 bits belong to one pair and the high 16 bits to
+// another pair of the same shape class, so each VOP3P instruction advances two
+// cells.  With E' and F' clamped at zero and every value non-negative, the
+// cell update is nine packed operations for two cells:
+//     t  = sat(Hdiag + s)              signed saturating add
+//     h  = max(max(t, E'), F')
+//     g  = max(h + go, 0)              unsigned saturating subtract of -go
+//     E' = max(max(E' + ge, 0), g)     (likewise for F')
+//     best = max(best, h)
+// plus the sign extension of the int8 profile bytes into 16-bit halves (one
+// v_perm per two cells, one shift per four).  No value can exceed the best
+// score, and the signed add saturates at 32767, so a pair whose packed best
+// stays below 32767 has its exact score; a pair that reaches 32767 is queued
+// for the int32 kernel (k_sw_over).
+// ---------------------------------------------------------------------------
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_adds(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(s16x2, a),
+                                                                      __builtin_bit_cast(s16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_maxs(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, a),
+                                                                  __builtin_bit_cast(s16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_maxu(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                  __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t pk_subu(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
+                                                                      __builtin_bit_cast(u16x2, b)));
+}
+// (sign-extended byte k of wa, sign-extended byte k of wb) as two 16-bit
+// halves.  v_perm can replicate the sign bit of bytes 1 and 3 of either source
+// (selectors 8..11), so odd bytes come straight from the words and even bytes
+// from the words shifted left by 8 (sa = wa << 8, sb = wb << 8).
+template <int K>
+__device__ __forceinline__ uint32_t pk_sbyte(uint32_t wa, uint32_t wb, uint32_t sa, uint32_t sb) {
+    constexpr uint32_t kSel1 = 0x0A050801u;   // bytes: a1, sign(a1), b1, sign(b1)
+    constexpr uint32_t kSel3 = 0x0B070903u;   // bytes: a3, sign(a3), b3, sign(b3)
+    if constexpr (K == 0) return __builtin_amdgcn_perm(sb, sa, kSel1);
+    else if constexpr (K == 1) return __builtin_amdgcn_perm(wb, wa, kSel1);
+    else if constexpr (K == 2) return __builtin_amdgcn_perm(sb, sa, kSel3);
+    else return __builtin_amdgcn_perm(wb, wa, kSel3);
+}
+
+template <int W>
+__device__ __forceinline__ ProfWords<W> load_prof_at(const uint8_t* p) {
+    ProfWords<W> r;
+    if constexpr (W == 2) {
+        uint2 v = *reinterpret_cast<const uint2*>(p);
+        r.w[0] = v.x; r.w[1] = v.y;
+    } else {
+        r.w[0] = *reinterpret_cast<const uint32_t*>(p);
+    }
+    return r;
+}
+
+template <int R, int RMAXT>
+__device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_work,
+                                            const int8_t* __restrict__ s_mat, uint8_t* __restrict__ s_prof) {
+    constexpr int RP = prof_row_bytes(R);            // 4 or 8 bytes of profile per lane and residue
+    constexpr int W = RP / 4;
+    constexpr int kRows = kGroup * R;
+    constexpr int kColStride = kGroup * RP;          // bytes between the residue rows of a profile
+    constexpr int kProfBytes = kNRes * kGroup * prof_row_bytes(RMAXT);
+    constexpr uint32_t kSentPk = static_cast<uint32_t>(kSent * kColStride) * 0x10001u;
+    const int lane = threadIdx.x;
+    const int g = lane >> 4;
+    const int gl = lane & 15;
+    const uint32_t GO = a.go_pk, GE = a.ge_pk;
+
+    bool has[2];
+    int p[2], m[2], n[2];
+    const uint8_t* A[2];
+    const uint8_t* B[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t pos = static_cast<int64_t>(item) * kPairsPerWavePk + 2 * g + h;
+        has[h] = pos < n_work;
+        p[h] = 0; m[h] = 0; n[h] = 0;
+        A[h] = a.seqs; B[h] = a.seqs;
+        if (has[h]) {
+            p[h] = a.order[pos];
+            const int x = a.pairs[2 * p[h]], y = a.pairs[2 * p[h] + 1];
+            A[h] = a.seqs + a.offsets[x];
+            B[h] = a.seqs + a.offsets[y];
+            m[h] = static_cast<int>(a.offsets[x + 1] - a.offsets[x]);
+            n[h] = static_cast<int>(a.offsets[y + 1] - a.offsets[y]);
+        }
+    }
+    const int S0 = (m[0] + kRows - 1) / kRows;
+    const int S1 = (m[1] + kRows - 1) / kRows;
+    const int s_max = wave_max4(max(S0, S1));
+    uint8_t* prof0 = s_prof + (2 * g) * kProfBytes;
+    uint8_t* prof1 = prof0 + kProfBytes;
+    const uint8_t* lp0 = prof0 + gl * RP;
+    const uint8_t* lp1 = prof1 + gl * RP;
+    int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
+
+    bool bad = false;
+    uint32_t best = 0;
+
+    for (int s = 0; s < s_max; ++s) {
+        const bool act0 = s < S0, act1 = s < S1;
+        const bool rd0 = act0 && s > 0, rd1 = act1 && s > 0;
+        const bool wr0 = act0 && s + 1 < S0, wr1 = act1 && s + 1 < S1;
+        const int row0 = s * kRows;
+        const int n_act = max(act0 ? n[0] : 0, act1 ? n[1] : 0);
+        const int n_max = wave_max4(n_act);
+        const bool rd_any = wave_max4((rd0 || rd1) ? 1 : 0) != 0;
+        const bool wr_any = wave_max4((wr0 || wr1) ? 1 : 0) != 0;
+
+        // ---- the two query profiles of this strip: prof_h[c][gl][r] = M[a_i][c]
+        {
+            int code0[R], code1[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = row0 + gl * R + r;
+                int v0 = kSent, v1 = kSent;
+                if (act0 && i < m[0]) {
+                    v0 = A[0][i];
+                    if (v0 > 19) { bad = true; v0 = kSent; }
+                }
+                if (act1 && i < m[1]) {
+                    v1 = A[1][i];
+                    if (v1 > 19) { bad = true; v1 = kSent; }
+                }
+                code0[r] = v0 * kMatStride;
+                code1[r] = v1 * kMatStride;
+            }
+            __syncthreads();   // previous strip's readers are done with the profiles
+#pragma unroll 1
+            for (int c = 0; c < kNRes; ++c) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    uint32_t w[W];
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int r = 4 * q + k;
+                            const int8_t v = (r < R) ? s_mat[(h ? code1[r] : code0[r]) + c] : int8_t(-128);
+                            word |= static_cast<uint32_t>(static_cast<uint8_t>(v)) << (8 * k);
+                        }
+                        w[q] = word;
+                    }
+                    uint8_t* dst = (h ? prof1 : prof0) + c * kColStride + gl * RP;
+                    if constexpr (W == 2) *reinterpret_cast<uint2*>(dst) = make_uint2(w[0], w[1]);
+                    else *reinterpret_cast<uint32_t*>(dst) = w[0];
+                }
+            }
+            __syncthreads();
+        }
+
+        // column residues of both pairs, as profile byte offsets in the two halves
+        const bool live0 = act0 && n[0] > 0, live1 = act1 && n[1] > 0;
+        // the two bytes stay separate until their chunk is switched in, so
+        // the loads remain in flight for a whole 16-column chunk
+        auto col_raw = [&](int col) -> int2 {
+            const uint8_t* s0 = live0 ? B[0] + min(col, n[0] - 1) : a.dummy;
+            const uint8_t* s1 = live1 ? B[1] + min(col, n[1] - 1) : a.dummy;
+            return make_int2(*s0, *s1);
+        };
+        auto col_in = [&](int2 v, int col) -> uint32_t {
+            int c0 = v.x, c1 = v.y;
+            if (!(act0 && col < n[0])) c0 = kSent;
+            else if (c0 > 19) { bad = true; c0 = kSent; }
+            if (!(act1 && col < n[1])) c1 = kSent;
+            else if (c1 > 19) { bad = true; c1 = kSent; }
+            return static_cast<uint32_t>(c0 * kColStride) | (static_cast<uint32_t>(c1 * kColStride) << 16);
+        };
+        auto rd_mask = [&](int col) -> uint32_t {
+            return ((rd0 && col < n[0]) ? 0xffffu : 0u) | ((rd1 && col < n[1]) ? 0xffff0000u : 0u);
+        };
+        auto bnd_raw = [&](int col) -> int2 { return bnd[min(col, a.bnd_stride - 1)]; };
+
+        auto sweep = [&](auto multi) {
+            constexpr bool kMulti = decltype(multi)::value;
+            uint32_t HA[R], HB[R], E[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) { HA[r] = 0; E[r] = 0; }
+            uint32_t hdiag = 0, Hout = 0, Fout = 0;
+            uint32_t feedR = col_in(col_raw(gl), gl);
+            int2 nfeedR = col_raw(kGroup + gl);
+            uint32_t feedH = 0, feedF = 0, collH = 0, collF = 0;
+            int2 nfeed = make_int2(0, 0);
+            if constexpr (kMulti) {
+                const int2 v0 = bnd_raw(gl);
+                const uint32_t mk = rd_mask(gl);
+                feedH = static_cast<uint32_t>(v0.x) & mk;
+                feedF = static_cast<uint32_t>(v0.y) & mk;
+                nfeed = bnd_raw(kGroup + gl);
+            }
+            uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR), static_cast<int>(kSentPk)));
+            ProfWords<W> pa0 = load_prof_at<W>(lp0 + (c & 0xffffu));
+            ProfWords<W> pa1 = load_prof_at<W>(lp1 + (c >> 16));
+            ProfWords<W> pb0, pb1;
+
+            auto cells = [&](const uint32_t (&Hi)[R], uint32_t (&Ho)[R], const ProfWords<W>& w0,
+                             const ProfWords<W>& w1) {
+                uint32_t Htop, F;
+                if constexpr (kMulti) {
+                    Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedH), static_cast<int>(Hout)));
+                    F = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedF), static_cast<int>(Fout)));
+                } else {
+                    Htop = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Hout)));
+                    F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
+                }
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t wa = w0.w[q], wb = w1.w[q];
+                    const uint32_t sa = wa << 8, sb = wb << 8;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int r = 4 * q + k;
+                        if (r >= R) break;
+                        uint32_t sub;
+                        if (k == 0) sub = pk_sbyte<0>(wa, wb, sa, sb);
+                        else if (k == 1) sub = pk_sbyte<1>(wa, wb, sa, sb);
+                        else if (k == 2) sub = pk_sbyte<2>(wa, wb, sa, sb);
+                        else sub = pk_sbyte<3>(wa, wb, sa, sb);
+                        const uint32_t d = (r == 0) ? hdiag : Hi[r - 1];
+                        const uint32_t h = pk_maxs(pk_maxs(pk_adds(d, sub), E[r]), F);
+                        const uint32_t go = pk_subu(h, GO);
+                        E[r] = pk_maxu(pk_subu(E[r], GE), go);
+                        F = pk_maxu(pk_subu(F, GE), go);
+                        Ho[r] = h;
+                        best = pk_maxs(best, h);
+                    }
+                }
+                hdiag = Htop;
+                Hout = Ho[R - 1];
+                Fout = F;
+            };
+            auto boundary = [&](int t, bool chunk_end) {
+                if constexpr (kMulti) {
+                    if (chunk_end) {
+                        const uint32_t mk = rd_mask(t + 1 + gl);
+                        feedH = static_cast<uint32_t>(nfeed.x) & mk;
+                        feedF = static_cast<uint32_t>(nfeed.y) & mk;
+                        nfeed = bnd_raw(t + 1 + kGroup + gl);
+                    } else {
+                        feedH = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedH)));
+                        feedF = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedF)));
+                    }
+                    collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
+                    collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
+                    if ((t & (kGroup - 1)) == kGroup - 1) {
+                        const int col = t - 2 * (kGroup - 1) + gl;
+                        if (col >= 0 && ((wr0 && col < n[0]) || (wr1 && col < n[1])))
+                            bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
+                    }
+                }
+            };
+
+            const int steps = (n_max + kGroup - 1 + 1) & ~1;
+#pragma unroll 1
+            for (int t = 0; t < steps; t += 2) {
+                {   // step t (even, never the last step of a 16-column chunk)
+                    const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
+                    const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+                    pb0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
+                    pb1 = load_prof_at<W>(lp1 + (cn >> 16));
+                    __builtin_amdgcn_sched_barrier(0);
+                    cells(HA, HB, pa0, pa1);
+                    boundary(t, false);
+                    feedR = feedR2;
+                    c = cn;
+                }
+                {   // step t+1
+                    const bool chunk_end = ((t + 2) & (kGroup - 1)) == 0;
+                    uint32_t feedR2;
+                    if (chunk_end) {
+                        feedR2 = col_in(nfeedR, t + 2 + gl);
+                        nfeedR = col_raw(t + 2 + kGroup + gl);
+                    } else {
+                        feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
+                    }
+                    const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+                    pa0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
+                    pa1 = load_prof_at<W>(lp1 + (cn >> 16));
+                    __builtin_amdgcn_sched_barrier(0);
+                    cells(HB, HA, pb0, pb1);
+                    boundary(t + 1, chunk_end);
+                    feedR = feedR2;
+                    c = cn;
+                }
+            }
+            if constexpr (kMulti) {
+                const int col = (steps - 1) - 2 * (kGroup - 1) + gl;
+                if (col >= 0 && ((wr0 && col < n[0]) || (wr1 && col < n[1])))
+                    bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
+                __threadfence();
+            }
+        };
+        if (rd_any || wr_any) sweep(std::true_type{});
+        else sweep(std::false_type{});
+    }
+
+    // ---- group reduction (both halves at once) and output
+    uint32_t Sb = best;
+#pragma unroll
+    for (int k = 1; k < kGroup; k <<= 1)
+        Sb = pk_maxs(Sb, static_cast<uint32_t>(__shfl_xor(static_cast<int>(Sb), k, kGroup)));
+    if (gl == 0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (!has[h]) continue;
+            const int v = static_cast<int>(h ? (Sb >> 16) : (Sb & 0xffffu));
+            if (v >= kPkSaturated) {
+                const int slot = atomicAdd(&a.ctr->n_over, 1);
+                a.over[slot] = p[h];
+            } else {
+                a.scores[p[h]] = v;
+            }
+        }
+    }
+    if (bad) atomicOr(a.err, kErrResidue);
+}
+
+template <int RMAXT>
+__global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
+    __shared__ int8_t s_mat[kNRes * kMatStride];
+    __shared__ __attribute__((aligned(16))) uint8_t
+        s_prof[kPairsPerWave * 2 * kNRes * kGroup * prof_row_bytes(RMAXT)];
+    for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
+    __syncthreads();
+    const int n_work = a.ctr->n_work;
+    const int n_items = (n_work + kPairsPerWavePk - 1) / kPairsPerWavePk;
+    while (true) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(&a.ctr->ticket, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items) break;
+        const uint32_t key = a.keys[static_cast<int64_t>(item) * kPairsPerWavePk];
+        const int R = kRMax - static_cast<int>(key >> 24);
+        if (R <= 1) run_item_pk<1, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R == 2) run_item_pk<2, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R == 3) run_item_pk<3, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT>(a, item, n_work, s_mat, s_prof);
+        else if constexpr (RMAXT >= 8) {
+            if (R == 5) run_item_pk<5, RMAXT>(a, item, n_work, s_mat, s_prof);
+            else if (R == 6) run_item_pk<6, RMAXT>(a, item, n_work, s_mat, s_prof);
+            else if (R == 7) run_item_pk<7, RMAXT>(a, item, n_work, s_mat, s_prof);
+            else run_item_pk<8, RMAXT>(a, item, n_work, s_mat, s_prof);
+        }
+    }
+}
+
+// int32 re-run of the pairs whose packed score saturated (usually none): the
+// widest rows-per-lane shape handles any query length
+__global__ __launch_bounds__(64) void k_sw_over(SwArgs a) {
+    __shared__ int8_t s_mat[kNRes * kMatStride];
+    __shared__ __attribute__((aligned(16))) uint8_t s_prof[kPairsPerWave * kNRes * kGroup * prof_row_bytes(kRMax)];
+    const int n_work = a.ctr->n_over;
+    if (n_work == 0) return;
+    for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
+    __syncthreads();
+    const int n_items = (n_work + kPairsPerWave - 1) / kPairsPerWave;
+    while (true) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(&a.ctr->ticket_over, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items) break;
+        run_item<kRMax, Pass::Score, kRMax>(a, a.over, item, n_work, s_mat, s_prof);
     }
 }
 
@@ -514,6 +893,28 @@ static int occupancy(int rmax) {
         case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 12>, 64, 0); break;
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 16>, 64, 0); break;
     }
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+hipError_t launch_sw_pk(const SwArgs& a, int grid, int grid_over, hipStream_t s) {
+    switch (a.rmax) {
+        case 4:  hipLaunchKernelGGL((k_sw_pk<4>), dim3(grid), dim3(64), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sw_pk<8>), dim3(grid), dim3(64), 0, s, a); break;
+    }
+    hipLaunchKernelGGL(k_sw_over, dim3(grid_over), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+int sw_pk_blocks_per_cu(int rmax) {
+    int nb = 0;
+    hipError_t e = (rmax == 4) ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw_pk<4>, 64, 0)
+                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw_pk<8>, 64, 0);
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+int sw_over_blocks_per_cu() {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw_over, 64, 0);
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 

@@ -42,24 +42,33 @@ def run(cm, ctx, ds, pairs):
     return out, s_only.cpu().numpy()
 
 
-@pytest.mark.parametrize("rmax", [8, 12, 16])
-def test_every_plan_is_exact(cm, data, rmax):
+PLANS = [(0, 8), (0, 12), (0, 16), (1, 4), (1, 8)]
+
+
+@pytest.mark.parametrize("packed,rmax", PLANS)
+def test_every_plan_is_exact(cm, data, packed, rmax):
+    """Every (kernel, rows-per-lane limit, blocks per CU) gives the oracle's results;
+    the packed kernel serves the score pass, the others keep an int32 plan."""
     ds, pairs, ref = data
     ctx = cm.Context(0)
-    for p in range(3):
-        _, _, _ = ctx.get_plan(p)
-    occ = [ctx.get_plan(p)[2] for p in range(3)]
+    assert ctx.get_plan(0)[:2] == (1, 8)            # default score plan: packed, 8 rows
     for bpc_pick in ("one", "max"):
         for p in range(3):
-            ctx.set_plan(p, 16, 1)                      # occupancy limit of this rmax:
-            ctx.set_plan(p, rmax, 1)
-            mx = ctx.get_plan(p)[2]
-            ctx.set_plan(p, rmax, 1 if bpc_pick == "one" else mx)
+            if packed and p != 0:
+                ctx.set_plan(p, 0, 16, 1)
+                continue
+            ctx.set_plan(p, packed, rmax, 1)
+            mx = ctx.get_plan(p)[3]
+            assert mx >= 1
+            ctx.set_plan(p, packed, rmax, 1 if bpc_pick == "one" else mx)
         out, s_only = run(cm, ctx, ds, pairs)
         bad = np.flatnonzero((out != ref).any(1))
-        assert len(bad) == 0, (rmax, bpc_pick, pairs[bad[0]], out[bad[0]], ref[bad[0]])
+        assert len(bad) == 0, (packed, rmax, bpc_pick, pairs[bad[0]], out[bad[0]], ref[bad[0]])
         assert np.array_equal(s_only, ref[:, 0])
-    assert all(o >= 1 for o in occ)
+    with pytest.raises(cm.CMError):
+        ctx.set_plan(1, 1, 8, 1)                     # packed plans exist for the score pass only
+    with pytest.raises(cm.CMError):
+        ctx.set_plan(0, 1, 16, 1)                    # packed rows-per-lane limit is 4 or 8
     ctx.close()
 
 
@@ -69,29 +78,29 @@ def test_autotune_and_plan_cache(cm, data, tmp_path):
     res = torch.from_numpy(ds.residues).cuda()
     off = torch.from_numpy(ds.offsets).cuda()
     rows = ctx.autotune(res, off, torch.from_numpy(pairs).cuda(), ds.matrix, 0)
-    assert len(rows) >= 3
-    best = min(rows, key=lambda r: r[2])
-    assert ctx.get_plan(0)[:2] == best[:2]
+    assert len(rows) >= 5 and {r[0] for r in rows} == {0, 1}
+    best = min(rows, key=lambda r: r[3])
+    assert ctx.get_plan(0)[:3] == best[:3]
     out, s_only = run(cm, ctx, ds, pairs)
     assert np.array_equal(out, ref) and np.array_equal(s_only, ref[:, 0])
     path = str(tmp_path / "plans.txt")
     ctx.save_plans(path)
     ctx2 = cm.Context(0)
-    ctx2.set_plan(0, 8, 1)
+    ctx2.set_plan(0, 0, 8, 1)
     ctx2.load_plans(path)
-    assert ctx2.get_plan(0)[:2] == best[:2]
+    assert ctx2.get_plan(0)[:3] == best[:3]
     bad = tmp_path / "bad.txt"
     bad.write_text("not a plan file\n")
     with pytest.raises(cm.CMError):
         ctx2.load_plans(str(bad))
-    assert ctx2.get_plan(0)[:2] == best[:2]
+    assert ctx2.get_plan(0)[:3] == best[:3]
     os.environ["CM_AUTOTUNE_CACHE"] = path
     try:
         ctx3 = cm.Context(0)
-        assert ctx3.get_plan(0)[:2] == best[:2]
+        assert ctx3.get_plan(0)[:3] == best[:3]
         os.environ["CM_AUTOTUNE_CACHE"] = str(bad)
         ctx4 = cm.Context(0)                      # corrupt cache: defaults
-        assert ctx4.get_plan(0)[0] == 16
+        assert ctx4.get_plan(0)[:2] == (1, 8) and ctx4.get_plan(1)[:2] == (0, 16)
     finally:
         del os.environ["CM_AUTOTUNE_CACHE"]
     for c in (ctx, ctx2, ctx3, ctx4):

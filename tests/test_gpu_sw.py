@@ -218,3 +218,40 @@ def test_throughput_full_size_sampled(cm):
     osc, oea, oeb = sw_batch(ds.residues, ds.offsets, ds.pairs[pick], ds.matrix)
     assert np.array_equal(a[pick], osc)
     assert np.array_equal(ea.cpu().numpy()[pick], oea) and np.array_equal(eb.cpu().numpy()[pick], oeb)
+
+
+def test_packed_saturation_boundary(cm):
+    """Scores around the 16-bit limit of the packed score kernel.  With a +127
+    diagonal, an identical pair of length L scores 127 L: 258 residues give 32766
+    (exact in 16 bits), 259 give 32893 (the packed sum saturates and the pair is
+    recomputed by the int32 kernel).  Saturating and ordinary pairs share groups."""
+    M = np.full((20, 20), -7, np.int32)
+    np.fill_diagonal(M, 127)
+    rng = np.random.default_rng(97)
+    lens = [257, 258, 259, 260, 300, 1000, 4000]
+    seqs = []
+    for L in lens:
+        s = rng.integers(0, 20, size=L).astype(np.uint8)
+        seqs += [s, s.copy(), rng.integers(0, 20, size=L).astype(np.uint8)]
+    ds = cmgen.from_list(seqs, M)
+    pairs = []
+    for k in range(len(lens)):
+        a, b, c = 3 * k, 3 * k + 1, 3 * k + 2
+        pairs += [(a, b), (b, a), (a, a), (a, c), (c, b), (c, c)]
+    pairs = np.array(pairs * 3, np.int32)
+    res, off, pr = to_dev(ds, pairs)
+    sc = cm.sw_score_batch(res, off, pr, M)
+    cm.sync()
+    ref = sw_batch(ds.residues, ds.offsets, pairs, M, with_end=False)
+    assert np.array_equal(sc.cpu().numpy(), ref)
+    assert (ref > 32767).sum() > 10 and ((ref > 32000) & (ref < 32767)).sum() >= 6
+    ctx = cm.context()
+    saved = ctx.get_plan(0)
+    try:
+        for rmax in (4, 8):
+            ctx.set_plan(0, 1, rmax, 1)
+            sc = cm.sw_score_batch(res, off, pr, M)
+            cm.sync()
+            assert np.array_equal(sc.cpu().numpy(), ref), rmax
+    finally:
+        ctx.set_plan(0, saved[0], saved[1], saved[2])
