@@ -167,7 +167,9 @@ def main():
         exchange_alignments=s["exchange_alignments"], full_merges=s["full_merges"], exchanges=s["exchanges"],
         n_clusters=s["n_clusters"], n_similar_pairs=s["n_similar_pairs"], waves=s["waves"],
         gpu_s=s["t_gpu_s"], host_s=s["t_host_s"], merge_s=s["t_merge_s"], final_s=s["t_final_s"],
-        score_kernel_s=s["sw_kernel_s"], end_kernel_s=s["end_kernel_s"], end_pairs=s["end_pairs"])
+        score_kernel_s=s["sw_kernel_s"], end_kernel_s=s["end_kernel_s"], end_pairs=s["end_pairs"],
+        speculative_pairs=s["speculative_pairs"], final_candidates=s["final_candidates"],
+        cache_hits=s["cache_hits"], rounds=s["rounds"])
 
     if not args.no_recall:
         t = time.perf_counter()

@@ -584,6 +584,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
 
     bool bad = false;
+    int badcode = 0;
     uint32_t best = 0;
 
     for (int s = 0; s < s_max; ++s) {
@@ -648,12 +649,13 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
             const uint8_t* s1 = live1 ? B[1] + min(col, n[1] - 1) : a.dummy;
             return make_int2(*s0, *s1);
         };
+        // columns outside a pair read the sentinel; a code above 19 is
+        // recorded in badcode (reported after the item) and scores as the sentinel
         auto col_in = [&](int2 v, int col) -> uint32_t {
-            int c0 = v.x, c1 = v.y;
-            if (!(act0 && col < n[0])) c0 = kSent;
-            else if (c0 > 19) { bad = true; c0 = kSent; }
-            if (!(act1 && col < n[1])) c1 = kSent;
-            else if (c1 > 19) { bad = true; c1 = kSent; }
+            const bool in0 = act0 && col < n[0], in1 = act1 && col < n[1];
+            badcode = max(badcode, max(in0 ? v.x : 0, in1 ? v.y : 0));
+            const int c0 = in0 ? min(v.x, kSent) : kSent;
+            const int c1 = in1 ? min(v.y, kSent) : kSent;
             return static_cast<uint32_t>(c0 * kColStride) | (static_cast<uint32_t>(c1 * kColStride) << 16);
         };
         auto rd_mask = [&](int col) -> uint32_t {
@@ -683,12 +685,40 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
             ProfWords<W> pa1 = load_prof_at<W>(lp1 + (c >> 16));
             ProfWords<W> pb0, pb1;
 
-            auto cells = [&](const uint32_t (&Hi)[R], uint32_t (&Ho)[R], const ProfWords<W>& w0,
-                             const ProfWords<W>& w1) {
+            // One column step t.  Multi-strip: lane 0 takes the top row from
+            // the boundary feed (a 16-column chunk rotated one lane per step,
+            // reloaded when a chunk ends), and lane 15's bottom row of the
+            // previous step is collected into a 16-column register that is
+            // written to the boundary row every 16 steps.  Each feed register
+            // is rotated before the DPP that overwrites it, so that DPP can
+            // write in place.
+            auto cells = [&](int t, const uint32_t (&Hi)[R], uint32_t (&Ho)[R], const ProfWords<W>& w0,
+                             const ProfWords<W>& w1, bool chunk_last, bool store) {
                 uint32_t Htop, F;
                 if constexpr (kMulti) {
+                    uint32_t nH, nF;
+                    if (chunk_last) {
+                        const uint32_t mk = rd_mask(t + 1 + gl);
+                        nH = static_cast<uint32_t>(nfeed.x) & mk;
+                        nF = static_cast<uint32_t>(nfeed.y) & mk;
+                        nfeed = bnd_raw(t + 1 + kGroup + gl);
+                    } else {
+                        nH = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedH)));
+                        nF = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedF)));
+                    }
                     Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedH), static_cast<int>(Hout)));
                     F = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedF), static_cast<int>(Fout)));
+                    feedH = nH;
+                    feedF = nF;
+                    collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
+                    collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
+                    if (store) {   // lane j holds the bottom row of column t - 31 + j
+                        // keeps the per-lane test inside this rarely taken branch
+                        asm volatile("" ::: "memory");
+                        const int col = t - 31 + gl;
+                        if (col >= 0 && ((wr0 && col < n[0]) || (wr1 && col < n[1])))
+                            bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
+                    }
                 } else {
                     Htop = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Hout)));
                     F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
@@ -719,45 +749,24 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
                 Hout = Ho[R - 1];
                 Fout = F;
             };
-            auto boundary = [&](int t, bool chunk_end) {
-                if constexpr (kMulti) {
-                    if (chunk_end) {
-                        const uint32_t mk = rd_mask(t + 1 + gl);
-                        feedH = static_cast<uint32_t>(nfeed.x) & mk;
-                        feedF = static_cast<uint32_t>(nfeed.y) & mk;
-                        nfeed = bnd_raw(t + 1 + kGroup + gl);
-                    } else {
-                        feedH = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedH)));
-                        feedF = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedF)));
-                    }
-                    collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
-                    collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
-                    if ((t & (kGroup - 1)) == kGroup - 1) {
-                        const int col = t - 2 * (kGroup - 1) + gl;
-                        if (col >= 0 && ((wr0 && col < n[0]) || (wr1 && col < n[1])))
-                            bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
-                    }
-                }
-            };
 
             const int steps = (n_max + kGroup - 1 + 1) & ~1;
 #pragma unroll 1
             for (int t = 0; t < steps; t += 2) {
-                {   // step t (even, never the last step of a 16-column chunk)
+                {   // step t (even: never the last step of a 16-column chunk)
                     const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
                     const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
                     pb0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
                     pb1 = load_prof_at<W>(lp1 + (cn >> 16));
                     __builtin_amdgcn_sched_barrier(0);
-                    cells(HA, HB, pa0, pa1);
-                    boundary(t, false);
+                    cells(t, HA, HB, pa0, pa1, false, (t & (kGroup - 1)) == 0 && t > 0);
                     feedR = feedR2;
                     c = cn;
                 }
                 {   // step t+1
-                    const bool chunk_end = ((t + 2) & (kGroup - 1)) == 0;
+                    const bool chunk_last = ((t + 2) & (kGroup - 1)) == 0;
                     uint32_t feedR2;
-                    if (chunk_end) {
+                    if (chunk_last) {
                         feedR2 = col_in(nfeedR, t + 2 + gl);
                         nfeedR = col_raw(t + 2 + kGroup + gl);
                     } else {
@@ -767,14 +776,16 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
                     pa0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
                     pa1 = load_prof_at<W>(lp1 + (cn >> 16));
                     __builtin_amdgcn_sched_barrier(0);
-                    cells(HB, HA, pb0, pb1);
-                    boundary(t + 1, chunk_end);
+                    cells(t + 1, HB, HA, pb0, pb1, chunk_last, false);
                     feedR = feedR2;
                     c = cn;
                 }
             }
             if constexpr (kMulti) {
-                const int col = (steps - 1) - 2 * (kGroup - 1) + gl;
+                // collect the last step's bottom row and write the final columns
+                collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
+                collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
+                const int col = steps - 31 + gl;
                 if (col >= 0 && ((wr0 && col < n[0]) || (wr1 && col < n[1])))
                     bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
                 __threadfence();
@@ -802,7 +813,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
             }
         }
     }
-    if (bad) atomicOr(a.err, kErrResidue);
+    if (bad || badcode > 19) atomicOr(a.err, kErrResidue);
 }
 
 template <int RMAXT>
