@@ -30,6 +30,33 @@
 #include "cm_internal.h"
 #include "cm_runtime.h"
 
+namespace cmdrv {
+// Device-side compaction of the end/start cells: every row (< live count)
+// whose score exceeds min_score appends (row, end_a, end_b, start_a,
+// start_b); rows arrive in any order (the host sorts them).
+__global__ void k_zero_u32(uint32_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+__global__ void k_end_compact(const int32_t* planes, int64_t stride, const int64_t* n_live, int64_t n,
+                              int32_t min_score, uint32_t* count, int32_t* entries) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t live = n_live ? *n_live : n;
+    if (i >= live || i >= n) return;
+    if (planes[i] > min_score) {
+        const uint32_t k = atomicAdd(count, 1u);
+        int32_t* e = entries + 5 * static_cast<int64_t>(k);
+        e[0] = static_cast<int32_t>(i);
+        e[1] = planes[stride + i];
+        e[2] = planes[2 * stride + i];
+        e[3] = planes[3 * stride + i];
+        e[4] = planes[4 * stride + i];
+    }
+}
+}  // namespace cmdrv
+
+// End and start cells of one pair whose score exceeds mT.
+struct EndRec { int32_t idx, ea, eb, sa, sb; };
+
 struct cm_result {
     std::vector<int32_t> reps;
     std::vector<int64_t> member_offsets;
@@ -145,6 +172,7 @@ struct Aligner {
         hipEvent_t e0 = nullptr, e1 = nullptr, done = nullptr;
         int64_t np = 0;
         int64_t stride = 0;     // distance between output planes (np, or the capacity)
+        int64_t prefix = 0;     // end records copied back with the scores
         bool spans = false;
         double cells = 0;
     } slot[2];
@@ -178,9 +206,48 @@ struct Aligner {
         if (st) (void)hipStreamDestroy(st);
     }
 
+    // Device output of a slot with capacity cap: 5 int32 planes (score,
+    // end_a, end_b, start_a, start_b), the live count (graphs), the end-record
+    // counter and cap end records of 5 int32.  The host copy holds the score
+    // plane, the counter and the first `prefix` records.
+    static size_t dev_ints(int64_t cap) { return static_cast<size_t>(cap) * 10 + 8; }
+    static int64_t prefix_of(int64_t cap) { return std::min<int64_t>(cap, cap / 64 + 4096); }
+    static size_t host_ints(int64_t cap, bool spans) {
+        return spans ? static_cast<size_t>(cap) + 4 + 5 * static_cast<size_t>(prefix_of(cap)) : static_cast<size_t>(cap);
+    }
+
+    // scores of every pair; end and start cells only where the coverage test
+    // can use them (score above mT), compacted on the device
+    cm_status enqueue(int32_t* d_pairs, int64_t n, int64_t cap, const int64_t* d_live, int32_t* dsc, bool spans,
+                      void* h_out) {
+        cm_status s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open,
+                                        p->gap_extend, dsc, nullptr, nullptr, st);
+        if (s != CM_OK) return s;
+        if (!spans)
+            return hipMemcpyAsync(h_out, dsc, static_cast<size_t>(cap) * 4, hipMemcpyDeviceToHost, st) == hipSuccess
+                       ? CM_OK : fail(CM_EDEVICE, "scores download");
+        s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open, p->gap_extend, dsc,
+                            dsc + cap, dsc + 2 * cap, p->mT, st);
+        if (s != CM_OK) return s;
+        s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open, p->gap_extend,
+                             dsc, dsc + cap, dsc + 2 * cap, p->mT, dsc + 3 * cap, dsc + 4 * cap, st);
+        if (s != CM_OK) return s;
+        uint32_t* d_count = reinterpret_cast<uint32_t*>(dsc + 5 * cap + 4);
+        int32_t* d_ent = dsc + 5 * cap + 8;
+        hipLaunchKernelGGL(cmdrv::k_zero_u32, dim3(1), dim3(64), 0, st, d_count);
+        hipLaunchKernelGGL(cmdrv::k_end_compact, dim3(static_cast<unsigned>((cap + 255) / 256)), dim3(256), 0, st,
+                           dsc, cap, d_live, n, p->mT, d_count, d_ent);
+        int32_t* h = static_cast<int32_t*>(h_out);
+        hipError_t e = hipMemcpyAsync(h, dsc, static_cast<size_t>(cap) * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(h + cap, d_count, 16, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h + cap + 4, d_ent, static_cast<size_t>(prefix_of(cap)) * 20, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipGetLastError();
+        return e == hipSuccess ? CM_OK : hip_fail(e, "results download");
+    }
+
     // Enqueue the alignment of np pairs (flat a,b) in slot k.  With spans,
-    // the output holds 5 int32 planes: score, end_a, end_b, start_a, start_b
-    // (start only for scores > mT, else -1).
+    // the pairs scoring above mT also get end and start cells (EndRec).
     cm_status submit(int k, const int32_t* pairs, int64_t np, bool spans) {
         Slot& sl = slot[k];
         sl.np = np;
@@ -193,38 +260,21 @@ struct Aligner {
             cells += static_cast<double>((*len)[pairs[2 * q]]) * (*len)[pairs[2 * q + 1]];
         sl.cells = cells;
         if (ctx->graphs) return submit_graph(k, pairs, np, spans);
-        const size_t pb = static_cast<size_t>(np) * 8, ob = static_cast<size_t>(np) * 4;
+        const size_t pb = static_cast<size_t>(np) * 8;
         cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
         cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
-        if (!d_pairs.ensure(pb) || !d_out.ensure(ob * (spans ? 5 : 1)) || !sl.h_pairs.ensure(pb) ||
-            !sl.h_out.ensure(ob * (spans ? 5 : 1)))
+        if (!d_pairs.ensure(pb) || !d_out.ensure(dev_ints(np) * 4) || !sl.h_pairs.ensure(pb) ||
+            !sl.h_out.ensure(host_ints(np, spans) * 4) || !sl.h_err.ensure(16))
             return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(np));
+        sl.prefix = prefix_of(np);
         std::memcpy(sl.h_pairs.ptr, pairs, pb);
         int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
-        int32_t* dea = dsc + np;
-        int32_t* deb = dea + np;
-        int32_t* dsa = deb + np;
-        int32_t* dsb = dsa + np;
         hipError_t e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
         (void)hipEventRecord(sl.e0, st);
-        // scores of every pair; end and start cells only where the coverage
-        // test can use them (score above mT)
-        cm_status s = cm_sw_score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np,
-                                        p->matrix, p->gap_open, p->gap_extend, dsc, nullptr, nullptr, st);
+        cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr);
         if (s != CM_OK) return s;
-        if (spans) {
-            s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np, nullptr,
-                                p->matrix, p->gap_open, p->gap_extend, dsc, dea, deb, p->mT, st);
-            if (s != CM_OK) return s;
-            s = cm_sw_span_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), np, p->matrix,
-                                 p->gap_open, p->gap_extend, dsc, dea, deb, p->mT, dsa, dsb, st);
-            if (s != CM_OK) return s;
-        }
         (void)hipEventRecord(sl.e1, st);
-        e = hipMemcpyAsync(sl.h_out.ptr, dsc, ob * (spans ? 5 : 1), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(e, "scores download");
-        if (!sl.h_err.ensure(16)) return fail(CM_ENOMEM, "pinned flag");
         e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "flag download");
         (void)hipEventRecord(sl.done, st);
@@ -238,11 +288,12 @@ struct Aligner {
         int64_t cap = 1024;
         while (cap < np) cap *= 2;
         sl.stride = cap;
-        const size_t pb = static_cast<size_t>(cap) * 8, ob = static_cast<size_t>(cap) * 4;
+        sl.prefix = prefix_of(cap);
+        const size_t pb = static_cast<size_t>(cap) * 8;
         cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
         cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
-        if (!d_pairs.ensure(pb) || !d_out.ensure(ob * 5 + 64) || !sl.h_pairs.ensure(pb) || !sl.h_out.ensure(ob * 5) ||
-            !sl.h_err.ensure(16))
+        if (!d_pairs.ensure(pb) || !d_out.ensure(dev_ints(cap) * 4) || !sl.h_pairs.ensure(pb) ||
+            !sl.h_out.ensure(host_ints(cap, true) * 4) || !sl.h_err.ensure(16))
             return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(cap));
         cm_status s = cmrt::reserve(ctx, cap);
         if (s != CM_OK) return s;
@@ -269,16 +320,7 @@ struct Aligner {
             if (e != hipSuccess) { ctx->timer.on = timed; return hip_fail(e, "begin capture"); }
             (void)hipMemcpyAsync(d_live, h_live, 8, hipMemcpyHostToDevice, st);
             (void)hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
-            s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
-                                  p->matrix, p->gap_open, p->gap_extend, dsc, nullptr, nullptr, st);
-            if (s == CM_OK && spans)
-                s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
-                                    p->matrix, p->gap_open, p->gap_extend, dsc, dsc + cap, dsc + 2 * cap, p->mT, st);
-            if (s == CM_OK && spans)
-                s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, static_cast<int32_t*>(d_pairs.ptr), cap, d_live,
-                                     p->matrix, p->gap_open, p->gap_extend, dsc, dsc + cap, dsc + 2 * cap, p->mT,
-                                     dsc + 3 * cap, dsc + 4 * cap, st);
-            (void)hipMemcpyAsync(sl.h_out.ptr, dsc, ob * (spans ? 5 : 1), hipMemcpyDeviceToHost, st);
+            s = enqueue(static_cast<int32_t*>(d_pairs.ptr), cap, cap, d_live, dsc, spans, sl.h_out.ptr);
             (void)hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
@@ -302,10 +344,12 @@ struct Aligner {
         return CM_OK;
     }
 
-    // Wait for slot k and copy its results into out.
-    cm_status wait(int k, std::vector<int32_t>& out) {
+    // Wait for slot k: scores into out, and (with spans) the end records of
+    // the pairs scoring above mT, sorted by pair index, into ends.
+    cm_status wait(int k, std::vector<int32_t>& out, std::vector<EndRec>* ends = nullptr) {
         Slot& sl = slot[k];
-        out.resize(static_cast<size_t>(sl.np) * (sl.spans ? 5 : 1));
+        out.resize(static_cast<size_t>(sl.np));
+        if (ends) ends->clear();
         if (sl.np == 0) return CM_OK;
         hipError_t e = hipEventSynchronize(sl.done);
         if (e != hipSuccess) return hip_fail(e, "alignment batch");
@@ -315,10 +359,21 @@ struct Aligner {
             cm_status s = cm_context_sync(ctx);   // clears the flag and describes it
             return s != CM_OK ? s : fail(CM_ERANGE, "device flagged bad input");
         }
-        const int planes = sl.spans ? 5 : 1;
-        for (int q = 0; q < planes; ++q)
-            std::memcpy(out.data() + q * sl.np, static_cast<const int32_t*>(sl.h_out.ptr) + q * sl.stride,
-                        static_cast<size_t>(sl.np) * 4);
+        const int32_t* h = static_cast<const int32_t*>(sl.h_out.ptr);
+        std::memcpy(out.data(), h, static_cast<size_t>(sl.np) * 4);
+        if (sl.spans && ends) {
+            const int64_t cnt = static_cast<uint32_t>(h[sl.stride]);
+            ends->resize(static_cast<size_t>(cnt));
+            const int64_t head = std::min(cnt, sl.prefix);
+            std::memcpy(ends->data(), h + sl.stride + 4, static_cast<size_t>(head) * 20);
+            if (cnt > head) {   // more records than the prefix copy held
+                const int32_t* d_ent = static_cast<const int32_t*>(ctx->drv[2 * k + 1].ptr) + 5 * sl.stride + 8;
+                e = hipMemcpy(ends->data() + head, d_ent + 5 * head, static_cast<size_t>(cnt - head) * 20,
+                              hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return hip_fail(e, "end records download");
+            }
+            std::sort(ends->begin(), ends->end(), [](const EndRec& a, const EndRec& b) { return a.idx < b.idx; });
+        }
         cmrt::drain_timers(ctx, false);
         stats->t_gpu_s += ms * 1e-3;
         stats->waves += 1;
@@ -711,6 +766,7 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     // are always aligned
     std::vector<uint8_t> keep(total, 1);
     std::vector<int32_t> kept;
+    const std::vector<int32_t>* src = &pairs;
     cm_status s = CM_OK;
     if (screened(CM_STAGE_REP)) {
         std::vector<int32_t> cand;
@@ -735,16 +791,20 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
         kept.reserve(pairs.size());
         for (size_t k = 0; k < total; ++k)
             if (keep[k]) { kept.push_back(pairs[2 * k]); kept.push_back(pairs[2 * k + 1]); }
-    } else {
-        kept = pairs;
+        src = &kept;
     }
     std::vector<int32_t> out;
-    const size_t nk = kept.size() / 2;
-    s = al_.run(kept.data(), static_cast<int64_t>(nk), true, out);
+    std::vector<EndRec> ends;
+    const size_t nk = src->size() / 2;
+    const auto ta = Clock::now();
+    s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
+    if (s != CM_OK) return s;
+    const auto tb = Clock::now();
+    s = al_.wait(0, out, &ends);
     if (s != CM_OK) return s;
     const auto t1 = Clock::now();
     std::vector<uint8_t> bits(total, 0);
-    size_t q = 0;
+    size_t q = 0, qe = 0;
     for (size_t k = 0; k < total; ++k) {
         if (!keep[k]) continue;                 // dropped by the screen: not similar
         const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
@@ -757,8 +817,11 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
         }
         if (sc > p_.mT) {
             ++st_.end_pairs;
-            const int32_t ea = out[nk + q], eb = out[2 * nk + q];
-            const int32_t sa = out[3 * nk + q], sb = out[4 * nk + q];
+            if (qe >= ends.size() || ends[qe].idx != static_cast<int32_t>(q))
+                return fail(CM_EDEVICE, "missing end record for pair %zu", q);
+            const int32_t ea = ends[qe].ea, eb = ends[qe].eb;
+            const int32_t sa = ends[qe].sa, sb = ends[qe].sb;
+            ++qe;
             const int32_t u1 = len_[r1] - (ea - sa + 1);
             const int32_t u2 = len_[r2] - (eb - sb + 1);
             if (u1 < p_.mU) b |= kT21;   // cluster2's rep covers nearly all of rep1
@@ -790,8 +853,10 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     }
     const auto t3 = Clock::now();
     if (log_)
-        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f align %.3f)\n",
-                jobs.size(), total, secs(t0, t1), secs(t1, t2), secs(t2, t3), waves, n_req, t_rep, t_al);
+        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs (prep %.3f submit %.3f wait %.3f) "
+                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f align %.3f)\n",
+                jobs.size(), total, secs(t0, t1), secs(t0, ta), secs(ta, tb), secs(tb, t1), secs(t1, t2),
+                secs(t2, t3), waves, n_req, t_rep, t_al);
     return CM_OK;
 }
 
