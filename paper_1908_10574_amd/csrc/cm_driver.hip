@@ -170,6 +170,8 @@ struct Aligner {
     struct Slot {
         Pinned h_pairs, h_out, h_err;
         hipEvent_t e0 = nullptr, e1 = nullptr, done = nullptr;
+        hipEvent_t scored = nullptr;   // score plane on the host (spans, outside graphs)
+        bool have_scores = false;
         int64_t np = 0;
         int64_t stride = 0;     // distance between output planes (np, or the capacity)
         int64_t prefix = 0;     // end records copied back with the scores
@@ -192,7 +194,7 @@ struct Aligner {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(CM_EDEVICE, "stream");
         for (Slot& sl : slot)
             if (hipEventCreate(&sl.e0) != hipSuccess || hipEventCreate(&sl.e1) != hipSuccess ||
-                hipEventCreate(&sl.done) != hipSuccess)
+                hipEventCreate(&sl.done) != hipSuccess || hipEventCreate(&sl.scored) != hipSuccess)
                 return fail(CM_EDEVICE, "events");
         return CM_OK;
     }
@@ -202,6 +204,7 @@ struct Aligner {
             if (sl.e0) (void)hipEventDestroy(sl.e0);
             if (sl.e1) (void)hipEventDestroy(sl.e1);
             if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.scored) (void)hipEventDestroy(sl.scored);
         }
         if (st) (void)hipStreamDestroy(st);
     }
@@ -219,13 +222,16 @@ struct Aligner {
     // scores of every pair; end and start cells only where the coverage test
     // can use them (score above mT), compacted on the device
     cm_status enqueue(int32_t* d_pairs, int64_t n, int64_t cap, const int64_t* d_live, int32_t* dsc, bool spans,
-                      void* h_out) {
+                      void* h_out, hipEvent_t scored) {
         cm_status s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open,
                                         p->gap_extend, dsc, nullptr, nullptr, st);
         if (s != CM_OK) return s;
-        if (!spans)
-            return hipMemcpyAsync(h_out, dsc, static_cast<size_t>(cap) * 4, hipMemcpyDeviceToHost, st) == hipSuccess
-                       ? CM_OK : fail(CM_EDEVICE, "scores download");
+        int32_t* h = static_cast<int32_t*>(h_out);
+        hipError_t e = hipMemcpyAsync(h, dsc, static_cast<size_t>(cap) * 4, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "scores download");
+        if (!spans) return CM_OK;
+        // the host can process the scores while the end and start passes run
+        if (scored) (void)hipEventRecord(scored, st);
         s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open, p->gap_extend, dsc,
                             dsc + cap, dsc + 2 * cap, p->mT, st);
         if (s != CM_OK) return s;
@@ -237,13 +243,22 @@ struct Aligner {
         hipLaunchKernelGGL(cmdrv::k_zero_u32, dim3(1), dim3(64), 0, st, d_count);
         hipLaunchKernelGGL(cmdrv::k_end_compact, dim3(static_cast<unsigned>((cap + 255) / 256)), dim3(256), 0, st,
                            dsc, cap, d_live, n, p->mT, d_count, d_ent);
-        int32_t* h = static_cast<int32_t*>(h_out);
-        hipError_t e = hipMemcpyAsync(h, dsc, static_cast<size_t>(cap) * 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(h + cap, d_count, 16, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(h + cap, d_count, 16, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(h + cap + 4, d_ent, static_cast<size_t>(prefix_of(cap)) * 20, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipGetLastError();
         return e == hipSuccess ? CM_OK : hip_fail(e, "results download");
+    }
+
+    // Grow slot k's staging for batches up to np pairs now, so that later
+    // submits do not reallocate (a device free would wait for in-flight work).
+    cm_status reserve(int k, int64_t np, bool spans) {
+        Slot& sl = slot[k];
+        const size_t pb = static_cast<size_t>(np) * 8;
+        if (!ctx->drv[2 * k].ensure(pb) || !ctx->drv[2 * k + 1].ensure(dev_ints(np) * 4) || !sl.h_pairs.ensure(pb) ||
+            !sl.h_out.ensure(host_ints(np, spans) * 4) || !sl.h_err.ensure(16))
+            return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(np));
+        return ctx->graphs ? CM_OK : cmrt::reserve(ctx, np);
     }
 
     // Enqueue the alignment of np pairs (flat a,b) in slot k.  With spans,
@@ -272,7 +287,9 @@ struct Aligner {
         hipError_t e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
         (void)hipEventRecord(sl.e0, st);
-        cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr);
+        sl.have_scores = false;
+        cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr,
+                              spans ? sl.scored : nullptr);
         if (s != CM_OK) return s;
         (void)hipEventRecord(sl.e1, st);
         e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
@@ -320,7 +337,7 @@ struct Aligner {
             if (e != hipSuccess) { ctx->timer.on = timed; return hip_fail(e, "begin capture"); }
             (void)hipMemcpyAsync(d_live, h_live, 8, hipMemcpyHostToDevice, st);
             (void)hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
-            s = enqueue(static_cast<int32_t*>(d_pairs.ptr), cap, cap, d_live, dsc, spans, sl.h_out.ptr);
+            s = enqueue(static_cast<int32_t*>(d_pairs.ptr), cap, cap, d_live, dsc, spans, sl.h_out.ptr, nullptr);
             (void)hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
@@ -341,6 +358,21 @@ struct Aligner {
         if (e != hipSuccess) return hip_fail(e, "graph launch");
         (void)hipEventRecord(sl.e1, st);
         (void)hipEventRecord(sl.done, st);
+        (void)hipEventRecord(sl.scored, st);
+        sl.have_scores = false;
+        return CM_OK;
+    }
+
+    // Scores of slot k (submitted with spans) into out, as soon as the score
+    // pass is back; wait() later adds the end records.
+    cm_status wait_scores(int k, std::vector<int32_t>& out) {
+        Slot& sl = slot[k];
+        out.resize(static_cast<size_t>(sl.np));
+        if (sl.np == 0) return CM_OK;
+        hipError_t e = hipEventSynchronize(sl.scored);
+        if (e != hipSuccess) return hip_fail(e, "score pass");
+        std::memcpy(out.data(), sl.h_out.ptr, static_cast<size_t>(sl.np) * 4);
+        sl.have_scores = true;
         return CM_OK;
     }
 
@@ -348,7 +380,7 @@ struct Aligner {
     // the pairs scoring above mT, sorted by pair index, into ends.
     cm_status wait(int k, std::vector<int32_t>& out, std::vector<EndRec>* ends = nullptr) {
         Slot& sl = slot[k];
-        out.resize(static_cast<size_t>(sl.np));
+        if (!sl.have_scores) out.resize(static_cast<size_t>(sl.np));
         if (ends) ends->clear();
         if (sl.np == 0) return CM_OK;
         hipError_t e = hipEventSynchronize(sl.done);
@@ -360,7 +392,8 @@ struct Aligner {
             return s != CM_OK ? s : fail(CM_ERANGE, "device flagged bad input");
         }
         const int32_t* h = static_cast<const int32_t*>(sl.h_out.ptr);
-        std::memcpy(out.data(), h, static_cast<size_t>(sl.np) * 4);
+        if (!sl.have_scores) std::memcpy(out.data(), h, static_cast<size_t>(sl.np) * 4);
+        sl.have_scores = false;
         if (sl.spans && ends) {
             const int64_t cnt = static_cast<uint32_t>(h[sl.stride]);
             ends->resize(static_cast<size_t>(cnt));
@@ -800,34 +833,41 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
     if (s != CM_OK) return s;
     const auto tb = Clock::now();
+    // scores first (the end and start passes are still running), then the
+    // coverage bits of the pairs scoring above mT
+    s = al_.wait_scores(0, out);
+    if (s != CM_OK) return s;
+    std::vector<uint8_t> bits(total, 0);
+    std::vector<size_t> deferred;            // batch index k of the pairs above mT
+    size_t q = 0;
+    for (size_t k = 0; k < total; ++k) {
+        if (!keep[k]) continue;                 // dropped by the screen: not similar
+        const int32_t sc = out[q++];
+        if (sc >= p_.T) {
+            bits[k] = kSim;
+            // similar representative scores may be needed again (exchanges, final stage)
+            cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
+        }
+        if (sc > p_.mT) deferred.push_back(k);
+    }
     s = al_.wait(0, out, &ends);
     if (s != CM_OK) return s;
     const auto t1 = Clock::now();
-    std::vector<uint8_t> bits(total, 0);
-    size_t q = 0, qe = 0;
-    for (size_t k = 0; k < total; ++k) {
-        if (!keep[k]) continue;                 // dropped by the screen: not similar
-        const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
-        const int32_t sc = out[q];
-        uint8_t b = 0;
-        if (sc >= p_.T) {
-            b |= kSim;
-            // similar representative scores may be needed again (exchanges, final stage)
-            cache_.put(unordered_key(r1, r2), sc);
-        }
-        if (sc > p_.mT) {
+    if (deferred.size() != ends.size()) return fail(CM_EDEVICE, "end records: %zu of %zu", ends.size(), deferred.size());
+    q = 0;
+    size_t qe = 0;
+    for (size_t k = 0; k < total && qe < deferred.size(); ++k) {
+        if (!keep[k]) continue;
+        if (k == deferred[qe]) {
+            if (ends[qe].idx != static_cast<int32_t>(q)) return fail(CM_EDEVICE, "missing end record for pair %zu", q);
+            const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
+            const int32_t u1 = len_[r1] - (ends[qe].ea - ends[qe].sa + 1);
+            const int32_t u2 = len_[r2] - (ends[qe].eb - ends[qe].sb + 1);
+            if (u1 < p_.mU) bits[k] |= kT21;   // cluster2's rep covers nearly all of rep1
+            if (u2 < p_.mU) bits[k] |= kT12;
             ++st_.end_pairs;
-            if (qe >= ends.size() || ends[qe].idx != static_cast<int32_t>(q))
-                return fail(CM_EDEVICE, "missing end record for pair %zu", q);
-            const int32_t ea = ends[qe].ea, eb = ends[qe].eb;
-            const int32_t sa = ends[qe].sa, sb = ends[qe].sb;
             ++qe;
-            const int32_t u1 = len_[r1] - (ea - sa + 1);
-            const int32_t u2 = len_[r2] - (eb - sb + 1);
-            if (u1 < p_.mU) b |= kT21;   // cluster2's rep covers nearly all of rep1
-            if (u2 < p_.mU) b |= kT12;
         }
-        bits[k] = b;
         ++q;
     }
     for (MergeJob& job : jobs) simulate(job, bits.data() + job.rep_off);
@@ -873,7 +913,13 @@ cm_status Driver::final_stage(cm_result* res) {
         std::sort(sorted[k].begin(), sorted[k].end());
         for (int32_t x : sorted[k]) of[x].push_back(static_cast<int32_t>(k));
     }
+    // chunks start small so the device starts early, then double up to 2M pairs
     const int64_t kChunk = 1 << 21;
+    int64_t chunk = 1 << 15;
+    for (int k = 0; k < 2; ++k) {
+        cm_status s0 = al_.reserve(k, kChunk + (1 << 16), false);
+        if (s0 != CM_OK) return s0;
+    }
     struct Chunk {
         std::vector<int32_t> gpu;            // pairs sent to the device
         std::vector<int32_t> cx, cy, cs;     // candidates; cs = known score or -1
@@ -978,9 +1024,13 @@ cm_status Driver::final_stage(cm_result* res) {
                 c.gpu.push_back(y);
             }
         }
-        if (static_cast<int64_t>(c.gpu.size() / 2) >= kChunk || static_cast<int64_t>(c.cx.size()) >= 4 * kChunk) {
+        if (static_cast<int64_t>(c.gpu.size() / 2) >= chunk || static_cast<int64_t>(c.cx.size()) >= 4 * kChunk) {
             cm_status s = ship();
             if (s != CM_OK) return s;
+            chunk = std::min<int64_t>(2 * chunk, kChunk);
+            if (log_ && (st_.waves & 15) == 0)
+                fprintf(stderr, "[cm] final: element %d of %d, %lld candidates\n", x, n_,
+                        static_cast<long long>(st_.final_candidates));
         }
     }
     cm_status s = ship();
