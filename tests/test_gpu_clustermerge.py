@@ -206,3 +206,28 @@ def test_graph_replay_matches_eager_20k(cm):
         assert all(r1 == r2 and np.array_equal(m1, m2) for (r1, m1), (r2, m2) in zip(g["clusters"], eager["clusters"]))
     print("graph", g["stats"]["t_total_s"], "eager", eager["stats"]["t_total_s"])
     ctx.close()
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_end_records_beyond_prefix(cm, graphs):
+    """9,000 identical proteins: the first tree level has 4,500 merges whose single
+    representative pair scores above mT, more end records than the copy that returns
+    with the scores holds, so the rest is fetched separately.  Every merge is a full
+    merge: one cluster, n - 1 comparisons, every pair similar."""
+    n = 9000
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 20, size=30).astype(np.uint8)
+    ds = cmgen.from_list([a] * n)
+    assert int(ds.matrix[a, a].sum()) > 166
+    res, off = dev_store(ds)
+    ctx = cm.Context(0)
+    ctx.set_graphs(graphs)
+    g = cm.clustermerge_run(res, off, ds.matrix, max_result_pairs=0, ctx=ctx)
+    judge = ocm.ProteinJudge(ds.residues, ds.offsets, ds.matrix)
+    clusters, st = ocm.bottom_up_merge(n, judge)
+    assert [(c.rep, c.objs) for c in clusters] == [(int(r), list(m)) for r, m in g["clusters"]]
+    assert g["stats"]["rep_comparisons"] == st.rep_comparisons == n - 1
+    assert g["stats"]["full_merges"] == n - 1
+    assert g["stats"]["end_pairs"] == n - 1
+    assert g["stats"]["n_similar_pairs"] == n * (n - 1) // 2
+    ctx.close()
