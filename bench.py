@@ -74,11 +74,63 @@ def cpu_baseline(ds, n_sample, T=120, mT=166, mU=15):
                        f"({len(judge._score)} alignments, {cells:.3e} cells, {dt:.1f} s, single thread)")
 
 
+def sampled_recall(cm, res, off, M, clusters, n, k_sample, seed=7, T=120, chunk=1 << 23):
+    """Pair recall estimated from k_sample elements x drawn uniformly: every
+    (x, y), y != x, is scored on the GPU; truth(x) = {y : score >= T};
+    found(x) = truth(x) restricted to the y sharing a final cluster with x.
+    Ratio estimate sum(found) / sum(truth) with a percentile bootstrap interval."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    xs = np.sort(rng.choice(n, size=k_sample, replace=False)).astype(np.int32)
+    sampled = np.zeros(n, bool)
+    sampled[xs] = True
+    together = {int(x): [] for x in xs}
+    for _, members in clusters:
+        m = np.asarray(members)
+        for x in m[sampled[m]]:
+            together[int(x)].append(m)
+    ys = np.arange(n, dtype=np.int32)
+    truth = np.zeros(k_sample, np.int64)
+    found = np.zeros(k_sample, np.int64)
+    cells = 0.0
+    L = np.diff(np.asarray(off.cpu()) if hasattr(off, "cpu") else off).astype(np.float64)
+    t0 = time.perf_counter()
+    per = max(1, chunk // n)
+    for b in range(0, k_sample, per):
+        xb = xs[b:b + per]
+        pr = np.stack([np.repeat(xb, n), np.tile(ys, len(xb))], 1).astype(np.int32)
+        pr = pr[pr[:, 0] != pr[:, 1]]
+        cells += float((L[pr[:, 0]] * L[pr[:, 1]]).sum())
+        sc = cm.sw_score_batch(res, off, torch.from_numpy(pr).cuda(), M).cpu().numpy()
+        for i, x in enumerate(xb):
+            sel = pr[:, 0] == x
+            yt = pr[sel, 1][sc[sel] >= T]
+            mem = np.unique(np.concatenate(together[int(x)])) if together[int(x)] else np.zeros(0, np.int32)
+            truth[b + i] = len(yt)
+            found[b + i] = int(np.isin(yt, mem).sum())
+    dt = time.perf_counter() - t0
+    est = found.sum() / max(truth.sum(), 1)
+    boot = []
+    for _ in range(2000):
+        idx = rng.integers(0, k_sample, size=k_sample)
+        boot.append(found[idx].sum() / max(truth[idx].sum(), 1))
+    lo, hi = np.percentile(boot, [2.5, 97.5])
+    return dict(recall=float(est), ci95=[float(lo), float(hi)], sampled_elements=int(k_sample),
+                sampled_truth_pairs=int(truth.sum()), sampled_found_pairs=int(found.sum()),
+                sample_s=dt, sample_gcups=cells / dt / 1e9)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["clustermerge-20k", "clustermerge-300k"], default="clustermerge-20k",
+                    help="clustermerge-300k: 300,000 proteins, 25,000 families, lengths clipped to 30-5,000; "
+                         "recall from a sample of elements (use --steps 1 --warmup 0)")
+    ap.add_argument("--recall-sample", type=int, default=256,
+                    help="clustermerge-300k: elements whose pairs with every protein define the recall sample")
     ap.add_argument("--n-seqs", type=int, default=20000)
     ap.add_argument("--n-families", type=int, default=2000)
     ap.add_argument("--throughput-pairs", type=int, default=1000000)
@@ -106,7 +158,14 @@ def main():
     import paper_1908_10574_amd as cm
 
     dev = torch.device("cuda:0")
-    ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families)
+    large = args.workload == "clustermerge-300k"
+    if large:
+        args.n_seqs, args.n_families = 300000, 25000
+        ds = cmgen.clustermerge_large()
+    else:
+        ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families)
+    # the large store reports counts and the set hash only (billions of pairs)
+    cm_kw = dict(max_result_pairs=0) if large else {}
     res = torch.from_numpy(ds.residues).to(dev)
     off = torch.from_numpy(ds.offsets).to(dev)
     M = ds.matrix
@@ -123,13 +182,15 @@ def main():
         del src, dst
 
     for w in range(args.warmup):
-        g = cm.clustermerge_run(res, off, M)
+        g = cm.clustermerge_run(res, off, M, **cm_kw)
         log(f"warmup {w}: {g['stats']['t_total_s']:.2f} s")
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
+    if large:
+        os.environ["CM_LOG"] = "1"          # per-level progress lines
     for k in range(args.steps):
-        g = cm.clustermerge_run(res, off, M)
+        g = cm.clustermerge_run(res, off, M, **cm_kw)
         stats.append(g["stats"])
         log(f"step {k}: {g['stats']['t_total_s']:.2f} s")
     torch.cuda.synchronize()
@@ -146,7 +207,7 @@ def main():
     achieved = opc * k_cells / k_sec
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
                     unit="TOP/s (16-bit packed)" if packed else "TOP/s (int32)",
-                    frac=achieved / peak, traffic=measured_traffic(),
+                    frac=achieved / peak, traffic=None if large else measured_traffic(),
                     kernel=("k_sw_pk (packed 16-bit Smith-Waterman score kernel; saturated pairs re-run in int32)"
                             if packed else "k_sw (int32 Smith-Waterman score kernel)"),
                     ops_per_cell=opc, launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
@@ -158,8 +219,8 @@ def main():
                ms_per_step=1e3 * step_s, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="i32", data="synthetic",
                config=dict(workload=f"clustermerge-{ds.n}: {args.n_families} Zipf(1.2) families, lognormal "
-                                    "lengths median 350 sigma 0.6 clipped 30-2000, T=120 mT=166 mU=15, "
-                                    "gap -11/-1, matrix seed 1917, plain method",
+                                    f"lengths median 350 sigma 0.6 clipped 30-{5000 if large else 2000}, "
+                                    "T=120 mT=166 mU=15, gap -11/-1, matrix seed 1917, plain method",
                            n_seqs=ds.n, residues=int(len(ds.residues))),
                roofline=roofline)
     out["clustermerge"] = dict(
@@ -171,7 +232,13 @@ def main():
         speculative_pairs=s["speculative_pairs"], final_candidates=s["final_candidates"],
         cache_hits=s["cache_hits"], rounds=s["rounds"])
 
-    if not args.no_recall:
+    plain_clusters = g["clusters"]
+    if not args.no_recall and large:
+        out["clustermerge"]["recall_sample"] = sampled_recall(cm, res, off, M, plain_clusters, ds.n,
+                                                              args.recall_sample)
+        out["clustermerge"]["recall"] = out["clustermerge"]["recall_sample"]["recall"]
+        log(f"sampled recall {out['clustermerge']['recall']:.5f}")
+    elif not args.no_recall:
         t = time.perf_counter()
         truth, tcells = cm.allvsall_count(res, off, M)
         tt = time.perf_counter() - t
@@ -187,8 +254,9 @@ def main():
         scr, tau, info = screen_train.train_on_dataset(tr, epochs=args.screen_epochs, seed=1,
                                                        keep_recall=args.screen_keep, log=log)
         del tr
-        kw = dict(screen=scr, screen_tau=tau, screen_min_product=args.screen_min_product)
-        g = cm.clustermerge_run(res, off, M, **kw)   # warm
+        kw = dict(screen=scr, screen_tau=tau, screen_min_product=args.screen_min_product, **cm_kw)
+        if not large:
+            g = cm.clustermerge_run(res, off, M, **kw)   # warm
         sstats = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -207,7 +275,12 @@ def main():
                                    f"{args.screen_pairs} pairs (half within-family), labels from the GPU "
                                    f"Smith-Waterman (score >= 120), {args.screen_epochs} epochs, batch 4096, "
                                    f"Adam lr 1e-3", gen_s=gen_s, **info))
-        if "truth_pairs" in out["clustermerge"]:
+        if large and not args.no_recall:
+            rs = sampled_recall(cm, res, off, M, g["clusters"], ds.n, args.recall_sample)
+            scr_out["recall_sample"] = rs
+            scr_out["recall"] = rs["recall"]
+            scr_out["recall_vs_plain"] = rs["recall"] / max(out["clustermerge"]["recall"], 1e-12)
+        elif "truth_pairs" in out["clustermerge"]:
             truth = out["clustermerge"]["truth_pairs"]
             scr_out["recall"] = ss["n_similar_pairs"] / max(truth, 1)
             scr_out["recall_vs_plain"] = scr_out["recall"] / out["clustermerge"]["recall"]
