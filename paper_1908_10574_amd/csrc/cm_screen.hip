@@ -237,12 +237,11 @@ cm_status cm_screen_infer(const cm_screen* s_, const uint16_t* feat, const int32
     cm_screen* s = const_cast<cm_screen*>(s_);
     if (!s || !feat || !pairs || !logits || n_pairs < 0) return fail(CM_EINVAL, "bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t chunk = 1 << 20;
+    const int64_t chunk = 1 << 24;
     for (int64_t first = 0; first < n_pairs; first += chunk) {
         const int n = static_cast<int>(n_pairs - first < chunk ? n_pairs - first : chunk);
-        const int mb = static_cast<int>(round_up(n, 32));
         cms::FwdArgs a = fwd_args(s, feat, pairs + 2 * first, n, logits + first);
-        cm_status r = chk(cms::launch_fwd(a, mb, st), "screen inference");
+        cm_status r = chk(cms::launch_infer(a, st), "screen inference");
         if (r != CM_OK) return r;
     }
     return CM_OK;

@@ -53,6 +53,8 @@ struct GemmArgs {
 hipError_t launch_kmer(const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs, uint16_t* feat, uint32_t* err,
                        hipStream_t s);
 hipError_t launch_fwd(const FwdArgs& a, int mb, hipStream_t s);
+// inference only (logits): 128 pairs per block, any n
+hipError_t launch_infer(const FwdArgs& a, hipStream_t s);
 hipError_t launch_pair_xt(const uint16_t* feat, const int32_t* pairs, int n, int mb, uint16_t* xt, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& g, int epi, hipStream_t s);
 hipError_t launch_backward_tail(const float* z, const uint8_t* y, int n, int mb, const uint16_t* h2,

@@ -194,6 +194,140 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(FwdArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// inference forward: 128 pairs per block, 8 waves, each wave owns 64 hidden
+// units for all 128 rows, so every weight fragment loaded from L2 feeds 8
+// row tiles (4x the reuse of k_mlp_fwd).  Same rounding points as k_mlp_fwd
+// (X, h1, h2 rounded to bf16; fp32 accumulation), no training outputs.
+// The pair input is built 32 columns at a time into a double-buffered LDS
+// tile, its feature loads issued one step ahead.
+// ---------------------------------------------------------------------------
+constexpr int kIR = 128;           // pairs per block
+constexpr int kIW = 8;             // waves per block
+constexpr int kIK = 32;            // layer-1 K step
+
+__global__ __launch_bounds__(512) void k_mlp_infer(FwdArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[2][kIR][kIK + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t h1s[kIR][kHidden + 8];
+    __shared__ float zpart[kIW][kIR];
+    __shared__ int pa[kIR], pb[kIR];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t m0 = static_cast<int64_t>(blockIdx.x) * kIR;
+    if (tid < kIR) {
+        const int64_t m = m0 + tid;
+        pa[tid] = m < a.n ? a.pairs[2 * m] : 0;
+        pb[tid] = m < a.n ? a.pairs[2 * m + 1] : 0;
+    }
+    __syncthreads();
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int nw = wave * 64;                        // this wave's first hidden unit
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // ---- layer 1: X [128 x 2048] . W1^T
+    const int br = tid >> 2, bk = (tid & 3) * 8;     // builder: row, 8 columns of the step
+    const uint16_t* fa = a.feat + static_cast<int64_t>(pa[br]) * kBuckets;
+    const uint16_t* fb = a.feat + static_cast<int64_t>(pb[br]) * kBuckets;
+    bf16x8 va = ld8(fa + bk), vb = ld8(fb + bk);
+    constexpr int kSteps = kIn / kIK;
+    for (int s = 0; s < kSteps; ++s) {
+        const int kc = s * kIK;
+        bf16x8 b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = ld8(a.w1 + static_cast<int64_t>(nw + 16 * c + r) * kIn + kc + kq);
+        {
+            const bool diff = kc < kBuckets;
+            uint16_t o[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const float x = static_cast<float>(va[j]), y = static_cast<float>(vb[j]);
+                o[j] = f2bf(diff ? fabsf(x - y) : x * y);
+            }
+            uint4 pk;
+            pk.x = static_cast<uint32_t>(o[0]) | (static_cast<uint32_t>(o[1]) << 16);
+            pk.y = static_cast<uint32_t>(o[2]) | (static_cast<uint32_t>(o[3]) << 16);
+            pk.z = static_cast<uint32_t>(o[4]) | (static_cast<uint32_t>(o[5]) << 16);
+            pk.w = static_cast<uint32_t>(o[6]) | (static_cast<uint32_t>(o[7]) << 16);
+            *reinterpret_cast<uint4*>(&xs[s & 1][br][bk]) = pk;
+            if (s + 1 < kSteps) {
+                const int kk = (kc + kIK + bk) & (kBuckets - 1);
+                va = ld8(fa + kk);
+                vb = ld8(fb + kk);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&xs[s & 1][16 * t + r][kq]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t][c] = mfma(av, b[c], acc[t][c]);
+        }
+    }
+    // epilogue 1: h1 = bf16(relu(acc + b1)) -> LDS
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int n = nw + 16 * c + r;
+        const float bias = a.b1[n];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h1s[16 * t + 4 * (lane >> 4) + q][n] = f2bf(fmaxf(acc[t][c][q] + bias, 0.f));
+            acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    __syncthreads();
+
+    // ---- layer 2: h1 [128 x 512] . W2^T
+#pragma unroll 2
+    for (int ks = 0; ks < kHidden; ks += 32) {
+        bf16x8 b[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = ld8(a.w2 + static_cast<int64_t>(nw + 16 * c + r) * kHidden + ks + kq);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(&h1s[16 * t + r][ks + kq]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[t][c] = mfma(av, b[c], acc[t][c]);
+        }
+    }
+    // epilogue 2: h2 = bf16(relu(acc + b2)); partial logit over this wave's units
+    float zp[8][4];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) zp[t][q] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int n = nw + 16 * c + r;
+        const float bias = a.b2[n];
+        const float w3 = bf2f(a.w3[n]);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zp[t][q] += bf2f(f2bf(fmaxf(acc[t][c][q] + bias, 0.f))) * w3;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float v = zp[t][q];
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o, 16);
+            if (r == 0) zpart[wave][16 * t + 4 * (lane >> 4) + q] = v;
+        }
+    __syncthreads();
+    if (tid < kIR) {
+        const int64_t m = m0 + tid;
+        float z = a.b3[0];
+#pragma unroll
+        for (int w = 0; w < kIW; ++w) z += zpart[w][tid];
+        if (m < a.n) a.z[m] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // X transposed [2048][ld] for the layer-1 weight gradient (training only)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_pair_xt(const uint16_t* feat, const int32_t* pairs, int n, int ld,
@@ -368,6 +502,11 @@ hipError_t launch_kmer(const uint8_t* seqs, const int64_t* offsets, int32_t n_se
 }
 hipError_t launch_fwd(const FwdArgs& a, int mb, hipStream_t s) {
     hipLaunchKernelGGL(k_mlp_fwd, dim3(mb / kRows), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_infer(const FwdArgs& a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_infer, dim3(static_cast<unsigned>((a.n + kIR - 1) / kIR)), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_pair_xt(const uint16_t* feat, const int32_t* pairs, int n, int mb, uint16_t* xt, hipStream_t s) {
