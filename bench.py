@@ -202,14 +202,16 @@ def main():
     k_launch = sum(x["sw_launches"] for x in stats)
     k_sec = sum(x["sw_kernel_s"] for x in stats)
     k_cells = sum(x["aligned_cells"] for x in stats)
-    packed = ctx.get_plan(0)[0] == 1
+    packed = ctx.get_plan(0)[0] >= 1         # packed 16-bit kernels (two-profile or shared-query)
     opc, peak = (PK_OPS_PER_CELL, PEAK_PK16_OPS) if packed else (OPS_PER_CELL, PEAK_INT32_OPS)
     achieved = opc * k_cells / k_sec
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=peak / 1e12,
                     unit="TOP/s (16-bit packed)" if packed else "TOP/s (int32)",
                     frac=achieved / peak, traffic=None if large else measured_traffic(),
-                    kernel=("k_sw_pk (packed 16-bit Smith-Waterman score kernel; saturated pairs re-run in int32)"
-                            if packed else "k_sw (int32 Smith-Waterman score kernel)"),
+                    kernel=({1: "k_sw_pk (packed 16-bit Smith-Waterman score kernel; saturated pairs re-run in int32)",
+                             2: "k_sw_pkq + k_sw_pk (packed 16-bit Smith-Waterman score kernels: items of eight pairs "
+                                "sharing a query, then the rest; saturated pairs re-run in int32)"}
+                            .get(ctx.get_plan(0)[0], "k_sw (int32 Smith-Waterman score kernel)")),
                     ops_per_cell=opc, launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
                     ops_per_launch=opc * k_cells / max(k_launch, 1),
                     cell_rate_gcups=k_cells / k_sec / 1e9,

@@ -82,18 +82,22 @@ cm_status cm_context_set_timing(cm_context* ctx, int on);
 cm_status cm_context_set_graphs(cm_context* ctx, int on);
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
 
-/* Launch plan of the alignment kernels, per pass: the kernel (packed = 1: the
- * packed 16-bit kernel, two pairs per register, score pass only, with pairs
- * whose score reaches 32767 recomputed by the int32 kernel; packed = 0: the
- * int32 kernel), the most query rows a lane holds (int32: 8, 12 or 16; packed:
- * 4 or 8; strips are 16 x that many rows) and the persistent blocks per CU
- * (1 .. occupancy limit).  Results never depend on the plan.  A context starts
- * from (packed, 8, occupancy limit) for the score pass and (int32, 16,
- * occupancy limit) for the others and, when the environment variable
- * CM_AUTOTUNE_CACHE names a plan file written by cm_plan_save for the same GPU
- * architecture and HIP runtime, from the plans recorded there (a missing,
- * foreign or corrupt file is ignored).  cm_plan_set fails with CM_EINVAL on a
- * plan that is not valid for the pass. */
+/* Launch plan of the alignment kernels, per pass: the kernel (packed = 2: the
+ * score pass groups pairs by query and runs items of eight pairs sharing one
+ * query on the shared-query packed 16-bit kernel (up to 32 rows per lane),
+ * the rest on the two-profile packed kernel; packed = 1: the two-profile
+ * packed 16-bit kernel for every pair (two pairs per register); packed = 0: the
+ * int32 kernel.  Packed plans serve the score pass only, and pairs whose
+ * packed score reaches 32767 are recomputed by the int32 kernel), the most
+ * query rows a lane holds (int32: 8, 12 or 16; packed: 4 or 8; shared-query:
+ * 32; strips are 16 x that many rows) and the persistent blocks per CU (1 ..
+ * occupancy limit).  Results never depend on the plan.  A context starts from
+ * (2, 32, occupancy limit) for the score pass and (0, 16, occupancy limit) for
+ * the others and, when the environment variable CM_AUTOTUNE_CACHE names a plan
+ * file written by cm_plan_save for the same GPU architecture and HIP runtime,
+ * from the plans recorded there (a missing, foreign or corrupt file is
+ * ignored).  cm_plan_set fails with CM_EINVAL on a plan that is not valid for
+ * the pass. */
 cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t* rmax, int32_t* blocks_per_cu,
                       int32_t* max_blocks_per_cu);
 cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, int32_t blocks_per_cu);
@@ -102,7 +106,7 @@ cm_status cm_plan_load(cm_context* ctx, const char* path);
 /* Autotuner: times every candidate plan of `pass` (CM_PASS_SCORE or
  * CM_PASS_SCORE_END) on the given pair sample (device pointers as in
  * cm_sw_score_batch), fails with CM_EDEVICE if two candidates disagree on any
- * output, and keeps the fastest.  table (host, nullable) receives up to 16 rows
+ * output, and keeps the fastest.  table (host, nullable) receives up to 32 rows
  * of (packed, rmax, blocks_per_cu, milliseconds); *n_rows their count.
  * Synchronous. */
 cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,

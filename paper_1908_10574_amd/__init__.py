@@ -168,7 +168,7 @@ class Context:
         offsets = _dev(offsets, torch.int64, "offsets")
         pairs = _dev(pairs, torch.int32, "pairs")
         torch.cuda.current_stream().synchronize()
-        tab = (ctypes.c_double * 64)()
+        tab = (ctypes.c_double * 128)()
         n = _i32()
         m = _matrix_host(matrix)
         _check(_lib.cm_autotune(self.handle, residues.data_ptr() if residues.numel() else None,

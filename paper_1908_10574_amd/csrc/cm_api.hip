@@ -71,6 +71,89 @@ cm_status check_gaps(int32_t go, int32_t ge) {
     return CM_OK;
 }
 
+// temp bytes for the shared-query plan's sort, scan and selects over n pairs
+static size_t plan_q_temp(int64_t n) {
+    size_t t0 = 0, t1 = 0, t2 = 0;
+    const int ni = static_cast<int>(n);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t0, static_cast<uint64_t*>(nullptr), static_cast<uint64_t*>(nullptr),
+                                             static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr), ni, 0, 64);
+    (void)hipcub::DeviceScan::InclusiveScan(nullptr, t1, static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                                            hipcub::Max(), ni);
+    (void)hipcub::DeviceSelect::Flagged(nullptr, t2, static_cast<int32_t*>(nullptr), static_cast<uint8_t*>(nullptr),
+                                        static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr), ni);
+    size_t t3 = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, t3, static_cast<uint32_t*>(nullptr), static_cast<uint32_t*>(nullptr),
+                                             static_cast<int32_t*>(nullptr), static_cast<int32_t*>(nullptr), ni, 0, 32);
+    return std::max(std::max(t0, t3), std::max(t1, t2));
+}
+
+static bool ensure_plan_q(cm_context* ctx, int64_t n) {
+    const size_t m = static_cast<size_t>(n);
+    return ctx->keys.ensure(m * 8) && ctx->keys_alt.ensure(m * 8) && ctx->vals.ensure(m * 4) &&
+           ctx->vals_alt.ensure(m * 4) && ctx->q_start.ensure(m * 4) && ctx->q_len.ensure(m * 4) &&
+           ctx->q_flags.ensure(m * 2) && ctx->q_lists.ensure(m * 12) && ctx->over.ensure(m * 4) &&
+           ctx->sort_tmp.ensure(plan_q_temp(n));
+}
+
+// Shared-query plan and launches of the score pass (plan kind 2).
+static cm_status run_pass_q(cm_context* ctx, cmk::SwArgs& a, hipStream_t st, int& timer_pair) {
+    const int64_t n = a.n_pairs;
+    if (!ensure_plan_q(ctx, n)) return fail(CM_ENOMEM, "cannot allocate the shared-query plan for %lld pairs",
+                                            static_cast<long long>(n));
+    const int ni = static_cast<int>(n);
+    uint64_t* keys = static_cast<uint64_t*>(ctx->keys.ptr);
+    uint64_t* keys_s = static_cast<uint64_t*>(ctx->keys_alt.ptr);
+    int32_t* vals = static_cast<int32_t*>(ctx->vals.ptr);
+    int32_t* vals_s = static_cast<int32_t*>(ctx->vals_alt.ptr);
+    int32_t* start = static_cast<int32_t*>(ctx->q_start.ptr);
+    int32_t* len = static_cast<int32_t*>(ctx->q_len.ptr);
+    uint8_t* fa = static_cast<uint8_t*>(ctx->q_flags.ptr);
+    uint8_t* fb = fa + n;
+    int32_t* list_a = static_cast<int32_t*>(ctx->q_lists.ptr);
+    int32_t* list_b = list_a + n;
+    cmk::Counters* ctr = ctx->counters;
+    size_t tmp = ctx->sort_tmp.cap;
+    hipError_t e = cmk::launch_plan_q(a, keys, vals, st);
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(ctx->sort_tmp.ptr, tmp, keys, keys_s, vals, vals_s, ni, 0, 64, st);
+    if (e == hipSuccess) e = cmk::launch_runs_q(keys_s, n, &ctr->n_work, len, st);
+    tmp = ctx->sort_tmp.cap;
+    if (e == hipSuccess) e = hipcub::DeviceScan::InclusiveScan(ctx->sort_tmp.ptr, tmp, len, start, hipcub::Max(), ni, st);
+    if (e == hipSuccess) e = cmk::launch_flags_q(keys_s, start, n, &ctr->n_work, len, fa, fb, st);
+    tmp = ctx->sort_tmp.cap;
+    if (e == hipSuccess)
+        e = hipcub::DeviceSelect::Flagged(ctx->sort_tmp.ptr, tmp, vals_s, fa, list_a, &ctr->n_sel[0], ni, st);
+    tmp = ctx->sort_tmp.cap;
+    if (e == hipSuccess)
+        e = hipcub::DeviceSelect::Flagged(ctx->sort_tmp.ptr, tmp, vals_s, fb, list_b, &ctr->n_sel[1], ni, st);
+    // the rest, sorted by the two-profile kernel's own shape keys so that the
+    // pairs of an item have like shapes (start / len are free again)
+    cmk::SwArgs bb = a;
+    bb.rmax = cmk::kRMaxChoicePk[cmk::kNumRMaxPk - 1];
+    uint32_t* kb = reinterpret_cast<uint32_t*>(start);
+    uint32_t* kb_s = reinterpret_cast<uint32_t*>(len);
+    int32_t* list_b_s = list_b + n;
+    if (e == hipSuccess) e = cmk::launch_keys_list(bb, list_b, &ctr->n_sel[1], n, kb, st);
+    tmp = ctx->sort_tmp.cap;
+    if (e == hipSuccess)
+        e = hipcub::DeviceRadixSort::SortPairs(ctx->sort_tmp.ptr, tmp, kb, kb_s, list_b, list_b_s, ni, 0, 32, st);
+    if (e != hipSuccess) return hip_fail(e, "shared-query plan");
+    cmk::SwArgs aa = a;
+    aa.keys = nullptr; aa.order = list_a; aa.n_work_ptr = &ctr->n_sel[0]; aa.ticket = &ctr->ticket;
+    aa.rmax = cmk::kRMaxQ;
+    bb.keys = kb_s; bb.order = list_b_s; bb.n_work_ptr = &ctr->n_sel[1]; bb.ticket = &ctr->ticket_b;
+    KernelTimer& kt = ctx->timer;
+    if (timer_pair >= 0) (void)hipEventRecord(kt.pool[2 * timer_pair], st);
+    e = cmk::launch_sw_pkq(aa, bb, ctx->n_cu * ctx->plan[CM_PASS_SCORE].blocks_per_cu,
+                           ctx->n_cu * ctx->occ_pk[cmk::kNumRMaxPk - 1], ctx->n_cu * ctx->occ_over, st);
+    if (e != hipSuccess) return hip_fail(e, "alignment launch");
+    if (timer_pair >= 0) {
+        (void)hipEventRecord(kt.pool[2 * timer_pair + 1], st);
+        kt.pending.emplace_back(CM_PASS_SCORE, timer_pair);
+    }
+    return CM_OK;
+}
+
 // plan -> sort -> persistent sweep for one pass
 cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st) {
     if (a.n_pairs <= 0) return CM_OK;
@@ -105,6 +188,22 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
     a.bnd = static_cast<int2*>(ctx->bnd.ptr);
     a.bnd_stride = ctx->bnd_stride;
     a.zero = 0;
+    if (packed && plan.packed == 2) {
+        a.over = static_cast<int32_t*>(ctx->over.ptr);
+        int timer_pair = -1;
+        KernelTimer& kt = ctx->timer;
+        if (kt.on) {
+            if (kt.next * 2 + 2 > kt.pool.size()) {
+                hipEvent_t b, c;
+                if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&c) != hipSuccess)
+                    return fail(CM_EDEVICE, "timing events");
+                kt.pool.push_back(b);
+                kt.pool.push_back(c);
+            }
+            timer_pair = static_cast<int>(kt.next++);
+        }
+        return run_pass_q(ctx, a, st, timer_pair);
+    }
     e = cmk::launch_plan(a, pass, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<int32_t*>(ctx->vals.ptr), st);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     e = hipcub::DeviceRadixSort::SortPairs(
@@ -157,6 +256,7 @@ void drain_timers(cm_context* ctx, bool blocking) {
 
 int plan_limit(const cm_context* ctx, int pass, int packed, int rmax) {
     if (pass < 0 || pass > 2) return 0;
+    if (packed == 2) return (pass == CM_PASS_SCORE && rmax == cmk::kRMaxQ) ? ctx->occ_pkq : 0;
     if (packed) {
         if (pass != CM_PASS_SCORE) return 0;
         for (int q = 0; q < cmk::kNumRMaxPk; ++q)
@@ -177,9 +277,9 @@ cm_status load_plans(cm_context* ctx, const char* path) {
     int rt, pass, packed, rmax, bpc, used = 0;
     while (fscanf(f, "%63s %d %d %d %d %d", arch, &rt, &pass, &packed, &rmax, &bpc) == 6) {
         if (std::strcmp(arch, ctx->arch) != 0 || rt != ctx->runtime_version) continue;
-        const int lim = plan_limit(ctx, pass, packed != 0, rmax);
+        const int lim = plan_limit(ctx, pass, packed, rmax);
         if (lim < 1 || bpc < 1 || bpc > lim) continue;
-        ctx->plan[pass].packed = packed != 0;
+        ctx->plan[pass].packed = packed;
         ctx->plan[pass].rmax = rmax;
         ctx->plan[pass].blocks_per_cu = bpc;
         ++used;
@@ -210,6 +310,8 @@ cm_status reserve(cm_context* ctx, int64_t n) {
         nullptr);
     if (e != hipSuccess) return hip_fail(e, "sort size query");
     if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
+    if (ctx->plan[CM_PASS_SCORE].packed == 2 && !ensure_plan_q(ctx, n))
+        return fail(CM_ENOMEM, "cannot allocate the shared-query plan");
     return CM_OK;
 }
 
@@ -363,10 +465,13 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     }
     ctx->occ_over = cmk::sw_over_blocks_per_cu();
     gmax = ctx->occ_over > gmax ? ctx->occ_over : gmax;
-    // the score pass defaults to the packed kernel with up to 8 rows per lane
-    ctx->plan[CM_PASS_SCORE].packed = 1;
-    ctx->plan[CM_PASS_SCORE].rmax = cmk::kRMaxChoicePk[cmk::kNumRMaxPk - 1];
-    ctx->plan[CM_PASS_SCORE].blocks_per_cu = ctx->occ_pk[cmk::kNumRMaxPk - 1];
+    ctx->occ_pkq = cmk::sw_pkq_blocks_per_cu();
+    gmax = ctx->occ_pkq > gmax ? ctx->occ_pkq : gmax;
+    // the score pass defaults to the shared-query packed kernel (items of one
+    // query, up to 32 rows per lane; the rest on the two-profile packed kernel)
+    ctx->plan[CM_PASS_SCORE].packed = 2;
+    ctx->plan[CM_PASS_SCORE].rmax = cmk::kRMaxQ;
+    ctx->plan[CM_PASS_SCORE].blocks_per_cu = ctx->occ_pkq;
     gmax *= ctx->n_cu;
     void* small = nullptr;
     e = hipMalloc(&small, 4096);
@@ -403,6 +508,10 @@ void cm_context_destroy(cm_context* ctx) {
     ctx->sort_tmp.release();
     ctx->bnd.release();
     ctx->over.release();
+    ctx->q_start.release();
+    ctx->q_len.release();
+    ctx->q_flags.release();
+    ctx->q_lists.release();
     ctx->extra_release();
     for (hipEvent_t ev : ctx->timer.pool) (void)hipEventDestroy(ev);
     if (ctx->small) (void)hipFree(ctx->small);
@@ -421,6 +530,7 @@ cm_status cm_context_sync(cm_context* ctx) {
     if (flag) {
         const uint32_t zero = 0;
         (void)hipMemcpy(ctx->err_flag, &zero, sizeof(zero), hipMemcpyHostToDevice);
+        if (flag & cmk::kErrPlan) return fail(CM_EDEVICE, "internal error: an item's pairs do not share its query");
         return fail(CM_ERANGE, "device flagged bad input:%s%s%s%s",
                     (flag & cmk::kErrResidue) ? " residue>=20" : "",
                     (flag & cmk::kErrIndex) ? " index out of range" : "",
@@ -464,13 +574,16 @@ cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t*
 
 cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, int32_t blocks_per_cu) {
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
-    if (packed && pass != CM_PASS_SCORE) return fail(CM_EINVAL, "the packed kernel serves the score pass only");
-    const int lim = plan_limit(ctx, pass, packed != 0, rmax);
-    if (lim < 1) return fail(CM_EINVAL, packed ? "packed rmax must be 4 or 8" : "rmax must be 8, 12 or 16");
+    if (packed < 0 || packed > 2) return fail(CM_EINVAL, "packed must be 0, 1 or 2");
+    if (packed && pass != CM_PASS_SCORE) return fail(CM_EINVAL, "the packed kernels serve the score pass only");
+    const int lim = plan_limit(ctx, pass, packed, rmax);
+    if (lim < 1)
+        return fail(CM_EINVAL, packed == 2 ? "shared-query rmax must be 32"
+                                           : (packed ? "packed rmax must be 4 or 8" : "rmax must be 8, 12 or 16"));
     if (blocks_per_cu < 1 || blocks_per_cu > lim)
         return fail(CM_EINVAL, "blocks_per_cu must be in [1, %d]", lim);
     drain_timers(ctx, true);
-    ctx->plan[pass].packed = packed != 0;
+    ctx->plan[pass].packed = packed;
     ctx->plan[pass].rmax = rmax;
     ctx->plan[pass].blocks_per_cu = blocks_per_cu;
     return CM_OK;

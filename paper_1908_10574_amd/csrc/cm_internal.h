@@ -20,9 +20,12 @@ constexpr int kPairsPerWavePk = 8;
 constexpr int kNumRMaxPk = 2;
 constexpr int kRMaxChoicePk[kNumRMaxPk] = {4, 8};
 constexpr int kPkSaturated = 32767; // a packed score this high may have saturated
+// shared-query packed kernel: the eight pairs of a wavefront share their query,
+// so one LDS profile serves the wavefront and a lane can hold up to 32 rows
+constexpr int kRMaxQ = 32;
 constexpr int kMatStride = 24;      // bytes per row of the int8 matrix in LDS
 // query-profile bytes per row slot: R rows padded to 4, 8 or 16 bytes
-constexpr int prof_row_bytes(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : 16); }
+constexpr int prof_row_bytes(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32)); }
 constexpr uint32_t kSkipKey = 0xffffffffu;
 
 // Error bits raised by kernels (reported by cm_context_sync).
@@ -30,6 +33,7 @@ constexpr uint32_t kErrResidue = 1u;     // residue code >= 20
 constexpr uint32_t kErrIndex = 2u;       // pair index outside [0, n_seqs)
 constexpr uint32_t kErrLength = 4u;      // sequence longer than CM_MAX_LEN
 constexpr uint32_t kErrCell = 8u;        // span input end cell outside its sequence
+constexpr uint32_t kErrPlan = 16u;       // internal: an item's pairs do not share the shape the plan promised
 
 // Counters block in device memory.
 struct Counters {
@@ -37,7 +41,9 @@ struct Counters {
     int32_t ticket;      // persistent-queue ticket
     int32_t n_over;      // pairs the packed kernel handed to the int32 kernel
     int32_t ticket_over; // ticket of the int32 re-run over those pairs
-    int32_t pad[12];
+    int32_t n_sel[2];    // shared-query plan: pairs in full same-query items / the rest
+    int32_t ticket_b;    // ticket of the second packed launch (the rest)
+    int32_t pad[9];
 };
 
 struct SwArgs {
@@ -55,6 +61,8 @@ struct SwArgs {
     int32_t end_filter;         // score+end pass: only pairs whose known score > min_score
     uint32_t go_pk, ge_pk;      // packed kernel: -gap_open, -gap_extend (capped at 65535) in both halves
     int32_t* over;              // packed kernel: indices of saturated pairs (capacity n_pairs)
+    const int32_t* n_work_ptr;  // packed kernels: work count (null: ctr->n_work)
+    int32_t* ticket;            // packed kernels: ticket counter (null: ctr->ticket)
     const uint32_t* keys;       // sorted plan keys (R, strips, columns)
     const int32_t* order;       // pair index per sorted position
     Counters* ctr;
@@ -81,5 +89,24 @@ int sw_blocks_per_cu(Pass pass, int rmax);
 hipError_t launch_sw_pk(const SwArgs& a, int grid, int grid_over, hipStream_t s);   // uses a.rmax
 int sw_pk_blocks_per_cu(int rmax);
 int sw_over_blocks_per_cu();
+int sw_pkq_blocks_per_cu();
+
+// Shared-query plan (score pass): 64-bit keys (rows-per-lane class, strips,
+// query, columns), sorted; then every run of pairs with the same query is cut
+// into full items of eight (list A, the shared-query kernel, when the item's
+// subject lengths are close) and the rest (list B, the two-profile packed
+// kernel, re-sorted by its own shape keys).
+hipError_t launch_plan_q(const SwArgs& a, uint64_t* keys, int32_t* vals, hipStream_t s);
+hipError_t launch_runs_q(const uint64_t* keys_sorted, int64_t n, const int32_t* n_work, int32_t* start_in,
+                         hipStream_t s);
+hipError_t launch_flags_q(const uint64_t* keys_sorted, const int32_t* start, int64_t n, const int32_t* n_work,
+                          int32_t* run_len, uint8_t* flag_a, uint8_t* flag_b, hipStream_t s);
+// two-profile shape keys (a.rmax) of the pairs of a list, skip keys past *count
+hipError_t launch_keys_list(const SwArgs& a, const int32_t* list, const int32_t* count, int64_t n, uint32_t* keys,
+                            hipStream_t s);
+// list A on the shared-query kernel, list B (sorted by its shape keys) on the
+// two-profile kernel, then the int32 re-run
+hipError_t launch_sw_pkq(const SwArgs& a_list, const SwArgs& b_list, int grid, int grid_b, int grid_over,
+                         hipStream_t s);
 
 }  // namespace cmk

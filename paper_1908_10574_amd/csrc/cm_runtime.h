@@ -44,10 +44,13 @@ struct cm_context {
     // score pass only, or int32), rows-per-lane limit and persistent blocks per
     // CU; occ = occupancy limit per (pass, rmax choice), occ_pk per packed rmax
     // choice, occ_over of the int32 re-run of saturated packed pairs
+    // packed: 0 int32 kernel, 1 two-profile packed kernel, 2 shared-query packed
+    // kernel (items of one query, up to 32 rows per lane) with the rest on kind 1
     struct Plan { int packed = 0; int rmax = 16; int blocks_per_cu = 1; } plan[3];
     int occ[3][cmk::kNumRMax] = {};
     int occ_pk[cmk::kNumRMaxPk] = {};
     int occ_over = 1;
+    int occ_pkq = 1;                    // shared-query packed kernel (plan kind 2, rmax 32)
     char arch[64] = {0};
     int runtime_version = 0;
     void* small = nullptr;              // counters, error flag, dummy bytes
@@ -57,6 +60,7 @@ struct cm_context {
     cmrt::DeviceBuf keys, keys_alt, vals, vals_alt, sort_tmp;
     cmrt::DeviceBuf bnd;                // boundary rows between strips
     cmrt::DeviceBuf over;               // saturated pairs of the packed kernel
+    cmrt::DeviceBuf q_start, q_len, q_flags, q_lists;   // shared-query plan scratch
     int32_t bnd_stride = 0;
     // buffers of the ClusterMerge driver and the screen (released with the context)
     cmrt::DeviceBuf drv[12];

@@ -26,7 +26,7 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
     const cm_context::Plan saved = ctx->plan[pass];
     const bool with_end = pass == CM_PASS_SCORE_END;
-    constexpr int kMaxRows = 16;
+    constexpr int kMaxRows = 32;
     int32_t* d = nullptr;
     hipError_t e = hipMalloc(&d, static_cast<size_t>(n_pairs) * 12);
     if (e != hipSuccess) return hip_fail(e, "tuner buffers");
@@ -44,8 +44,10 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     // candidates: (kernel, rows-per-lane limit); the packed kernel serves the score pass only
     struct Cand { int packed, rmax; };
     std::vector<Cand> cands;
-    if (pass == CM_PASS_SCORE)
+    if (pass == CM_PASS_SCORE) {
+        cands.push_back({2, cmk::kRMaxQ});
         for (int k = 0; k < cmk::kNumRMaxPk; ++k) cands.push_back({1, cmk::kRMaxChoicePk[k]});
+    }
     for (int k = 0; k < cmk::kNumRMax; ++k) cands.push_back({0, cmk::kRMaxChoice[k]});
     for (const Cand& cd : cands) {
         if (st != CM_OK) break;
@@ -78,8 +80,8 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
                 break;
             }
             if (ref.empty()) ref = cur;
-            else if (ref != cur) { st = fail(CM_EDEVICE, "launch plans disagree (%s, rmax %d, %d blocks/CU)",
-                                             cd.packed ? "packed" : "int32", cd.rmax, bpc); break; }
+            else if (ref != cur) { st = fail(CM_EDEVICE, "launch plans disagree (kernel %d, rmax %d, %d blocks/CU)",
+                                             cd.packed, cd.rmax, bpc); break; }
             if (table && rows < kMaxRows) {
                 table[4 * rows] = cd.packed;
                 table[4 * rows + 1] = cd.rmax;

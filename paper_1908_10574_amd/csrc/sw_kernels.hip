@@ -111,7 +111,10 @@ __device__ __forceinline__ void shape_for(int m, int rmax, bool even, int& R, in
 // plan: validate, write trivial results, build sort keys
 // ---------------------------------------------------------------------------
 __global__ void k_zero_counters(Counters* c) {
-    if (threadIdx.x == 0) { c->n_work = 0; c->ticket = 0; c->n_over = 0; c->ticket_over = 0; }
+    if (threadIdx.x == 0) {
+        c->n_work = 0; c->ticket = 0; c->n_over = 0; c->ticket_over = 0;
+        c->n_sel[0] = 0; c->n_sel[1] = 0; c->ticket_b = 0;
+    }
 }
 
 __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
@@ -532,7 +535,13 @@ __device__ __forceinline__ uint32_t pk_sbyte(uint32_t wa, uint32_t wb, uint32_t 
 template <int W>
 __device__ __forceinline__ ProfWords<W> load_prof_at(const uint8_t* p) {
     ProfWords<W> r;
-    if constexpr (W == 2) {
+    if constexpr (W >= 4) {
+#pragma unroll
+        for (int q = 0; q < W; q += 4) {
+            uint4 v = *reinterpret_cast<const uint4*>(p + 4 * q);
+            r.w[q] = v.x; r.w[q + 1] = v.y; r.w[q + 2] = v.z; r.w[q + 3] = v.w;
+        }
+    } else if constexpr (W == 2) {
         uint2 v = *reinterpret_cast<const uint2*>(p);
         r.w[0] = v.x; r.w[1] = v.y;
     } else {
@@ -541,10 +550,14 @@ __device__ __forceinline__ ProfWords<W> load_prof_at(const uint8_t* p) {
     return r;
 }
 
-template <int R, int RMAXT>
-__device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_work,
-                                            const int8_t* __restrict__ s_mat, uint8_t* __restrict__ s_prof) {
-    constexpr int RP = prof_row_bytes(R);            // 4 or 8 bytes of profile per lane and residue
+// kShared: the eight pairs of the item share their query (the plan groups
+// them), so one profile serves the whole wavefront; each group builds a
+// quarter of its residue rows.
+template <int R, int RMAXT, bool kShared>
+__device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __restrict__ order, int item,
+                                            int n_work, const int8_t* __restrict__ s_mat,
+                                            uint8_t* __restrict__ s_prof) {
+    constexpr int RP = prof_row_bytes(R);            // bytes of profile per lane and residue
     constexpr int W = RP / 4;
     constexpr int kRows = kGroup * R;
     constexpr int kColStride = kGroup * RP;          // bytes between the residue rows of a profile
@@ -566,7 +579,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
         p[h] = 0; m[h] = 0; n[h] = 0;
         A[h] = a.seqs; B[h] = a.seqs;
         if (has[h]) {
-            p[h] = a.order[pos];
+            p[h] = order[pos];
             const int x = a.pairs[2 * p[h]], y = a.pairs[2 * p[h] + 1];
             A[h] = a.seqs + a.offsets[x];
             B[h] = a.seqs + a.offsets[y];
@@ -577,8 +590,18 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
     const int S0 = (m[0] + kRows - 1) / kRows;
     const int S1 = (m[1] + kRows - 1) / kRows;
     const int s_max = wave_max4(max(S0, S1));
-    uint8_t* prof0 = s_prof + (2 * g) * kProfBytes;
-    uint8_t* prof1 = prof0 + kProfBytes;
+    uint8_t* prof0 = kShared ? s_prof : s_prof + (2 * g) * kProfBytes;
+    uint8_t* prof1 = kShared ? s_prof : prof0 + kProfBytes;
+    bool bad_plan = false;
+    if constexpr (kShared) {
+        // every pair of the item must have group 0's first query
+        const uint64_t a0 = reinterpret_cast<uint64_t>(A[0]);
+        const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(a0 & 0xffffffffu)));
+        const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(a0 >> 32)));
+        const uint64_t first = (static_cast<uint64_t>(hi) << 32) | lo;
+        bad_plan = (has[0] && reinterpret_cast<uint64_t>(A[0]) != first) ||
+                   (has[1] && reinterpret_cast<uint64_t>(A[1]) != first);
+    }
     const uint8_t* lp0 = prof0 + gl * RP;
     const uint8_t* lp1 = prof1 + gl * RP;
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
@@ -617,9 +640,9 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
             }
             __syncthreads();   // previous strip's readers are done with the profiles
 #pragma unroll 1
-            for (int c = 0; c < kNRes; ++c) {
+            for (int c = kShared ? g : 0; c < kNRes; c += kShared ? kPairsPerWave : 1) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < (kShared ? 1 : 2); ++h) {
                     uint32_t w[W];
 #pragma unroll
                     for (int q = 0; q < W; ++q) {
@@ -633,8 +656,15 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
                         w[q] = word;
                     }
                     uint8_t* dst = (h ? prof1 : prof0) + c * kColStride + gl * RP;
-                    if constexpr (W == 2) *reinterpret_cast<uint2*>(dst) = make_uint2(w[0], w[1]);
-                    else *reinterpret_cast<uint32_t*>(dst) = w[0];
+                    if constexpr (W >= 4) {
+#pragma unroll
+                        for (int q = 0; q < W; q += 4)
+                            *reinterpret_cast<uint4*>(dst + 4 * q) = make_uint4(w[q], w[q + 1], w[q + 2], w[q + 3]);
+                    } else if constexpr (W == 2) {
+                        *reinterpret_cast<uint2*>(dst) = make_uint2(w[0], w[1]);
+                    } else {
+                        *reinterpret_cast<uint32_t*>(dst) = w[0];
+                    }
                 }
             }
             __syncthreads();
@@ -814,6 +844,18 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, int item, int n_wor
         }
     }
     if (bad || badcode > 19) atomicOr(a.err, kErrResidue);
+    if (bad_plan) atomicOr(a.err, kErrPlan);
+}
+
+// rows per lane of an item from its first pair's query (lists without keys)
+__device__ __forceinline__ int item_rows(const SwArgs& a, const int32_t* order, int item, int per_item, int rmax,
+                                         bool even) {
+    const int p = order[static_cast<int64_t>(item) * per_item];
+    const int x = a.pairs[2 * p];
+    const int m = static_cast<int>(a.offsets[x + 1] - a.offsets[x]);
+    int R, strips;
+    shape_for(m, rmax, even, R, strips);
+    return __builtin_amdgcn_readfirstlane(R);
 }
 
 template <int RMAXT>
@@ -821,28 +863,168 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
     __shared__ __attribute__((aligned(16))) uint8_t
         s_prof[kPairsPerWave * 2 * kNRes * kGroup * prof_row_bytes(RMAXT)];
+    const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
+    if (n_work == 0) return;
+    int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
     for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
     __syncthreads();
-    const int n_work = a.ctr->n_work;
     const int n_items = (n_work + kPairsPerWavePk - 1) / kPairsPerWavePk;
     while (true) {
         int item = 0;
-        if (threadIdx.x == 0) item = atomicAdd(&a.ctr->ticket, 1);
+        if (threadIdx.x == 0) item = atomicAdd(ticket, 1);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
-        const uint32_t key = a.keys[static_cast<int64_t>(item) * kPairsPerWavePk];
-        const int R = kRMax - static_cast<int>(key >> 24);
-        if (R <= 1) run_item_pk<1, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R == 2) run_item_pk<2, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R == 3) run_item_pk<3, RMAXT>(a, item, n_work, s_mat, s_prof);
-        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT>(a, item, n_work, s_mat, s_prof);
+        int R;
+        if (a.keys) R = kRMax - static_cast<int>(a.keys[static_cast<int64_t>(item) * kPairsPerWavePk] >> 24);
+        else R = item_rows(a, a.order, item, kPairsPerWavePk, RMAXT, false);
+        if (R <= 1) run_item_pk<1, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R == 2) run_item_pk<2, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R == 3) run_item_pk<3, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
         else if constexpr (RMAXT >= 8) {
-            if (R == 5) run_item_pk<5, RMAXT>(a, item, n_work, s_mat, s_prof);
-            else if (R == 6) run_item_pk<6, RMAXT>(a, item, n_work, s_mat, s_prof);
-            else if (R == 7) run_item_pk<7, RMAXT>(a, item, n_work, s_mat, s_prof);
-            else run_item_pk<8, RMAXT>(a, item, n_work, s_mat, s_prof);
+            if (R == 5) run_item_pk<5, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+            else if (R == 6) run_item_pk<6, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+            else if (R == 7) run_item_pk<7, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+            else run_item_pk<8, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
         }
     }
+}
+
+// Shared-query packed kernel: items of eight pairs with one query, even rows
+// per lane up to 32 (strips of up to 512 rows), one LDS profile per wavefront.
+template <int R>
+__device__ __forceinline__ bool run_pkq_if(const SwArgs& a, int Rw, int item, int n_work, const int8_t* s_mat,
+                                           uint8_t* s_prof) {
+    if (Rw != R) return false;
+    run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof);
+    return true;
+}
+
+__global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
+    __shared__ int8_t s_mat[kNRes * kMatStride];
+    __shared__ __attribute__((aligned(16))) uint8_t s_prof[kNRes * kGroup * prof_row_bytes(kRMaxQ)];
+    const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
+    if (n_work == 0) return;
+    int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
+    for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
+    __syncthreads();
+    const int n_items = (n_work + kPairsPerWavePk - 1) / kPairsPerWavePk;
+    while (true) {
+        int item = 0;
+        if (threadIdx.x == 0) item = atomicAdd(ticket, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items) break;
+        const int R = item_rows(a, a.order, item, kPairsPerWavePk, kRMaxQ, true);
+        run_pkq_if<2>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<4>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<6>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<8>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<10>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<12>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<14>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<16>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<18>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<20>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<22>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<24>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<26>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<28>(a, R, item, n_work, s_mat, s_prof) ||
+            run_pkq_if<30>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<32>(a, R, item, n_work, s_mat, s_prof);
+    }
+}
+
+// ---- shared-query plan
+// the two-profile kernel's shape key (rows-per-lane class, strips, columns)
+// for every pair of a list (entries at or past *count: skip key)
+__global__ void k_keys_list(SwArgs a, const int32_t* list, const int32_t* count, int64_t n, uint32_t* keys) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    uint32_t key = kSkipKey;
+    if (i < *count) {
+        const int p = list[i];
+        const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
+        const int m = static_cast<int>(a.offsets[x + 1] - a.offsets[x]);
+        const int nn = static_cast<int>(a.offsets[y + 1] - a.offsets[y]);
+        int R, strips;
+        shape_for(m, a.rmax, false, R, strips);
+        key = (static_cast<uint32_t>(kRMax - R) << 24) | (static_cast<uint32_t>(255 - min(strips, 255)) << 16) |
+              static_cast<uint32_t>(65535 - nn);
+    }
+    keys[i] = key;
+}
+
+__global__ void k_plan_q(SwArgs a, uint64_t* keys, int32_t* vals) {
+    const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (p >= a.n_pairs) return;
+    uint64_t key = ~0ull;
+    if (a.n_live && p >= *a.n_live) {
+        keys[p] = key;
+        vals[p] = static_cast<int32_t>(p);
+        return;
+    }
+    const int x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
+    if (x < 0 || x >= a.n_seqs || y < 0 || y >= a.n_seqs) {
+        atomicOr(a.err, kErrIndex);
+    } else {
+        const int64_t lx = a.offsets[x + 1] - a.offsets[x];
+        const int64_t ly = a.offsets[y + 1] - a.offsets[y];
+        if (lx > 16384 || ly > 16384 || lx < 0 || ly < 0) {
+            atomicOr(a.err, kErrLength);
+        } else if (lx == 0 || ly == 0) {
+            a.scores[p] = 0;
+        } else {
+            int R, strips;
+            shape_for(static_cast<int>(lx), kRMaxQ, true, R, strips);
+            key = (static_cast<uint64_t>(kRMaxQ - R) << 58) |
+                  (static_cast<uint64_t>(255 - min(strips, 255)) << 50) |
+                  (static_cast<uint64_t>(static_cast<uint32_t>(x)) << 16) |
+                  static_cast<uint64_t>(65535 - static_cast<int>(ly));
+            atomicAdd(&a.ctr->n_work, 1);
+        }
+    }
+    keys[p] = key;
+    vals[p] = static_cast<int32_t>(p);
+}
+
+// start_in[i] = i at the first pair of a query run, else 0 (a max-scan then
+// gives every position its run start)
+__global__ void k_heads_q(const uint64_t* keys, int64_t n, const int32_t* n_work, int32_t* start_in) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    const bool head = i < *n_work && (i == 0 || (keys[i] >> 16) != (keys[i - 1] >> 16));
+    start_in[i] = head ? static_cast<int32_t>(i) : 0;
+}
+
+// run length at each run start (binary search for the run's end), then the
+// item lists: the first 8 * floor(len / 8) pairs of a run go to list A
+__global__ void k_runlen_q(const uint64_t* keys, const int32_t* start, int64_t n, const int32_t* n_work,
+                           int32_t* run_len) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t w = *n_work;
+    if (i >= n || i >= w || start[i] != i) return;
+    const uint64_t q = keys[i] >> 16;
+    int64_t lo = i, hi = w - 1;          // last index with the same run key
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if ((keys[mid] >> 16) == q) lo = mid;
+        else hi = mid - 1;
+    }
+    run_len[i] = static_cast<int32_t>(lo - i + 1);
+}
+// An item goes to list A only if its subjects' lengths are close (the
+// shortest at least 7/8 of the longest, the item runs to the longest);
+// otherwise its pairs are packed with like shapes from other queries.
+__global__ void k_flags_q(const uint64_t* keys, const int32_t* start, const int32_t* run_len, int64_t n,
+                          const int32_t* n_work, uint8_t* flag_a, uint8_t* flag_b) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    uint8_t fa = 0, fb = 0;
+    if (i < *n_work) {
+        const int32_t s = start[i];
+        const int32_t len = run_len[s];
+        if ((i - s) < (len & ~7)) {
+            const int64_t first = s + ((i - s) & ~7);       // columns sorted longest first
+            const int n_long = 65535 - static_cast<int>(keys[first] & 0xffffu);
+            const int n_short = 65535 - static_cast<int>(keys[first + 7] & 0xffffu);
+            fa = 8 * n_short >= 7 * n_long;
+        }
+        fb = !fa;
+    }
+    flag_a[i] = fa;
+    flag_b[i] = fb;
 }
 
 // int32 re-run of the pairs whose packed score saturated (usually none): the
@@ -904,6 +1086,49 @@ static int occupancy(int rmax) {
         case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 12>, 64, 0); break;
         default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw<P, 16>, 64, 0); break;
     }
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+hipError_t launch_plan_q(const SwArgs& a, uint64_t* keys, int32_t* vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, a.ctr);
+    if (a.n_pairs > 0)
+        hipLaunchKernelGGL(k_plan_q, dim3(static_cast<unsigned>((a.n_pairs + 255) / 256)), dim3(256), 0, s, a, keys,
+                           vals);
+    return hipGetLastError();
+}
+hipError_t launch_runs_q(const uint64_t* keys_sorted, int64_t n, const int32_t* n_work, int32_t* start_in,
+                         hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_heads_q, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, keys_sorted, n,
+                           n_work, start_in);
+    return hipGetLastError();
+}
+hipError_t launch_flags_q(const uint64_t* keys_sorted, const int32_t* start, int64_t n, const int32_t* n_work,
+                          int32_t* run_len, uint8_t* flag_a, uint8_t* flag_b, hipStream_t s) {
+    if (n > 0) {
+        const dim3 g(static_cast<unsigned>((n + 255) / 256));
+        hipLaunchKernelGGL(k_runlen_q, g, dim3(256), 0, s, keys_sorted, start, n, n_work, run_len);
+        hipLaunchKernelGGL(k_flags_q, g, dim3(256), 0, s, keys_sorted, start, run_len, n, n_work, flag_a, flag_b);
+    }
+    return hipGetLastError();
+}
+hipError_t launch_keys_list(const SwArgs& a, const int32_t* list, const int32_t* count, int64_t n, uint32_t* keys,
+                            hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_keys_list, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, a, list, count,
+                           n, keys);
+    return hipGetLastError();
+}
+hipError_t launch_sw_pkq(const SwArgs& a_list, const SwArgs& b_list, int grid, int grid_b, int grid_over,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_sw_pkq, dim3(grid), dim3(64), 0, s, a_list);
+    hipLaunchKernelGGL((k_sw_pk<8>), dim3(grid_b), dim3(64), 0, s, b_list);
+    hipLaunchKernelGGL(k_sw_over, dim3(grid_over), dim3(64), 0, s, a_list);
+    return hipGetLastError();
+}
+int sw_pkq_blocks_per_cu() {
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sw_pkq, 64, 0);
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 

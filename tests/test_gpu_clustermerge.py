@@ -27,9 +27,9 @@ def dev_store(ds):
     return res, torch.from_numpy(ds.offsets.copy()).cuda()
 
 
-def run_both(cm, ds, T=120, mT=166, mU=15):
+def run_both(cm, ds, T=120, mT=166, mU=15, ctx=None):
     res, off = dev_store(ds)
-    g = cm.clustermerge_run(res, off, ds.matrix, T=T, mT=mT, mU=mU)
+    g = cm.clustermerge_run(res, off, ds.matrix, T=T, mT=mT, mU=mU, ctx=ctx)
     clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix, T=T, mT=mT, mU=mU)
     return g, clusters, pairs, st
 
@@ -63,11 +63,17 @@ def test_small_families_exact(cm):
     assert len(pairs) / truth > 0.9
 
 
-def test_zipf_families_exact(cm):
+@pytest.mark.parametrize("score_plan", [None, (1, 8), (0, 16)])
+def test_zipf_families_exact(cm, score_plan):
     ds = cmgen.clustermerge_families(n_seqs=500, n_families=50, seed=212, median=120, hi=400)
-    g, clusters, pairs, st = run_both(cm, ds)
+    ctx = cm.Context(0)
+    if score_plan:
+        ctx.set_plan(0, score_plan[0], score_plan[1], 1)
+        ctx.set_plan(0, score_plan[0], score_plan[1], ctx.get_plan(0)[3])
+    g, clusters, pairs, st = run_both(cm, ds, ctx=ctx)
     assert_same(g, clusters, pairs, st)
     assert st.full_merges > 0 and st.exchanges > 0
+    ctx.close()
 
 
 @pytest.mark.parametrize("mT,mU", [(10**6, 15), (120, 400), (166, 0)])

@@ -42,7 +42,7 @@ def run(cm, ctx, ds, pairs):
     return out, s_only.cpu().numpy()
 
 
-PLANS = [(0, 8), (0, 12), (0, 16), (1, 4), (1, 8)]
+PLANS = [(0, 8), (0, 12), (0, 16), (1, 4), (1, 8), (2, 32)]
 
 
 @pytest.mark.parametrize("packed,rmax", PLANS)
@@ -51,7 +51,7 @@ def test_every_plan_is_exact(cm, data, packed, rmax):
     the packed kernel serves the score pass, the others keep an int32 plan."""
     ds, pairs, ref = data
     ctx = cm.Context(0)
-    assert ctx.get_plan(0)[:2] == (1, 8)            # default score plan: packed, 8 rows
+    assert ctx.get_plan(0)[:2] == (2, 32)           # default score plan: shared-query packed
     for bpc_pick in ("one", "max"):
         for p in range(3):
             if packed and p != 0:
@@ -69,6 +69,8 @@ def test_every_plan_is_exact(cm, data, packed, rmax):
         ctx.set_plan(1, 1, 8, 1)                     # packed plans exist for the score pass only
     with pytest.raises(cm.CMError):
         ctx.set_plan(0, 1, 16, 1)                    # packed rows-per-lane limit is 4 or 8
+    with pytest.raises(cm.CMError):
+        ctx.set_plan(0, 2, 16, 1)                    # the shared-query kernel takes up to 32 rows
     ctx.close()
 
 
@@ -78,7 +80,7 @@ def test_autotune_and_plan_cache(cm, data, tmp_path):
     res = torch.from_numpy(ds.residues).cuda()
     off = torch.from_numpy(ds.offsets).cuda()
     rows = ctx.autotune(res, off, torch.from_numpy(pairs).cuda(), ds.matrix, 0)
-    assert len(rows) >= 5 and {r[0] for r in rows} == {0, 1}
+    assert len(rows) >= 6 and {r[0] for r in rows} == {0, 1, 2}
     best = min(rows, key=lambda r: r[3])
     assert ctx.get_plan(0)[:3] == best[:3]
     out, s_only = run(cm, ctx, ds, pairs)
@@ -100,7 +102,7 @@ def test_autotune_and_plan_cache(cm, data, tmp_path):
         assert ctx3.get_plan(0)[:3] == best[:3]
         os.environ["CM_AUTOTUNE_CACHE"] = str(bad)
         ctx4 = cm.Context(0)                      # corrupt cache: defaults
-        assert ctx4.get_plan(0)[:2] == (1, 8) and ctx4.get_plan(1)[:2] == (0, 16)
+        assert ctx4.get_plan(0)[:2] == (2, 32) and ctx4.get_plan(1)[:2] == (0, 16)
     finally:
         del os.environ["CM_AUTOTUNE_CACHE"]
     for c in (ctx, ctx2, ctx3, ctx4):

@@ -248,10 +248,10 @@ def test_packed_saturation_boundary(cm):
     ctx = cm.context()
     saved = ctx.get_plan(0)
     try:
-        for rmax in (4, 8):
-            ctx.set_plan(0, 1, rmax, 1)
+        for kind, rmax in ((1, 4), (1, 8), (2, 32)):
+            ctx.set_plan(0, kind, rmax, 1)
             sc = cm.sw_score_batch(res, off, pr, M)
             cm.sync()
-            assert np.array_equal(sc.cpu().numpy(), ref), rmax
+            assert np.array_equal(sc.cpu().numpy(), ref), (kind, rmax)
     finally:
         ctx.set_plan(0, saved[0], saved[1], saved[2])
