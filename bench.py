@@ -40,10 +40,10 @@ def log(msg):
 
 
 def measured_traffic():
-    """HBM bytes per launch of the packed score kernel from the committed
+    """HBM bytes per score pass (k_sw_pkq + k_sw_pk) from the committed
     PMC summary, if it was taken on the current kernel source; else None."""
     import hashlib
-    prof = os.path.join(ROOT, "profiles", "k_sw_pk_traffic_clustermerge_20k.txt")
+    prof = os.path.join(ROOT, "profiles", "k_sw_pkq_traffic_clustermerge_20k.txt")
     src = os.path.join(ROOT, "paper_1908_10574_amd", "csrc", "sw_kernels.hip")
     if not os.path.exists(prof):
         return None
