@@ -17,6 +17,8 @@
 //           form one GPU batch; the replays resume until every merge is done.
 // The final stage aligns the unique within-cluster pairs (Section 6.1),
 // generated per element in sorted order, reusing scores already computed.
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -51,6 +53,11 @@ __global__ void k_end_compact(const int32_t* planes, int64_t stride, const int64
         e[3] = planes[3 * stride + i];
         e[4] = planes[4 * stride + i];
     }
+}
+// keep[i] = guard[i] (bypasses the screen) or logit >= tau
+__global__ void k_keep(const float* z, const uint8_t* guard, float tau, int64_t n, uint8_t* keep) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i < n) keep[i] = (guard[i] != 0 || z[i] >= tau) ? 1 : 0;
 }
 }  // namespace cmdrv
 
@@ -172,6 +179,8 @@ struct Aligner {
         hipEvent_t e0 = nullptr, e1 = nullptr, done = nullptr;
         hipEvent_t scored = nullptr;   // score plane on the host (spans, outside graphs)
         bool have_scores = false;
+        bool screened = false;         // screened batch: np candidates, the kept ones aligned
+        int64_t kept = 0;
         int64_t np = 0;
         int64_t stride = 0;     // distance between output planes (np, or the capacity)
         int64_t prefix = 0;     // end records copied back with the scores
@@ -189,9 +198,12 @@ struct Aligner {
     };
     std::vector<Graph> graphs;
     Pinned sh_pairs, sh_out;   // screen staging (separate from the in-flight slots)
+    hipEvent_t scr0 = nullptr, scr1 = nullptr;   // around the device-side screen of a batch
 
     cm_status init() {
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(CM_EDEVICE, "stream");
+        if (hipEventCreate(&scr0) != hipSuccess || hipEventCreate(&scr1) != hipSuccess)
+            return fail(CM_EDEVICE, "events");
         for (Slot& sl : slot)
             if (hipEventCreate(&sl.e0) != hipSuccess || hipEventCreate(&sl.e1) != hipSuccess ||
                 hipEventCreate(&sl.done) != hipSuccess || hipEventCreate(&sl.scored) != hipSuccess)
@@ -206,6 +218,8 @@ struct Aligner {
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.scored) (void)hipEventDestroy(sl.scored);
         }
+        if (scr0) (void)hipEventDestroy(scr0);
+        if (scr1) (void)hipEventDestroy(scr1);
         if (st) (void)hipStreamDestroy(st);
     }
 
@@ -265,6 +279,7 @@ struct Aligner {
     // the pairs scoring above mT also get end and start cells (EndRec).
     cm_status submit(int k, const int32_t* pairs, int64_t np, bool spans) {
         Slot& sl = slot[k];
+        sl.screened = false;
         sl.np = np;
         sl.stride = np;
         sl.spans = spans;
@@ -363,6 +378,90 @@ struct Aligner {
         return CM_OK;
     }
 
+    // Screened batch in slot 0 (not under graph capture): the device screens
+    // the np candidates (guard[i] != 0 bypasses the screen), compacts the kept
+    // pairs in order and aligns them with end and start cells.  wait_scores()
+    // then returns the kept pairs' scores in order and keep_flags() the
+    // decision for every candidate.
+    cm_status submit_screened(const int32_t* pairs, const uint8_t* guard, int64_t np, const cm_screen* scr,
+                              const uint16_t* feat, float tau) {
+        Slot& sl = slot[0];
+        sl.np = np;
+        sl.stride = np;
+        sl.spans = true;
+        sl.cells = 0;
+        sl.screened = true;
+        sl.kept = 0;
+        sl.have_scores = false;
+        sl.prefix = prefix_of(np);
+        if (np == 0) return CM_OK;
+        const size_t pb = static_cast<size_t>(np) * 8;
+        size_t tmp = 0;
+        hipError_t e = hipcub::DeviceSelect::Flagged(nullptr, tmp, static_cast<uint64_t*>(nullptr),
+                                                     static_cast<uint8_t*>(nullptr), static_cast<uint64_t*>(nullptr),
+                                                     static_cast<int64_t*>(nullptr), static_cast<int>(np));
+        if (e != hipSuccess) return hip_fail(e, "select size query");
+        // screen scratch: logits, guard flags, keep flags, kept count, select temp
+        const size_t o_guard = static_cast<size_t>(np) * 4, o_keep = o_guard + np;
+        const size_t o_count = (o_keep + np + 15) & ~static_cast<size_t>(15), o_tmp = o_count + 16;
+        cmrt::DeviceBuf& d_pairs = ctx->drv[0];
+        cmrt::DeviceBuf& d_out = ctx->drv[1];
+        cmrt::DeviceBuf& d_kept = ctx->drv[4];
+        cmrt::DeviceBuf& d_scr = ctx->drv[11];
+        const size_t hb = host_ints(np, true) * 4;
+        if (!d_pairs.ensure(pb) || !d_out.ensure(dev_ints(np) * 4) || !d_kept.ensure(pb) ||
+            !d_scr.ensure(o_tmp + tmp) || !sl.h_pairs.ensure(pb + np) || !sl.h_out.ensure(hb + np) ||
+            !sl.h_err.ensure(16))
+            return fail(CM_ENOMEM, "cannot stage %lld screened pairs", static_cast<long long>(np));
+        char* scr_base = static_cast<char*>(d_scr.ptr);
+        float* z = reinterpret_cast<float*>(scr_base);
+        uint8_t* d_guard = reinterpret_cast<uint8_t*>(scr_base + o_guard);
+        uint8_t* d_keep = reinterpret_cast<uint8_t*>(scr_base + o_keep);
+        int64_t* d_count = reinterpret_cast<int64_t*>(scr_base + o_count);
+        std::memcpy(sl.h_pairs.ptr, pairs, pb);
+        std::memcpy(static_cast<char*>(sl.h_pairs.ptr) + pb, guard, static_cast<size_t>(np));
+        e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_guard, static_cast<char*>(sl.h_pairs.ptr) + pb, static_cast<size_t>(np),
+                               hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "pairs upload");
+        (void)hipEventRecord(sl.e0, st);
+        (void)hipEventRecord(scr0, st);
+        cm_status s = cm_screen_infer(scr, feat, static_cast<const int32_t*>(d_pairs.ptr), np, z, st);
+        if (s != CM_OK) return s;
+        hipLaunchKernelGGL(cmdrv::k_keep, dim3(static_cast<unsigned>((np + 255) / 256)), dim3(256), 0, st, z, d_guard,
+                           tau, np, d_keep);
+        e = hipcub::DeviceSelect::Flagged(scr_base + o_tmp, tmp, static_cast<const uint64_t*>(d_pairs.ptr), d_keep,
+                                          static_cast<uint64_t*>(d_kept.ptr), d_count, static_cast<int>(np), st);
+        if (e != hipSuccess) return hip_fail(e, "screen select");
+        (void)hipEventRecord(scr1, st);
+        e = hipMemcpyAsync(static_cast<char*>(sl.h_out.ptr) + hb, d_keep, static_cast<size_t>(np),
+                           hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "keep flags download");
+        s = enqueue(static_cast<int32_t*>(d_kept.ptr), np, np, d_count, static_cast<int32_t*>(d_out.ptr), true,
+                    sl.h_out.ptr, sl.scored);
+        if (s != CM_OK) return s;
+        (void)hipEventRecord(sl.e1, st);
+        e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "flag download");
+        (void)hipEventRecord(sl.done, st);
+        return CM_OK;
+    }
+    // keep decisions of the screened batch in slot 0 (valid after wait_scores)
+    const uint8_t* keep_flags() const {
+        return static_cast<const uint8_t*>(slot[0].h_out.ptr) + host_ints(slot[0].np, true) * 4;
+    }
+    // device seconds of the last batch's screen (after wait_scores)
+    double screen_seconds() {
+        float ms = 0.f;
+        return hipEventElapsedTime(&ms, scr0, scr1) == hipSuccess ? ms * 1e-3 : 0.0;
+    }
+    // the screened batch aligned `kept` pairs of `cells` cells (for the statistics)
+    void set_kept(int64_t kept, double cells) {
+        slot[0].kept = kept;
+        slot[0].cells = cells;
+    }
+
     // Scores of slot k (submitted with spans) into out, as soon as the score
     // pass is back; wait() later adds the end records.
     cm_status wait_scores(int k, std::vector<int32_t>& out) {
@@ -410,9 +509,10 @@ struct Aligner {
         cmrt::drain_timers(ctx, false);
         stats->t_gpu_s += ms * 1e-3;
         stats->waves += 1;
-        stats->aligned_pairs += sl.np;
+        stats->aligned_pairs += sl.screened ? sl.kept : sl.np;
         stats->aligned_cells += sl.cells;
         sl.np = 0;
+        sl.screened = false;
         return CM_OK;
     }
 
@@ -801,15 +901,33 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     std::vector<int32_t> kept;
     const std::vector<int32_t>* src = &pairs;
     cm_status s = CM_OK;
-    if (screened(CM_STAGE_REP)) {
+    // the device screens, compacts and aligns in one stream (host-side
+    // screening under graph capture)
+    const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
+    auto guarded = [&](int32_t a, int32_t b) {
+        const int64_t prod = static_cast<int64_t>(cl_[a].objs.size()) * cl_[b].objs.size();
+        return p_.screen_min_product > 0 && prod >= p_.screen_min_product;
+    };
+    std::vector<uint8_t> guard;
+    int64_t n_guard = 0;
+    if (dev_screen) {
+        guard.assign(total, 0);
+        for (const MergeJob& job : jobs) {
+            size_t k = job.rep_off;
+            for (int32_t a : sets_[job.set1])
+                for (int32_t b : sets_[job.set2]) {
+                    if (guarded(a, b)) { guard[k] = 1; ++n_guard; }
+                    ++k;
+                }
+        }
+    } else if (screened(CM_STAGE_REP)) {
         std::vector<int32_t> cand;
         std::vector<size_t> cand_idx;
         for (const MergeJob& job : jobs) {
             size_t k = job.rep_off;
             for (int32_t a : sets_[job.set1])
                 for (int32_t b : sets_[job.set2]) {
-                    const int64_t prod = static_cast<int64_t>(cl_[a].objs.size()) * cl_[b].objs.size();
-                    if (p_.screen_min_product <= 0 || prod < p_.screen_min_product) {
+                    if (!guarded(a, b)) {
                         cand.push_back(pairs[2 * k]);
                         cand.push_back(pairs[2 * k + 1]);
                         cand_idx.push_back(k);
@@ -830,13 +948,34 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     std::vector<EndRec> ends;
     const size_t nk = src->size() / 2;
     const auto ta = Clock::now();
-    s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
+    if (dev_screen)
+        s = al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(total), scr_,
+                                static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau);
+    else
+        s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
     if (s != CM_OK) return s;
     const auto tb = Clock::now();
     // scores first (the end and start passes are still running), then the
     // coverage bits of the pairs scoring above mT
     s = al_.wait_scores(0, out);
     if (s != CM_OK) return s;
+    if (dev_screen) {
+        const uint8_t* kf = al_.keep_flags();
+        int64_t n_kept = 0;
+        double cells = 0;
+        for (size_t k = 0; k < total; ++k) {
+            keep[k] = kf[k];
+            if (keep[k]) {
+                ++n_kept;
+                cells += static_cast<double>(len_[pairs[2 * k]]) * len_[pairs[2 * k + 1]];
+            } else {
+                ++st_.screened_out;
+            }
+        }
+        st_.screened_pairs += static_cast<int64_t>(total) - n_guard;
+        st_.t_screen_s += al_.screen_seconds();
+        al_.set_kept(n_kept, cells);
+    }
     std::vector<uint8_t> bits(total, 0);
     std::vector<size_t> deferred;            // batch index k of the pairs above mT
     size_t q = 0;
