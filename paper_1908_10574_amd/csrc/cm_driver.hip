@@ -639,6 +639,7 @@ private:
     Aligner al_;
     cm_stats st_{};
     bool log_ = false;
+    double t_spec_ = 0;   // host seconds in speculate (logging)
     std::vector<int32_t> len_;
     std::vector<Cluster> cl_;
     std::vector<std::vector<int32_t>> sets_;
@@ -808,7 +809,9 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
             if (s >= p_.T) add2.push_back(m);
         }
         if (missing) {
+            const auto sp0 = Clock::now();
             speculate(job, req);
+            t_spec_ += secs(sp0, Clock::now());
             return true;
         }
         st_.exchange_alignments += tests;
@@ -1033,9 +1036,10 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     const auto t3 = Clock::now();
     if (log_)
         fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs (prep %.3f submit %.3f wait %.3f) "
-                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f align %.3f)\n",
+                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f)\n",
                 jobs.size(), total, secs(t0, t1), secs(t0, ta), secs(ta, tb), secs(tb, t1), secs(t1, t2),
-                secs(t2, t3), waves, n_req, t_rep, t_al);
+                secs(t2, t3), waves, n_req, t_rep, t_spec_, t_al);
+    t_spec_ = 0;
     return CM_OK;
 }
 
