@@ -111,6 +111,15 @@ public:
         vals_[i] = v;
     }
     size_t size() const { return size_; }
+    // entries as (key, value) sorted by key: for keys made with key(x, y),
+    // grouped by x with y ascending
+    void sorted_entries(std::vector<std::pair<uint64_t, int32_t>>* out) const {
+        out->clear();
+        out->reserve(size_);
+        for (size_t i = 0; i < keys_.size(); ++i)
+            if (keys_[i] != kEmpty) out->emplace_back(keys_[i], vals_[i]);
+        std::sort(out->begin(), out->end());
+    }
 
 private:
     static constexpr uint64_t kEmpty = ~0ull;
@@ -1128,6 +1137,12 @@ cm_status Driver::final_stage(cm_result* res) {
         cur = 1 - cur;
         return CM_OK;
     };
+    // cached scores as per-element runs sorted by partner: candidates of x
+    // come sorted by y, so one forward walk finds the cached ones (a probe of
+    // the hash map per candidate costs a cache miss each)
+    std::vector<std::pair<uint64_t, int32_t>> known;
+    cache_.sorted_entries(&known);
+    size_t kp = 0;
     std::vector<int32_t> tmp;
     for (int32_t x = 0; x < n_; ++x) {
         // y > x sharing a cluster with x: the union of the sorted member
@@ -1152,15 +1167,17 @@ cm_status Driver::final_stage(cm_result* res) {
             ye = ys.data() + ys.size();
         }
         Chunk& c = ch[cur];
+        while (kp < known.size() && static_cast<int32_t>(known[kp].first >> 32) < x) ++kp;
         for (const int32_t* py = yb; py != ye; ++py) {
             const int32_t y = *py;
             ++st_.final_candidates;
-            int32_t sc;
             c.cx.push_back(x);
             c.cy.push_back(y);
-            if (cache_.find(PairMap::key(x, y), &sc)) {
+            const uint64_t k = PairMap::key(x, y);
+            while (kp < known.size() && known[kp].first < k) ++kp;
+            if (kp < known.size() && known[kp].first == k) {
                 ++st_.cache_hits;
-                c.cs.push_back(sc);
+                c.cs.push_back(known[kp].second);
             } else {
                 c.cs.push_back(-1);
                 c.gpu.push_back(x);
