@@ -19,7 +19,9 @@ constexpr int kSent = 20;           // sentinel residue code (padding rows / col
 constexpr int kPairsPerWavePk = 8;
 constexpr int kNumRMaxPk = 2;
 constexpr int kRMaxChoicePk[kNumRMaxPk] = {4, 8};
-constexpr int kPkSaturated = 32767; // a packed score this high may have saturated
+// a packed best this high may have saturated (the 16-bit sums saturate at
+// 32767, and the running best is kept with binary16 maximum, exact below 0x7C00)
+constexpr int kPkSaturated = 0x7C00;
 // shared-query packed kernel: the eight pairs of a wavefront share their query,
 // so one LDS profile serves the wavefront and a lane can hold up to 32 rows
 constexpr int kRMaxQ = 32;

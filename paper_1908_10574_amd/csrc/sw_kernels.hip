@@ -518,6 +518,17 @@ __device__ __forceinline__ uint32_t pk_subu(uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
                                                                       __builtin_bit_cast(u16x2, b)));
 }
+// Largest of three pairs of non-negative 16-bit values, compared as binary16
+// (v_pk_maximum3_f16).  Patterns 0..0x7BFF are +0, subnormals and finite
+// positives, whose order is the integer order; 0x7C00 is +Inf and above are
+// NaNs, which the IEEE maximum propagates.  So the result equals the integer
+// maximum whenever that is below 0x7C00, and is at least 0x7C00 otherwise.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_max3f(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(
+        __builtin_elementwise_maximum(__builtin_bit_cast(f16x2, a), __builtin_bit_cast(f16x2, b)),
+        __builtin_bit_cast(f16x2, c)));
+}
 // (sign-extended byte k of wa, sign-extended byte k of wb) as two 16-bit
 // halves.  v_perm can replicate the sign bit of bytes 1 and 3 of either source
 // (selectors 8..11), so odd bytes come straight from the words and even bytes
@@ -772,7 +783,9 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                         E[r] = pk_maxu(pk_subu(E[r], GE), go);
                         F = pk_maxu(pk_subu(F, GE), go);
                         Ho[r] = h;
-                        best = pk_maxs(best, h);
+                        // two rows per update of the running best
+                        if (r & 1) best = pk_max3f(best, Ho[r - 1], h);
+                        else if (r == R - 1) best = pk_maxs(best, h);
                     }
                 }
                 hdiag = Htop;
