@@ -29,9 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "SW GCUPS (bit-exact int32); ClusterMerge time + pair recall, learned vs plain"
 OPS_PER_CELL = 8                       # int32: add, max3, max, add, add, max3, add, max3
 PEAK_INT32_OPS = 256 * 64 * 2.4e9      # CUs x lanes/clk x clock (MI355X)
-# packed 16-bit kernel, per cell: saturating add, max, max, saturating subtract
-# (open), subtract + max (E), subtract + max (F), max (best)
-PK_OPS_PER_CELL = 9
+# packed 16-bit kernels (biased values, maxima as binary16 maximum3), per cell:
+# saturating add (diagonal + substitution), maximum3 (H), saturating subtract
+# (open), subtract + maximum3 (E), subtract + maximum3 (F), half a maximum3
+# (best over two rows)
+PK_OPS_PER_CELL = 7.5
 PEAK_PK16_OPS = 256 * 64 * 2 * 2.4e9   # CUs x lanes/clk x 16-bit halves x clock
 
 

@@ -88,7 +88,7 @@ cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, d
  * the rest on the two-profile packed kernel; packed = 1: the two-profile
  * packed 16-bit kernel for every pair (two pairs per register); packed = 0: the
  * int32 kernel.  Packed plans serve the score pass only, and pairs whose
- * packed score reaches 31744 are recomputed by the int32 kernel), the most
+ * packed score reaches 31616 are recomputed by the int32 kernel), the most
  * query rows a lane holds (int32: 8, 12 or 16; packed: 4 or 8; shared-query:
  * 32; strips are 16 x that many rows) and the persistent blocks per CU (1 ..
  * occupancy limit).  Results never depend on the plan.  A context starts from

@@ -19,8 +19,12 @@ constexpr int kSent = 20;           // sentinel residue code (padding rows / col
 constexpr int kPairsPerWavePk = 8;
 constexpr int kNumRMaxPk = 2;
 constexpr int kRMaxChoicePk[kNumRMaxPk] = {4, 8};
-// a packed best this high may have saturated (the 16-bit sums saturate at
-// 32767, and the running best is kept with binary16 maximum, exact below 0x7C00)
+// The packed kernels keep H, E, F and the best score plus kPkBias, so that
+// H_diag + s is never negative and every value is a non-negative 16-bit
+// integer that orders like a binary16 below 0x7C00 (maxima of three values are
+// binary16 maximum3 operations).  A biased best of 0x7C00 or more (score of
+// 0x7C00 - kPkBias = 31616 or more) may be inexact: the pair is rescored in int32.
+constexpr int kPkBias = 128;        // covers the most negative profile byte, -128
 constexpr int kPkSaturated = 0x7C00;
 // shared-query packed kernel: the eight pairs of a wavefront share their query,
 // so one LDS profile serves the wavefront and a lane can hold up to 32 rows

@@ -486,18 +486,24 @@ __global__ __launch_bounds__(64) void k_sw(SwArgs a) {
 // The same strip / skew / DPP decomposition as run_item, but every register
 // holds two pairs: the low 16 bits belong to one pair and the high 16 bits to
 // another pair of the same shape class, so each VOP3P instruction advances two
-// cells.  With E' and F' clamped at zero and every value non-negative, the
-// cell update is nine packed operations for two cells:
-//     t  = sat(Hdiag + s)              signed saturating add
-//     h  = max(max(t, E'), F')
-//     g  = max(h + go, 0)              unsigned saturating subtract of -go
-//     E' = max(max(E' + ge, 0), g)     (likewise for F')
-//     best = max(best, h)
+// cells.  E' and F' are clamped at zero, and H, E', F' and the best carry a
+// bias B = kPkBias = 128 (the magnitude of the most negative profile byte), so
+// Hdiag + s is never negative and every value is a non-negative 16-bit
+// integer.  Such integers below 0x7C00 order exactly like binary16 numbers
+// (+0, subnormals, normals), so the maxima of three values are one
+// v_pk_maximum3_f16 each, and the cell update is 7.5 packed operations for
+// two cells:
+//     t  = Hdiag + s                   signed saturating add
+//     h  = maximum3(t, E', F')         (= max(t, E', F', 0) + B)
+//     g  = h - |go|                    unsigned saturating subtract
+//     E' = maximum3(E' - |ge|, g, B)   (likewise for F'; B is the zero clamp)
+//     best = maximum3(best, h_r, h_r+1)  (two rows at a time)
 // plus the sign extension of the int8 profile bytes into 16-bit halves (one
-// v_perm per two cells, one shift per four).  No value can exceed the best
-// score, and the signed add saturates at 32767, so a pair whose packed best
-// stays below 32767 has its exact score; a pair that reaches 32767 is queued
-// for the int32 kernel (k_sw_over).
+// v_perm per two cells, one shift per four).  No value exceeds the biased
+// best, and values of 0x7C00 and above (+Inf and NaN patterns) propagate
+// through maximum3, so a pair whose biased best stays below 0x7C00 (score
+// below 31616) has its exact score; any other pair is queued for the int32
+// kernel (k_sw_over).
 // ---------------------------------------------------------------------------
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -509,10 +515,6 @@ __device__ __forceinline__ uint32_t pk_adds(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t pk_maxs(uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, a),
                                                                   __builtin_bit_cast(s16x2, b)));
-}
-__device__ __forceinline__ uint32_t pk_maxu(uint32_t a, uint32_t b) {
-    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
-                                                                  __builtin_bit_cast(u16x2, b)));
 }
 __device__ __forceinline__ uint32_t pk_subu(uint32_t a, uint32_t b) {
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(u16x2, a),
@@ -619,7 +621,9 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
 
     bool bad = false;
     int badcode = 0;
-    uint32_t best = 0;
+    // every H, E, F and best value carries the bias kPkBias (in both halves)
+    constexpr uint32_t KB = static_cast<uint32_t>(kPkBias) * 0x10001u;
+    uint32_t best = KB;
 
     for (int s = 0; s < s_max; ++s) {
         const bool act0 = s < S0, act1 = s < S1;
@@ -708,8 +712,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
             constexpr bool kMulti = decltype(multi)::value;
             uint32_t HA[R], HB[R], E[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) { HA[r] = 0; E[r] = 0; }
-            uint32_t hdiag = 0, Hout = 0, Fout = 0;
+            for (int r = 0; r < R; ++r) { HA[r] = KB; E[r] = KB; }
+            uint32_t hdiag = KB, Hout = KB, Fout = KB;
             uint32_t feedR = col_in(col_raw(gl), gl);
             int2 nfeedR = col_raw(kGroup + gl);
             uint32_t feedH = 0, feedF = 0, collH = 0, collF = 0;
@@ -717,8 +721,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
             if constexpr (kMulti) {
                 const int2 v0 = bnd_raw(gl);
                 const uint32_t mk = rd_mask(gl);
-                feedH = static_cast<uint32_t>(v0.x) & mk;
-                feedF = static_cast<uint32_t>(v0.y) & mk;
+                feedH = (static_cast<uint32_t>(v0.x) & mk) | (KB & ~mk);
+                feedF = (static_cast<uint32_t>(v0.y) & mk) | (KB & ~mk);
                 nfeed = bnd_raw(kGroup + gl);
             }
             uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR), static_cast<int>(kSentPk)));
@@ -740,8 +744,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                     uint32_t nH, nF;
                     if (chunk_last) {
                         const uint32_t mk = rd_mask(t + 1 + gl);
-                        nH = static_cast<uint32_t>(nfeed.x) & mk;
-                        nF = static_cast<uint32_t>(nfeed.y) & mk;
+                        nH = (static_cast<uint32_t>(nfeed.x) & mk) | (KB & ~mk);
+                        nF = (static_cast<uint32_t>(nfeed.y) & mk) | (KB & ~mk);
                         nfeed = bnd_raw(t + 1 + kGroup + gl);
                     } else {
                         nH = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedH)));
@@ -761,7 +765,9 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                             bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
                     }
                 } else {
-                    Htop = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Hout)));
+                    // lane 0's top row is the border (biased zero); a zero F
+                    // there is equivalent, since every E is at least the bias
+                    Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(KB), static_cast<int>(Hout)));
                     F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
                 }
 #pragma unroll
@@ -778,10 +784,13 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                         else if (k == 2) sub = pk_sbyte<2>(wa, wb, sa, sb);
                         else sub = pk_sbyte<3>(wa, wb, sa, sb);
                         const uint32_t d = (r == 0) ? hdiag : Hi[r - 1];
-                        const uint32_t h = pk_maxs(pk_maxs(pk_adds(d, sub), E[r]), F);
+                        // biased: t >= 0 because the bias covers the most
+                        // negative profile byte, so H = max(t, E, F) is one
+                        // binary16 maximum; the zero clamps become the bias
+                        const uint32_t h = pk_max3f(pk_adds(d, sub), E[r], F);
                         const uint32_t go = pk_subu(h, GO);
-                        E[r] = pk_maxu(pk_subu(E[r], GE), go);
-                        F = pk_maxu(pk_subu(F, GE), go);
+                        E[r] = pk_max3f(pk_subu(E[r], GE), go, KB);
+                        F = pk_max3f(pk_subu(F, GE), go, KB);
                         Ho[r] = h;
                         // two rows per update of the running best
                         if (r & 1) best = pk_max3f(best, Ho[r - 1], h);
@@ -852,7 +861,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 const int slot = atomicAdd(&a.ctr->n_over, 1);
                 a.over[slot] = p[h];
             } else {
-                a.scores[p[h]] = v;
+                a.scores[p[h]] = v - kPkBias;
             }
         }
     }

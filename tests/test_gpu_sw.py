@@ -222,15 +222,16 @@ def test_throughput_full_size_sampled(cm):
 
 def test_packed_saturation_boundary(cm):
     """Scores around the limits of the packed score kernel.  With a +127
-    diagonal, an identical pair of length L scores 127 L.  The running best is
-    exact below 0x7C00 = 31744: 249 residues give 31623 (packed result), 250
-    give 31750 (recomputed by the int32 kernel), 258 give 32766 (recomputed),
-    259 give 32893 (the packed sums saturate; recomputed).  Saturating and
-    ordinary pairs share groups."""
+    diagonal, an identical pair of length L scores 127 L.  Packed values carry
+    a bias of 128 and are exact below 0x7C00 = 31744, i.e. for scores below
+    31616: 248 residues give 31496 (packed result), 249 give 31623 (recomputed
+    by the int32 kernel), 258 give 32766 (recomputed), 259 give 32893 (the
+    packed sums saturate; recomputed).  Saturating and ordinary pairs share
+    groups."""
     M = np.full((20, 20), -7, np.int32)
     np.fill_diagonal(M, 127)
     rng = np.random.default_rng(97)
-    lens = [248, 249, 250, 251, 257, 258, 259, 260, 300, 1000, 4000]
+    lens = [247, 248, 249, 250, 257, 258, 259, 260, 300, 1000, 4000]
     seqs = []
     for L in lens:
         s = rng.integers(0, 20, size=L).astype(np.uint8)
@@ -246,8 +247,8 @@ def test_packed_saturation_boundary(cm):
     cm.sync()
     ref = sw_batch(ds.residues, ds.offsets, pairs, M, with_end=False)
     assert np.array_equal(sc.cpu().numpy(), ref)
-    assert (ref > 32767).sum() > 10 and ((ref >= 31744) & (ref < 32767)).sum() >= 6
-    assert ((ref > 31000) & (ref < 31744)).sum() >= 6
+    assert (ref > 32767).sum() > 10 and ((ref >= 31616) & (ref < 32767)).sum() >= 6
+    assert ((ref > 31000) & (ref < 31616)).sum() >= 6
     ctx = cm.context()
     saved = ctx.get_plan(0)
     try:
