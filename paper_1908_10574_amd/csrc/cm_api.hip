@@ -142,10 +142,16 @@ static cm_status run_pass_q(cm_context* ctx, cmk::SwArgs& a, hipStream_t st, int
     aa.keys = nullptr; aa.order = list_a; aa.n_work_ptr = &ctr->n_sel[0]; aa.ticket = &ctr->ticket;
     aa.rmax = cmk::kRMaxQ;
     bb.keys = kb_s; bb.order = list_b_s; bb.n_work_ptr = &ctr->n_sel[1]; bb.ticket = &ctr->ticket_b;
+    // the two kernels run concurrently: list B's boundary slots follow list A's
+    const int grid_a = ctx->n_cu * ctx->plan[CM_PASS_SCORE].blocks_per_cu;
+    const int grid_b = ctx->n_cu * ctx->occ_pk[cmk::kNumRMaxPk - 1];
+    bb.bnd = a.bnd + static_cast<int64_t>(grid_a) * cmk::kPairsPerWave * a.bnd_stride;
+    if (static_cast<size_t>(grid_a + grid_b) * cmk::kPairsPerWave * a.bnd_stride * sizeof(int2) > ctx->bnd.cap)
+        return fail(CM_EINVAL, "boundary rows too small for the shared-query launch");
     KernelTimer& kt = ctx->timer;
     if (timer_pair >= 0) (void)hipEventRecord(kt.pool[2 * timer_pair], st);
-    e = cmk::launch_sw_pkq(aa, bb, ctx->n_cu * ctx->plan[CM_PASS_SCORE].blocks_per_cu,
-                           ctx->n_cu * ctx->occ_pk[cmk::kNumRMaxPk - 1], ctx->n_cu * ctx->occ_over, st);
+    e = cmk::launch_sw_pkq(aa, bb, grid_a, grid_b, ctx->n_cu * ctx->occ_over, st, ctx->side, ctx->ev_fork,
+                           ctx->ev_join);
     if (e != hipSuccess) return hip_fail(e, "alignment launch");
     if (timer_pair >= 0) {
         (void)hipEventRecord(kt.pool[2 * timer_pair + 1], st);
@@ -466,7 +472,10 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     ctx->occ_over = cmk::sw_over_blocks_per_cu();
     gmax = ctx->occ_over > gmax ? ctx->occ_over : gmax;
     ctx->occ_pkq = cmk::sw_pkq_blocks_per_cu();
-    gmax = ctx->occ_pkq > gmax ? ctx->occ_pkq : gmax;
+    // the shared-query kernel and the two-profile kernel of its second list run
+    // concurrently, each with boundary-row slots of its own
+    const int g_q = ctx->occ_pkq + ctx->occ_pk[cmk::kNumRMaxPk - 1];
+    gmax = g_q > gmax ? g_q : gmax;
     // the score pass defaults to the shared-query packed kernel (items of one
     // query, up to 32 rows per lane; the rest on the two-profile packed kernel)
     ctx->plan[CM_PASS_SCORE].packed = 2;
@@ -489,7 +498,10 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
         delete ctx;
         return fail(CM_ENOMEM, "cannot allocate %zu bytes of boundary rows", bnd_bytes);
     }
-    e = hipDeviceSynchronize();
+    e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { cm_context_destroy(ctx); return hip_fail(e, "context init"); }
     const char* cache = getenv("CM_AUTOTUNE_CACHE");
     if (cache && *cache) (void)load_plans(ctx, cache);   // a missing or corrupt cache keeps the defaults
@@ -514,6 +526,9 @@ void cm_context_destroy(cm_context* ctx) {
     ctx->q_lists.release();
     ctx->extra_release();
     for (hipEvent_t ev : ctx->timer.pool) (void)hipEventDestroy(ev);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->small) (void)hipFree(ctx->small);
     delete ctx;
 }

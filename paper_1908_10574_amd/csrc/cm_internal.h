@@ -110,9 +110,11 @@ hipError_t launch_flags_q(const uint64_t* keys_sorted, const int32_t* start, int
 // two-profile shape keys (a.rmax) of the pairs of a list, skip keys past *count
 hipError_t launch_keys_list(const SwArgs& a, const int32_t* list, const int32_t* count, int64_t n, uint32_t* keys,
                             hipStream_t s);
-// list A on the shared-query kernel, list B (sorted by its shape keys) on the
-// two-profile kernel, then the int32 re-run
+// list A on the shared-query kernel (stream s) and, concurrently, list B
+// (sorted by its shape keys, boundary slots of its own) on the two-profile
+// kernel (stream side, forked from and joined back into s by the two events),
+// then the int32 re-run on s
 hipError_t launch_sw_pkq(const SwArgs& a_list, const SwArgs& b_list, int grid, int grid_b, int grid_over,
-                         hipStream_t s);
+                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join);
 
 }  // namespace cmk

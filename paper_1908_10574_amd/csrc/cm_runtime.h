@@ -66,6 +66,10 @@ struct cm_context {
     cmrt::DeviceBuf drv[12];
     cmrt::KernelTimer timer;
     bool graphs = false;                // capture per-wave launch sequences in hipGraphs
+    // the score pass of plan kind 2 runs its second list on this stream,
+    // forked from and joined back into the caller's stream by the two events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void extra_release() {
         for (auto& b : drv) b.release();
     }

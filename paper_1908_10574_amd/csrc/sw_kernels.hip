@@ -1142,9 +1142,19 @@ hipError_t launch_keys_list(const SwArgs& a, const int32_t* list, const int32_t*
     return hipGetLastError();
 }
 hipError_t launch_sw_pkq(const SwArgs& a_list, const SwArgs& b_list, int grid, int grid_b, int grid_over,
-                         hipStream_t s) {
+                         hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+    // list B runs on the side stream, concurrently with list A: its blocks
+    // take the compute units that list A leaves free (its tail, or the slots
+    // its occupancy leaves); the saturated pairs of both are rescored after
+    // the join
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sw_pk<8>), dim3(grid_b), dim3(64), 0, side, b_list);
     hipLaunchKernelGGL(k_sw_pkq, dim3(grid), dim3(64), 0, s, a_list);
-    hipLaunchKernelGGL((k_sw_pk<8>), dim3(grid_b), dim3(64), 0, s, b_list);
+    e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sw_over, dim3(grid_over), dim3(64), 0, s, a_list);
     return hipGetLastError();
 }
