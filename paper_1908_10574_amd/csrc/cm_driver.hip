@@ -24,8 +24,6 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <unordered_map>
-#include <unordered_set>
 #include <vector>
 
 #include "../../include/cm.h"
@@ -558,14 +556,59 @@ struct Aligner {
 // ---------------------------------------------------------------------------
 // clusters and the Algorithm 1 replay
 // ---------------------------------------------------------------------------
+// open-addressing set of non-negative int32 (element indices)
+class IdSet {
+public:
+    bool has(int32_t x) const {
+        if (slots_.empty()) return false;
+        for (size_t i = slot(x);; i = (i + 1) & mask_) {
+            const int32_t v = slots_[i];
+            if (v == x) return true;
+            if (v < 0) return false;
+        }
+    }
+    // true when x was not in the set
+    bool insert(int32_t x) {
+        if (2 * (size_ + 1) > slots_.size()) grow();
+        size_t i = slot(x);
+        while (slots_[i] >= 0) {
+            if (slots_[i] == x) return false;
+            i = (i + 1) & mask_;
+        }
+        slots_[i] = x;
+        ++size_;
+        return true;
+    }
+    void clear() {
+        if (size_) std::fill(slots_.begin(), slots_.end(), -1);
+        size_ = 0;
+    }
+
+private:
+    size_t slot(int32_t x) const {
+        return static_cast<size_t>((static_cast<uint32_t>(x) * 2654435761u) >> 7) & mask_;
+    }
+    void grow() {
+        std::vector<int32_t> old;
+        old.swap(slots_);
+        slots_.assign(old.empty() ? 16 : 2 * old.size(), -1);
+        mask_ = slots_.size() - 1;
+        size_ = 0;
+        for (int32_t v : old)
+            if (v >= 0) insert(v);
+    }
+    std::vector<int32_t> slots_;
+    size_t mask_ = 0, size_ = 0;
+};
+
 struct Cluster {
     int32_t rep;
     std::vector<int32_t> objs;
-    std::unordered_set<int32_t> mem;
+    IdSet mem;
     void add(int32_t x) {
-        if (mem.insert(x).second) objs.push_back(x);
+        if (mem.insert(x)) objs.push_back(x);
     }
-    bool has(int32_t x) const { return mem.count(x) != 0; }
+    bool has(int32_t x) const { return mem.has(x); }
 };
 
 // representative-pair outcome bits
@@ -648,6 +691,10 @@ private:
     Aligner al_;
     cm_stats st_{};
     bool log_ = false;
+    // speculate's scratch: slot per touched cluster (-1: none), lists and sets
+    std::vector<int32_t> spec_slot_;
+    std::vector<std::vector<int32_t>> spec_list_;
+    std::vector<IdSet> spec_set_;
     double t_spec_ = 0;   // host seconds in speculate (logging)
     std::vector<int32_t> len_;
     std::vector<Cluster> cl_;
@@ -725,22 +772,35 @@ void Driver::simulate(MergeJob& job, const uint8_t* bits) {
 void Driver::speculate(MergeJob& job, std::vector<int32_t>& req) {
     const std::vector<int32_t>& cs1 = sets_[job.set1];
     const std::vector<int32_t>& cs2 = sets_[job.set2];
-    std::unordered_map<int32_t, std::vector<int32_t>> extra;          // simulated additions
-    std::unordered_map<int32_t, std::unordered_set<int32_t>> extra_set;
+    // simulated additions per cluster of the two sets: a slot per cluster
+    // touched, its list in insertion order and its set (reused across calls)
+    const size_t n_slots = cs1.size() + cs2.size();
+    if (spec_list_.size() < n_slots) { spec_list_.resize(n_slots); spec_set_.resize(n_slots); }
+    if (spec_slot_.size() < cl_.size()) spec_slot_.resize(cl_.size(), -1);
+    std::vector<int32_t> touched;
+    auto slot_of = [&](int32_t cid) {
+        if (spec_slot_[cid] < 0) {
+            spec_slot_[cid] = static_cast<int32_t>(touched.size());
+            touched.push_back(cid);
+        }
+        return spec_slot_[cid];
+    };
     auto has = [&](int32_t cid, int32_t m) {
         if (cl_[cid].has(m)) return true;
-        auto it = extra_set.find(cid);
-        return it != extra_set.end() && it->second.count(m) != 0;
+        const int32_t sl = spec_slot_[cid];
+        return sl >= 0 && spec_set_[sl].has(m);
     };
     auto add = [&](int32_t cid, int32_t m) {
-        if (has(cid, m)) return;
-        extra[cid].push_back(m);
-        extra_set[cid].insert(m);
+        if (cl_[cid].has(m)) return;
+        const int32_t sl = slot_of(cid);
+        if (spec_set_[sl].insert(m)) spec_list_[sl].push_back(m);
     };
-    auto members = [&](int32_t cid, std::vector<int32_t>& out) {
-        out = cl_[cid].objs;
-        auto it = extra.find(cid);
-        if (it != extra.end()) out.insert(out.end(), it->second.begin(), it->second.end());
+    // members of a cluster with its simulated additions, visited in order
+    auto for_members = [&](int32_t cid, auto&& f) {
+        for (int32_t x : cl_[cid].objs) f(x);
+        const int32_t sl = spec_slot_[cid];
+        if (sl >= 0)
+            for (int32_t x : spec_list_[sl]) f(x);
     };
     auto want = [&](int32_t m, int32_t rep) {
         int32_t sc;
@@ -755,26 +815,34 @@ void Driver::speculate(MergeJob& job, std::vector<int32_t>& req) {
         }
         return true;   // unknown: assume similar
     };
-    std::vector<int32_t> m1, m2;
+    std::vector<int32_t> to_a, to_b;
     for (size_t k = job.next; k < job.events.size(); ++k) {
         const Event& ev = job.events[k];
         const int32_t a = cs1[ev.i], b = cs2[ev.j];
-        members(a, m1);
-        members(b, m2);
+        // a and b are distinct clusters and the slot lists are sized before
+        // the loop, so one cluster's members can be read while adding to the other
         if (ev.type == kAbsorb21) {
-            for (int32_t x : m1) add(b, x);
+            for_members(a, [&](int32_t x) { add(b, x); });
         } else if (ev.type == kAbsorb12) {
-            for (int32_t x : m2) add(a, x);
+            for_members(b, [&](int32_t x) { add(a, x); });
         } else {
             const int32_t ra = cl_[a].rep, rb = cl_[b].rep;
-            std::vector<int32_t> to_a, to_b;
-            for (int32_t x : m2)
+            to_a.clear();
+            to_b.clear();
+            for_members(b, [&](int32_t x) {
                 if (!has(a, x) && want(x, ra)) to_a.push_back(x);
-            for (int32_t x : m1)
+            });
+            for_members(a, [&](int32_t x) {
                 if (!has(b, x) && want(x, rb)) to_b.push_back(x);
+            });
             for (int32_t x : to_a) add(a, x);
             for (int32_t x : to_b) add(b, x);
         }
+    }
+    for (size_t q = 0; q < touched.size(); ++q) {
+        spec_list_[q].clear();
+        spec_set_[q].clear();
+        spec_slot_[touched[q]] = -1;
     }
 }
 
