@@ -912,14 +912,13 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
     }
 }
 
-// Shared-query packed kernel: items of eight pairs with one query, even rows
+// Shared-query packed kernel: items of eight pairs with one query, any rows
 // per lane up to 32 (strips of up to 512 rows), one LDS profile per wavefront.
 template <int R>
-__device__ __forceinline__ bool run_pkq_if(const SwArgs& a, int Rw, int item, int n_work, const int8_t* s_mat,
-                                           uint8_t* s_prof) {
-    if (Rw != R) return false;
-    run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof);
-    return true;
+__device__ __forceinline__ void run_pkq_range(const SwArgs& a, int Rw, int item, int n_work, const int8_t* s_mat,
+                                              uint8_t* s_prof) {
+    if (Rw == R) run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof);
+    else if constexpr (R < kRMaxQ) run_pkq_range<R + 1>(a, Rw, item, n_work, s_mat, s_prof);
 }
 
 __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
@@ -936,15 +935,8 @@ __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
         if (threadIdx.x == 0) item = atomicAdd(ticket, 1);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
-        const int R = item_rows(a, a.order, item, kPairsPerWavePk, kRMaxQ, true);
-        run_pkq_if<2>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<4>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<6>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<8>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<10>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<12>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<14>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<16>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<18>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<20>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<22>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<24>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<26>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<28>(a, R, item, n_work, s_mat, s_prof) ||
-            run_pkq_if<30>(a, R, item, n_work, s_mat, s_prof) || run_pkq_if<32>(a, R, item, n_work, s_mat, s_prof);
+        const int R = item_rows(a, a.order, item, kPairsPerWavePk, kRMaxQ, false);
+        run_pkq_range<1>(a, R, item, n_work, s_mat, s_prof);
     }
 }
 
@@ -989,7 +981,7 @@ __global__ void k_plan_q(SwArgs a, uint64_t* keys, int32_t* vals) {
             a.scores[p] = 0;
         } else {
             int R, strips;
-            shape_for(static_cast<int>(lx), kRMaxQ, true, R, strips);
+            shape_for(static_cast<int>(lx), kRMaxQ, false, R, strips);
             key = (static_cast<uint64_t>(kRMaxQ - R) << 58) |
                   (static_cast<uint64_t>(255 - min(strips, 255)) << 50) |
                   (static_cast<uint64_t>(static_cast<uint32_t>(x)) << 16) |
