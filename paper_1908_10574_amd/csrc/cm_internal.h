@@ -32,6 +32,11 @@ constexpr int kRMaxQ = 32;
 constexpr int kMatStride = 24;      // bytes per row of the int8 matrix in LDS
 // query-profile bytes per row slot: R rows padded to 4, 8 or 16 bytes
 constexpr int prof_row_bytes(int r) { return r <= 4 ? 4 : (r <= 8 ? 8 : (r <= 16 ? 16 : 32)); }
+// shared-query profile with 16-bit values (up to kR16Max rows per lane):
+// 2 bytes per row, padded to 8
+constexpr int kR16Max = 28;
+constexpr int prof16_row_bytes(int r) { return 8 * ((2 * r + 7) / 8); }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr uint32_t kSkipKey = 0xffffffffu;
 
 // Error bits raised by kernels (reported by cm_context_sync).

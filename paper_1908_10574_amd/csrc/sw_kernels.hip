@@ -563,14 +563,36 @@ __device__ __forceinline__ ProfWords<W> load_prof_at(const uint8_t* p) {
     return r;
 }
 
+// W words of a lane's profile row: 16-bit profiles are 8-byte aligned
+template <int W, bool k16>
+__device__ __forceinline__ ProfWords<W> load_prof_any(const uint8_t* p) {
+    if constexpr (k16) {
+        static_assert(W % 2 == 0, "16-bit profile rows are padded to 8 bytes");
+        ProfWords<W> r;
+#pragma unroll
+        for (int q = 0; q < W; q += 2) {
+            uint2 v = *reinterpret_cast<const uint2*>(p + 4 * q);
+            r.w[q] = v.x; r.w[q + 1] = v.y;
+        }
+        return r;
+    } else {
+        return load_prof_at<W>(p);
+    }
+}
+
 // kShared: the eight pairs of the item share their query (the plan groups
 // them), so one profile serves the whole wavefront; each group builds a
-// quarter of its residue rows.
+// quarter of its residue rows.  Up to kR16Max rows per lane the shared profile
+// holds 16-bit values, so the halves of a register are one v_perm of the two
+// pairs' profile words with no shift; above it, int8 values as in the
+// two-profile kernel (the LDS of eight wavefronts per CU bounds the 16-bit
+// profile at 28 rows per lane).
 template <int R, int RMAXT, bool kShared>
 __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __restrict__ order, int item,
                                             int n_work, const int8_t* __restrict__ s_mat,
                                             uint8_t* __restrict__ s_prof) {
-    constexpr int RP = prof_row_bytes(R);            // bytes of profile per lane and residue
+    constexpr bool k16 = kShared && R <= kR16Max;   // 16-bit shared profile
+    constexpr int RP = k16 ? prof16_row_bytes(R) : prof_row_bytes(R);   // bytes per lane and residue
     constexpr int W = RP / 4;
     constexpr int kRows = kGroup * R;
     constexpr int kColStride = kGroup * RP;          // bytes between the residue rows of a profile
@@ -659,19 +681,27 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
 #pragma unroll
                 for (int h = 0; h < (kShared ? 1 : 2); ++h) {
                     uint32_t w[W];
+                    constexpr int kPer = k16 ? 2 : 4;        // rows per word
 #pragma unroll
                     for (int q = 0; q < W; ++q) {
                         uint32_t word = 0;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const int r = 4 * q + k;
+                        for (int k = 0; k < kPer; ++k) {
+                            const int r = kPer * q + k;
                             const int8_t v = (r < R) ? s_mat[(h ? code1[r] : code0[r]) + c] : int8_t(-128);
-                            word |= static_cast<uint32_t>(static_cast<uint8_t>(v)) << (8 * k);
+                            if constexpr (k16)
+                                word |= static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(v))) << (16 * k);
+                            else
+                                word |= static_cast<uint32_t>(static_cast<uint8_t>(v)) << (8 * k);
                         }
                         w[q] = word;
                     }
                     uint8_t* dst = (h ? prof1 : prof0) + c * kColStride + gl * RP;
-                    if constexpr (W >= 4) {
+                    if constexpr (k16) {
+#pragma unroll
+                        for (int q = 0; q < W; q += 2)
+                            *reinterpret_cast<uint2*>(dst + 4 * q) = make_uint2(w[q], w[q + 1]);
+                    } else if constexpr (W >= 4) {
 #pragma unroll
                         for (int q = 0; q < W; q += 4)
                             *reinterpret_cast<uint4*>(dst + 4 * q) = make_uint4(w[q], w[q + 1], w[q + 2], w[q + 3]);
@@ -726,8 +756,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 nfeed = bnd_raw(kGroup + gl);
             }
             uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR), static_cast<int>(kSentPk)));
-            ProfWords<W> pa0 = load_prof_at<W>(lp0 + (c & 0xffffu));
-            ProfWords<W> pa1 = load_prof_at<W>(lp1 + (c >> 16));
+            ProfWords<W> pa0 = load_prof_any<W, k16>(lp0 + (c & 0xffffu));
+            ProfWords<W> pa1 = load_prof_any<W, k16>(lp1 + (c >> 16));
             ProfWords<W> pb0, pb1;
 
             // One column step t.  Multi-strip: lane 0 takes the top row from
@@ -770,19 +800,25 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                     Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(KB), static_cast<int>(Hout)));
                     F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
                 }
+                constexpr int kPer = k16 ? 2 : 4;            // rows per profile word
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t wa = w0.w[q], wb = w1.w[q];
-                    const uint32_t sa = wa << 8, sb = wb << 8;
+                    const uint32_t sa = k16 ? 0u : wa << 8, sb = k16 ? 0u : wb << 8;
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int r = 4 * q + k;
+                    for (int k = 0; k < kPer; ++k) {
+                        const int r = kPer * q + k;
                         if (r >= R) break;
                         uint32_t sub;
-                        if (k == 0) sub = pk_sbyte<0>(wa, wb, sa, sb);
-                        else if (k == 1) sub = pk_sbyte<1>(wa, wb, sa, sb);
-                        else if (k == 2) sub = pk_sbyte<2>(wa, wb, sa, sb);
-                        else sub = pk_sbyte<3>(wa, wb, sa, sb);
+                        if constexpr (k16) {
+                            // 16-bit rows: (row of pair 0, row of pair 1)
+                            sub = __builtin_amdgcn_perm(wb, wa, k == 0 ? 0x05040100u : 0x07060302u);
+                        } else {
+                            if (k == 0) sub = pk_sbyte<0>(wa, wb, sa, sb);
+                            else if (k == 1) sub = pk_sbyte<1>(wa, wb, sa, sb);
+                            else if (k == 2) sub = pk_sbyte<2>(wa, wb, sa, sb);
+                            else sub = pk_sbyte<3>(wa, wb, sa, sb);
+                        }
                         const uint32_t d = (r == 0) ? hdiag : Hi[r - 1];
                         // biased: t >= 0 because the bias covers the most
                         // negative profile byte, so H = max(t, E, F) is one
@@ -808,8 +844,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 {   // step t (even: never the last step of a 16-column chunk)
                     const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
                     const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
-                    pb0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
-                    pb1 = load_prof_at<W>(lp1 + (cn >> 16));
+                    pb0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
+                    pb1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
                     __builtin_amdgcn_sched_barrier(0);
                     cells(t, HA, HB, pa0, pa1, false, (t & (kGroup - 1)) == 0 && t > 0);
                     feedR = feedR2;
@@ -825,8 +861,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                         feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
                     }
                     const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
-                    pa0 = load_prof_at<W>(lp0 + (cn & 0xffffu));
-                    pa1 = load_prof_at<W>(lp1 + (cn >> 16));
+                    pa0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
+                    pa1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
                     __builtin_amdgcn_sched_barrier(0);
                     cells(t + 1, HB, HA, pb0, pb1, chunk_last, false);
                     feedR = feedR2;
@@ -923,7 +959,8 @@ __device__ __forceinline__ void run_pkq_range(const SwArgs& a, int Rw, int item,
 
 __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
-    __shared__ __attribute__((aligned(16))) uint8_t s_prof[kNRes * kGroup * prof_row_bytes(kRMaxQ)];
+    __shared__ __attribute__((aligned(16))) uint8_t
+        s_prof[kNRes * kGroup * cmax(prof_row_bytes(kRMaxQ), prof16_row_bytes(kR16Max))];
     const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
     if (n_work == 0) return;
     int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
