@@ -212,7 +212,11 @@ typedef struct cm_screen cm_screen;
 
 /* Run ClusterMerge on a device-resident sequence store (seqs, offsets: device
  * pointers as in cm_sw_score_batch).  Synchronous.  `screen` may be NULL
- * (plain method).  *out is library-owned; free it with cm_result_free. */
+ * (plain method).  *out is library-owned; free it with cm_result_free.
+ * Similarity (score >= T) is a property of the unordered pair (Algorithm 1
+ * compares clusters both ways), so the matrix must be symmetric (CM_EINVAL
+ * otherwise); the driver keeps one score per pair and aligns each pair in the
+ * orientation that batches best. */
 cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets,
                               int32_t n_seqs, const cm_params* params, const cm_screen* screen,
                               cm_result** out);

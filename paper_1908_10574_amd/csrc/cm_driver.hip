@@ -723,8 +723,8 @@ void Driver::request_exchange(const Cluster& c1, const Cluster& c2, std::vector<
         const int d = decision(k);
         if (d == 0 || (d == 1 && cache_.find(k, &s)) || pending_.find(k, &s)) return;
         pending_.put(k, 0);
+        req.push_back(rep);   // the representative is the query: one query per exchange
         req.push_back(m);
-        req.push_back(rep);
     };
     for (int32_t m : c2.objs)
         if (!c1.has(m)) want(m, c1.rep);
@@ -810,8 +810,8 @@ void Driver::speculate(MergeJob& job, std::vector<int32_t>& req) {
         if (d == 1 && cache_.find(k, &sc)) return sc >= p_.T;
         if (!pending_.find(k, &sc)) {
             pending_.put(k, 0);
-            req.push_back(m);
             req.push_back(rep);
+            req.push_back(m);
         }
         return true;   // unknown: assume similar
     };
@@ -1410,6 +1410,13 @@ cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_
     int8_t mat8[cmk::kNRes * cmk::kMatStride];
     s = cmrt::check_matrix(params->matrix, mat8);
     if (s != CM_OK) return s;
+    // similarity is a property of the unordered pair: the driver keeps one
+    // score per pair and aligns a pair in whichever orientation batches best
+    for (int x = 0; x < 20; ++x)
+        for (int y = 0; y < x; ++y)
+            if (params->matrix[20 * x + y] != params->matrix[20 * y + x])
+                return cmrt::fail(CM_EINVAL, "ClusterMerge needs a symmetric matrix (M[%d][%d] != M[%d][%d])",
+                                  x, y, y, x);
     if (params->T < 1 || params->mT < 0 || params->mU < 0 || params->max_result_pairs < 0)
         return cmrt::fail(CM_EINVAL, "T must be >= 1; mT, mU and max_result_pairs >= 0");
     if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");

@@ -98,6 +98,19 @@ def test_identical_proteins(cm):
     assert len(g["pairs"]) == 6
 
 
+def test_asymmetric_matrix_rejected(cm):
+    """One score serves both orientations of a pair, so ClusterMerge refuses an
+    asymmetric matrix before any work is enqueued."""
+    ds = cmgen.family_dataset(3, [3] * 3, lambda r: 60, 30, 120, 71)
+    res, off = dev_store(ds)
+    M = ds.matrix.copy()
+    M[2, 5] += 1
+    with pytest.raises(cm.CMError, match="symmetric"):
+        cm.clustermerge_run(res, off, M)
+    g = cm.clustermerge_run(res, off, ds.matrix)     # the symmetric one runs
+    assert g["stats"]["n_clusters"] >= 1
+
+
 @pytest.mark.parametrize("n", [1, 2, 3])
 def test_tiny_inputs(cm, n):
     ds = cmgen.clustermerge_families(n_seqs=n, n_families=1, seed=214, median=80, hi=200) if n > 0 else None
