@@ -142,6 +142,39 @@ def test_long_multistrip_pairs(cm):
     check_exact(cm, ds, pairs, label="long")
 
 
+def test_maximum_length(cm):
+    """Sequences at the longest accepted length (CM_MAX_LEN = 16,384; 32 strips of
+    512 rows in the shared-query kernel, 64 of 256 in the int32 kernels): one
+    query against eight subjects of 14,400-16,384 residues (an item of the
+    shared-query kernel: an identical copy, whose score saturates 16 bits and is
+    re-run in int32, mutated relatives and unrelated proteins), plus short
+    partners.  One residue more is rejected."""
+    rng = np.random.default_rng(113)
+    L = cm.CM_MAX_LEN
+    anc = rng.integers(0, 20, size=L).astype(np.uint8)
+    q = cmgen.mutate(rng, anc)
+    q = np.concatenate([q, rng.integers(0, 20, size=L).astype(np.uint8)])[:L]
+    subs = []
+    for k, n in enumerate((L, L - 1, 16000, 15500, 15000, 14800, 14600, 14400)):
+        if k == 0:
+            s_ = q.copy()                                  # self-score ~ 1.2e5: saturates 16 bits
+        else:
+            s_ = cmgen.mutate(rng, anc) if k % 2 == 0 else rng.integers(0, 20, size=n).astype(np.uint8)
+        subs.append(np.concatenate([s_, rng.integers(0, 20, size=L).astype(np.uint8)])[:n])
+    seqs = [q] + subs + [rng.integers(0, 20, size=n).astype(np.uint8) for n in (1, 17, 300)]
+    ds = cmgen.from_list(seqs)
+    assert ds.lengths().max() == L
+    pairs = np.array([(0, k) for k in range(1, 9)] + [(9, 0), (0, 10), (11, 0), (1, 2)], np.int32)
+    sc = check_exact(cm, ds, pairs, label="max-length")
+    assert sc.max() > 32767 and (sc[1:8] > 20000).sum() >= 3   # a saturated pair re-run in int32
+    too_long = cmgen.from_list([np.zeros(L + 1, np.uint8), np.zeros(5, np.uint8)])
+    res, off, pr = to_dev(too_long, np.array([[0, 1]], np.int32))
+    cm.sw_score_batch(res, off, pr, too_long.matrix)
+    with pytest.raises(cm.CMError) as e:
+        cm.sync()
+    assert e.value.status == cm.CM_ERANGE
+
+
 def test_throughput_workload_sampled(cm):
     """Shapes of the 1M-pair throughput workload: a 4,000-pair slice, every pair checked."""
     ds = cmgen.throughput_pool(n_pool=4000, n_pairs=4000, seed=303)
