@@ -25,7 +25,11 @@
  *  - Pointers documented as "device" are caller-owned device memory; calls
  *    enqueue work on `stream` (a hipStream_t, NULL = the null stream) and return
  *    without waiting.  The caller keeps buffers alive until the stream reaches
- *    the work.  Host pointers are read before the call returns.
+ *    the work.  Host pointers are read before the call returns.  Part of a
+ *    score pass may run on a stream of the context, forked from and joined
+ *    back into `stream` by events, so the call stays ordered on `stream`.  A
+ *    context's scratch serves one call at a time: calls on different streams
+ *    with one context must be ordered by the caller (or use one context each).
  *  - Errors: no C++ exception crosses this ABI.  Argument errors found on the
  *    host are returned immediately and nothing is enqueued.  Data errors found
  *    on the device (residue code >= 20, sequence index out of range, sequence

@@ -696,6 +696,9 @@ private:
     std::vector<std::vector<int32_t>> spec_list_;
     std::vector<IdSet> spec_set_;
     double t_spec_ = 0;   // host seconds in speculate (logging)
+    // representative pairs aligned but not compared by Algorithm 1 (logging):
+    // past a row's break, and against already-absorbed columns
+    int64_t spec_after_break_ = 0, spec_merged_col_ = 0;
     std::vector<int32_t> len_;
     std::vector<Cluster> cl_;
     std::vector<std::vector<int32_t>> sets_;
@@ -741,13 +744,14 @@ void Driver::simulate(MergeJob& job, const uint8_t* bits) {
     for (size_t i = 0; i < cs1.size(); ++i) {
         bool merged1 = false;
         for (size_t j = 0; j < n2; ++j) {
-            if (merged2[j]) continue;
+            if (merged2[j]) { ++spec_merged_col_; continue; }
             ++st_.rep_comparisons;
             const uint8_t b = bits[i * n2 + j];
             if (!(b & kSim)) continue;
             if (b & kT21) {                 // cluster2 absorbs cluster1; leave the inner loop
                 job.events.push_back({kAbsorb21, static_cast<int32_t>(i), static_cast<int32_t>(j)});
                 merged1 = true;
+                spec_after_break_ += static_cast<int64_t>(n2 - j - 1);
                 break;
             }
             if (b & kT12) {                 // cluster1 absorbs cluster2
@@ -1113,10 +1117,14 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     const auto t3 = Clock::now();
     if (log_)
         fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs (prep %.3f submit %.3f wait %.3f) "
-                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f)\n",
+                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f) "
+                "not compared: %lld past a break, %lld absorbed columns\n",
                 jobs.size(), total, secs(t0, t1), secs(t0, ta), secs(ta, tb), secs(tb, t1), secs(t1, t2),
-                secs(t2, t3), waves, n_req, t_rep, t_spec_, t_al);
+                secs(t2, t3), waves, n_req, t_rep, t_spec_, t_al, static_cast<long long>(spec_after_break_),
+                static_cast<long long>(spec_merged_col_));
     t_spec_ = 0;
+    spec_after_break_ = 0;
+    spec_merged_col_ = 0;
     return CM_OK;
 }
 
