@@ -123,6 +123,111 @@ def sampled_recall(cm, res, off, M, clusters, n, k_sample, seed=7, T=120, chunk=
                 sample_s=dt, sample_gcups=cells / dt / 1e9)
 
 
+def truth_pairs(cm, res, off, M, n, T_min, chunk=1 << 24):
+    """Every (x, y), x < y, of the store scoring at least T_min, with its
+    score: the all-vs-all triangle scored on the GPU in row blocks of about
+    `chunk` pairs (pair lists built on the host)."""
+    import numpy as np
+    import torch
+    xs, ys, ss = [], [], []
+    x0 = 0
+    while x0 < n - 1:
+        x1 = x0
+        tot = 0
+        while x1 < n - 1 and tot + (n - 1 - x1) <= max(chunk, n):
+            tot += n - 1 - x1
+            x1 += 1
+        cnt = n - 1 - np.arange(x0, x1)
+        x = np.repeat(np.arange(x0, x1, dtype=np.int64), cnt)
+        start = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        y = np.arange(tot, dtype=np.int64) - np.repeat(start, cnt) + x + 1
+        pr = torch.from_numpy(np.stack([x, y], 1).astype(np.int32)).cuda()
+        sc = cm.sw_score_batch(res, off, pr, M)
+        keep = sc >= T_min
+        xs.append(pr[keep, 0].cpu().numpy())
+        ys.append(pr[keep, 1].cpu().numpy())
+        ss.append(sc[keep].cpu().numpy())
+        x0 = x1
+    return np.concatenate(xs), np.concatenate(ys), np.concatenate(ss)
+
+
+def cluster_profile(clusters):
+    import numpy as np
+    sz = np.array([len(m) for _, m in clusters], np.int64)
+    return dict(n_clusters=int(len(sz)), largest=int(sz.max()) if len(sz) else 0,
+                frac_1_to_4=float((sz <= 4).mean()), frac_over_10=float((sz > 10).mean()),
+                frac_over_100=float((sz > 100).mean()), frac_over_1000=float((sz > 1000).mean()))
+
+
+def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
+    """Sensitivity to T, mT and mU (missed similar pairs and their scores,
+    clusters, comparisons, time) and to family divergence (substitution rate
+    of the members), on the ClusterMerge workload."""
+    import numpy as np
+    import torch
+    import cmgen
+    M = ds.matrix
+    n = ds.n
+    all_pairs = n * (n - 1) // 2
+    g = cm.clustermerge_run(res, off, M)                          # warm
+    t0 = time.perf_counter()
+    tx, ty, ts = truth_pairs(cm, res, off, M, n, 100)
+    t_truth = time.perf_counter() - t0
+    tkey = tx.astype(np.int64) * n + ty
+    marks = [150, 200, 300, 500, 1000]
+
+    def one(T, mT, mU):
+        t = time.perf_counter()
+        g = cm.clustermerge_run(res, off, M, T=T, mT=mT, mU=mU)
+        dt = time.perf_counter() - t
+        st = g["stats"]
+        sel = ts >= T
+        truth_keys, truth_sc = tkey[sel], ts[sel]
+        fp = np.asarray(g["pairs"], np.int64)
+        fkey = np.sort(fp[:, 0] * n + fp[:, 1]) if len(fp) else np.zeros(0, np.int64)
+        pos = np.clip(np.searchsorted(fkey, truth_keys), 0, max(len(fkey) - 1, 0))
+        hit = (fkey[pos] == truth_keys) if len(fkey) else np.zeros(len(truth_keys), bool)
+        miss = truth_sc[~hit]
+        compared = st["rep_comparisons"] + st["exchange_alignments"] + st["final_candidates"]
+        row = dict(T=T, mT=mT, mU=mU, time_s=dt, truth_pairs=int(len(truth_keys)), found_pairs=int(hit.sum()),
+                   recall=float(hit.mean()) if len(hit) else 1.0, missed_pairs=int(len(miss)),
+                   missed_median_score=float(np.median(miss)) if len(miss) else None,
+                   missed_mean_score=float(miss.mean()) if len(miss) else None,
+                   missed_max_score=int(miss.max()) if len(miss) else None,
+                   missed_at_least={str(m): int((miss >= m).sum()) for m in marks},
+                   comparisons=int(compared), comparisons_vs_all_pairs=compared / all_pairs,
+                   aligned_pairs=int(st["aligned_pairs"]), full_merges=int(st["full_merges"]),
+                   exchanges=int(st["exchanges"]))
+        row.update(cluster_profile(g["clusters"]))
+        log(f"sweep T={T} mT={mT} mU={mU}: {dt:.2f} s, recall {row['recall']:.6f}, "
+            f"{row['missed_pairs']} missed (median score {row['missed_median_score']}), {row['n_clusters']} clusters")
+        return row
+
+    rows = [one(T, mT, 15) for T in (100, 120, 140) for mT in (140, 166, 200, 250)]
+    rows += [one(120, 166, mU) for mU in (5, 30, 60)]
+    comp = []
+    for sub in (0.20, 0.30, 0.40):
+        d2 = cmgen.clustermerge_families(n_seqs=n_seqs, n_families=n_families, sub_rate=sub)
+        r2 = torch.from_numpy(d2.residues).cuda()
+        o2 = torch.from_numpy(d2.offsets).cuda()
+        cm.clustermerge_run(r2, o2, d2.matrix, max_result_pairs=0)       # warm
+        t = time.perf_counter()
+        g = cm.clustermerge_run(r2, o2, d2.matrix, max_result_pairs=0)
+        dt = time.perf_counter() - t
+        truth, _ = cm.allvsall_count(r2, o2, d2.matrix)
+        st = g["stats"]
+        compared = st["rep_comparisons"] + st["exchange_alignments"] + st["final_candidates"]
+        row = dict(sub_rate=sub, time_s=dt, recall=st["n_similar_pairs"] / max(truth, 1),
+                   truth_pairs=int(truth), comparisons_vs_all_pairs=compared / all_pairs,
+                   rep_comparisons=int(st["rep_comparisons"]), full_merges=int(st["full_merges"]),
+                   exchanges=int(st["exchanges"]), aligned_cells=float(st["aligned_cells"]))
+        row.update(cluster_profile(g["clusters"]))
+        log(f"composition sub_rate={sub}: {dt:.2f} s, {row['n_clusters']} clusters, recall {row['recall']:.6f}")
+        comp.append(row)
+    return dict(workload=ds.meta.get("workload"), truth_scoring_s=t_truth, all_pairs=all_pairs,
+                parameters=rows, composition=comp)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +246,8 @@ def main():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-throughput", action="store_true")
     ap.add_argument("--no-screen", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark: T / mT / mU and family-divergence sweep (one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device copy first (reference for HBM byte counters)")
     ap.add_argument("--screen-pairs", type=int, default=2000000)
@@ -174,6 +281,10 @@ def main():
     ctx = cm.context()
     torch.cuda.synchronize()
     log(f"store: {ds.n} proteins, {len(ds.residues)} residues")
+
+    if args.sweep:
+        print(json.dumps(dict(sweep=parameter_sweep(cm, ds, res, off, args.n_seqs, args.n_families))), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)

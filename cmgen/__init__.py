@@ -172,20 +172,23 @@ def _pack(seqs, fam, matrix, meta, pairs=None) -> Dataset:
 
 
 def family_dataset(n_families: int, sizes, length_fn, lo: int, hi: int, seed: int,
-                   matrix_seed: int = MATRIX_SEED) -> Dataset:
-    """Families of mutated copies of random ancestors, shuffled by the seed."""
+                   matrix_seed: int = MATRIX_SEED, sub_rate: float = 0.30,
+                   indel_rate: float = 0.05) -> Dataset:
+    """Families of mutated copies of random ancestors, shuffled by the seed
+    (member divergence: substitution and indel rates of ``mutate``)."""
     rng = np.random.default_rng(seed)
     seqs, fam = [], []
     for f in range(n_families):
         L = int(np.clip(length_fn(rng), lo, hi))
         anc = random_residues(rng, L)
         for _ in range(int(sizes[f])):
-            seqs.append(clip(rng, mutate(rng, anc), lo, hi))
+            seqs.append(clip(rng, mutate(rng, anc, sub_rate, indel_rate), lo, hi))
             fam.append(f)
     perm = rng.permutation(len(seqs))
     seqs = [seqs[i] for i in perm]
     fam = np.asarray(fam, dtype=np.int32)[perm]
-    meta = dict(seed=seed, matrix_seed=matrix_seed, n_families=n_families, lo=lo, hi=hi)
+    meta = dict(seed=seed, matrix_seed=matrix_seed, n_families=n_families, lo=lo, hi=hi,
+                sub_rate=sub_rate, indel_rate=indel_rate)
     return _pack(seqs, fam, make_matrix(matrix_seed), meta)
 
 
@@ -214,10 +217,11 @@ def allvsall_small(seed: int = 101) -> Dataset:
 
 def clustermerge_families(n_seqs: int = 20000, n_families: int = 2000, seed: int = 202,
                           median: float = 350.0, sigma: float = 0.6, lo: int = 30,
-                          hi: int = 2000) -> Dataset:
+                          hi: int = 2000, sub_rate: float = 0.30, indel_rate: float = 0.05) -> Dataset:
     """Zipf(1.2) families, lognormal lengths (median 350, sigma 0.6) clipped to [lo, hi]."""
     sizes = zipf_sizes(n_seqs, n_families)
-    ds = family_dataset(n_families, sizes, lognormal_len(median, sigma), lo, hi, seed)
+    ds = family_dataset(n_families, sizes, lognormal_len(median, sigma), lo, hi, seed,
+                        sub_rate=sub_rate, indel_rate=indel_rate)
     ds.meta.update(workload=f"clustermerge-{n_seqs}", median=median, sigma=sigma)
     return ds
 

@@ -128,3 +128,20 @@ def test_screened_replay_special_cases():
                                            min_product=mp)
         assert len(c) == ds.n and p == [] and s.full_merges == 0 and s.exchanges == 0
         assert s.rep_comparisons == ds.n * (ds.n - 1) // 2
+
+
+def test_generator_divergence_parameter():
+    """The family generator's member divergence: the defaults are the workload's
+    rates (0.30 substitutions, 0.05 indel events per position); a different
+    substitution rate keeps the lengths (same indel draws) and changes the
+    fraction of positions that differ from a zero-divergence copy."""
+    base = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17)
+    same = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17, sub_rate=0.30, indel_rate=0.05)
+    assert np.array_equal(base.residues, same.residues) and np.array_equal(base.offsets, same.offsets)
+    none = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17, sub_rate=0.0, indel_rate=0.0)
+    half = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17, sub_rate=0.5, indel_rate=0.0)
+    assert np.array_equal(none.offsets, half.offsets)
+    diff = (none.residues != half.residues).mean()
+    assert 0.45 < diff < 0.55
+    lo = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17, sub_rate=0.2)
+    assert np.array_equal(lo.offsets, base.offsets) and not np.array_equal(lo.residues, base.residues)
