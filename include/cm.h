@@ -180,6 +180,12 @@ typedef struct {
     int64_t screen_min_product;     /* when > 0: representative pairs whose clusters' member
                                        counts (at the start of the merge) multiply to at least
                                        this are aligned without consulting the screen */
+    int64_t rep_chunk_pairs;        /* representative pairs of a level are aligned in column
+                                       chunks of about this many pairs (at most 8 chunks), a row
+                                       leaving Algorithm 1's loop is not aligned against later
+                                       chunks; 0 = about 2^25, < 0 = one batch per level.  Not
+                                       used while a screen covers CM_STAGE_REP.  Results do not
+                                       depend on it. */
 } cm_params;
 
 #define CM_STAGE_REP       1u       /* representative vs representative */

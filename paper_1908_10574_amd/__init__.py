@@ -60,7 +60,7 @@ _lib.cm_sw_span_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P
 class CMParams(ctypes.Structure):
     _fields_ = [("matrix", _i32 * 400), ("gap_open", _i32), ("gap_extend", _i32), ("T", _i32),
                 ("mT", _i32), ("mU", _i32), ("screen_stages", ctypes.c_uint32), ("screen_tau", _f32),
-                ("max_result_pairs", _i64), ("screen_min_product", _i64)]
+                ("max_result_pairs", _i64), ("screen_min_product", _i64), ("rep_chunk_pairs", _i64)]
 
 
 class CMStats(ctypes.Structure):
@@ -280,7 +280,7 @@ def _np_from(ptr, n, dtype):
 
 
 def make_params(matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, screen_stages=0,
-                screen_tau=0.0, max_result_pairs=1 << 62, screen_min_product=0) -> CMParams:
+                screen_tau=0.0, max_result_pairs=1 << 62, screen_min_product=0, rep_chunk_pairs=0) -> CMParams:
     p = CMParams()
     m = _matrix_host(matrix)
     for k in range(400):
@@ -288,12 +288,14 @@ def make_params(matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, scree
     p.gap_open, p.gap_extend, p.T, p.mT, p.mU = int(gap_open), int(gap_extend), int(T), int(mT), int(mU)
     p.screen_stages, p.screen_tau, p.max_result_pairs = int(screen_stages), float(screen_tau), int(max_result_pairs)
     p.screen_min_product = int(screen_min_product)
+    p.rep_chunk_pairs = int(rep_chunk_pairs)
     return p
 
 
 def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1,
                      screen=None, screen_stages=CM_STAGE_REP | CM_STAGE_EXCHANGE, screen_tau=0.0,
-                     max_result_pairs=1 << 62, screen_min_product=0, ctx: Context | None = None):
+                     max_result_pairs=1 << 62, screen_min_product=0, rep_chunk_pairs=0,
+                     ctx: Context | None = None):
     """ClusterMerge on a device-resident store (residues u8, offsets i64: CUDA tensors).
 
     Returns dict(clusters=[(rep, members ndarray)], pairs=ndarray [k,2], scores=ndarray [k],
@@ -305,7 +307,7 @@ def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-
     offsets = _dev(offsets, torch.int64, "offsets")
     torch.cuda.current_stream().synchronize()
     p = make_params(matrix, T, mT, mU, gap_open, gap_extend, screen_stages if screen else 0, screen_tau,
-                    max_result_pairs, screen_min_product)
+                    max_result_pairs, screen_min_product, rep_chunk_pairs)
     res = _P()
     _check(_lib.cm_clustermerge_run(ctx.handle, residues.data_ptr() if residues.numel() else None,
                                     offsets.data_ptr(), offsets.numel() - 1, ctypes.byref(p),

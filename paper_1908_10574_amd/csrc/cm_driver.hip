@@ -653,6 +653,10 @@ public:
 private:
     cm_status load_lengths();
     cm_status merge_level(std::vector<MergeJob>& jobs);
+    // the representative wave of a level: every pair in one batch (with the
+    // screen when it covers this stage), or the columns in chunks
+    cm_status wave_a(std::vector<MergeJob>& jobs, size_t total);
+    cm_status wave_a_chunked(std::vector<MergeJob>& jobs, int chunks);
     void simulate(MergeJob& job, const uint8_t* bits);
     // apply events until done or blocked on missing scores; true when blocked
     bool replay(MergeJob& job, std::vector<int32_t>& req);
@@ -699,6 +703,7 @@ private:
     // representative pairs aligned but not compared by Algorithm 1 (logging):
     // past a row's break, and against already-absorbed columns
     int64_t spec_after_break_ = 0, spec_merged_col_ = 0;
+    double t_prep_ = 0, t_submit_ = 0, t_wait_ = 0, t_bits_ = 0;   // wave A phases (logging)
     std::vector<int32_t> len_;
     std::vector<Cluster> cl_;
     std::vector<std::vector<int32_t>> sets_;
@@ -959,13 +964,186 @@ cm_status Driver::align_requests(std::vector<int32_t>& req) {
 
 cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     const auto t0 = Clock::now();
-    // wave A: all representative pairs, oriented (cs1 rep, cs2 rep), with spans
-    std::vector<int32_t> pairs;
     size_t total = 0;
     for (MergeJob& job : jobs) {
         job.rep_off = total;
         total += sets_[job.set1].size() * sets_[job.set2].size();
     }
+    // a large representative product goes in column chunks (not under a
+    // screen of this stage): default about 2^25 pairs per chunk, at most 8
+    // (each chunk pays the latency of its end-cell and start-cell launches,
+    // so only waves of tens of millions of pairs gain)
+    int chunks = 1;
+    if (!screened(CM_STAGE_REP) && p_.rep_chunk_pairs >= 0) {
+        const int64_t per = p_.rep_chunk_pairs > 0 ? p_.rep_chunk_pairs : (int64_t(1) << 25);
+        chunks = static_cast<int>(std::min<int64_t>(8, (static_cast<int64_t>(total) + per - 1) / per));
+        if (chunks < 1) chunks = 1;
+    }
+    t_prep_ = t_submit_ = t_wait_ = t_bits_ = 0;
+    cm_status s = chunks > 1 ? wave_a_chunked(jobs, chunks) : wave_a(jobs, total);
+    if (s != CM_OK) return s;
+    const auto t2 = Clock::now();
+    // exchange waves
+    std::vector<int32_t> req;
+    int waves = 0;
+    double t_rep = 0, t_al = 0;
+    size_t n_req = 0;
+    while (true) {
+        bool any_blocked = false;
+        auto q0 = Clock::now();
+        for (MergeJob& job : jobs)
+            if (!job.done && replay(job, req)) any_blocked = true;
+        auto q1 = Clock::now();
+        t_rep += secs(q0, q1);
+        if (!any_blocked) break;
+        n_req += req.size() / 2;
+        s = align_requests(req);
+        if (s != CM_OK) return s;
+        t_al += secs(q1, Clock::now());
+        ++waves;
+    }
+    const auto t3 = Clock::now();
+    if (log_)
+        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs in %d chunk(s) (prep %.3f submit %.3f wait %.3f "
+                "bits+simulate %.3f) exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f) "
+                "not compared: %lld past a break, %lld absorbed columns\n",
+                jobs.size(), total, secs(t0, t2), chunks, t_prep_, t_submit_, t_wait_, t_bits_, secs(t2, t3), waves,
+                n_req, t_rep, t_spec_, t_al, static_cast<long long>(spec_after_break_),
+                static_cast<long long>(spec_merged_col_));
+    t_spec_ = 0;
+    spec_after_break_ = 0;
+    spec_merged_col_ = 0;
+    return CM_OK;
+}
+
+// Columns in chunks: chunk c aligns, for every merge of the level, the rows
+// (first-set clusters) still inside Algorithm 1's inner loop against the c-th
+// slice of the second set's columns.  Algorithm 1 advances slice by slice: in
+// a slice, a row's comparisons depend only on the absorbed flags of the
+// slice's columns, which only earlier rows of the same slice set, and on
+// whether the row left the loop in an earlier slice; a row that leaves (its
+// cluster is absorbed) is not aligned against later slices.  The events are
+// put back in row-major order at the end, so the replay is Algorithm 1's.
+cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
+    struct JobState {
+        std::vector<uint8_t> broken, merged2;
+        std::vector<int32_t> rows;          // rows aligned in the current slice
+    };
+    std::vector<JobState> js(jobs.size());
+    for (size_t b = 0; b < jobs.size(); ++b) {
+        js[b].broken.assign(sets_[jobs[b].set1].size(), 0);
+        js[b].merged2.assign(sets_[jobs[b].set2].size(), 0);
+        jobs[b].events.clear();
+        jobs[b].result.clear();
+    }
+    std::vector<int32_t> pairs, out;
+    std::vector<EndRec> ends;
+    std::vector<uint8_t> bits;
+    std::vector<size_t> deferred;
+    for (int c = 0; c < chunks; ++c) {
+        const auto q0 = Clock::now();
+        pairs.clear();
+        for (size_t b = 0; b < jobs.size(); ++b) {
+            const std::vector<int32_t>& cs1 = sets_[jobs[b].set1];
+            const std::vector<int32_t>& cs2 = sets_[jobs[b].set2];
+            const size_t n2 = cs2.size();
+            const size_t c0 = n2 * c / chunks, c1 = n2 * (c + 1) / chunks;
+            js[b].rows.clear();
+            for (size_t i = 0; i < cs1.size(); ++i) {
+                if (js[b].broken[i]) continue;
+                js[b].rows.push_back(static_cast<int32_t>(i));
+                const int32_t ra = cl_[cs1[i]].rep;
+                for (size_t j = c0; j < c1; ++j) {
+                    pairs.push_back(ra);
+                    pairs.push_back(cl_[cs2[j]].rep);
+                }
+            }
+        }
+        const size_t n = pairs.size() / 2;
+        if (n == 0) continue;
+        const auto q1 = Clock::now();
+        cm_status s = al_.submit(0, pairs.data(), static_cast<int64_t>(n), true);
+        if (s != CM_OK) return s;
+        const auto q2 = Clock::now();
+        s = al_.wait_scores(0, out);
+        if (s != CM_OK) return s;
+        bits.assign(n, 0);
+        deferred.clear();
+        for (size_t k = 0; k < n; ++k) {
+            const int32_t sc = out[k];
+            if (sc >= p_.T) {
+                bits[k] = kSim;
+                cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
+            }
+            if (sc > p_.mT) deferred.push_back(k);
+        }
+        s = al_.wait(0, out, &ends);
+        if (s != CM_OK) return s;
+        const auto q3 = Clock::now();
+        if (deferred.size() != ends.size())
+            return fail(CM_EDEVICE, "end records: %zu of %zu", ends.size(), deferred.size());
+        for (size_t qe = 0; qe < deferred.size(); ++qe) {
+            const size_t k = deferred[qe];
+            if (ends[qe].idx != static_cast<int32_t>(k)) return fail(CM_EDEVICE, "missing end record for pair %zu", k);
+            const int32_t u1 = len_[pairs[2 * k]] - (ends[qe].ea - ends[qe].sa + 1);
+            const int32_t u2 = len_[pairs[2 * k + 1]] - (ends[qe].eb - ends[qe].sb + 1);
+            if (u1 < p_.mU) bits[k] |= kT21;
+            if (u2 < p_.mU) bits[k] |= kT12;
+            ++st_.end_pairs;
+        }
+        // Algorithm 1 over this slice, rows in order
+        size_t q = 0;
+        for (size_t b = 0; b < jobs.size(); ++b) {
+            const size_t n2 = sets_[jobs[b].set2].size();
+            const size_t c0 = n2 * c / chunks, c1 = n2 * (c + 1) / chunks;
+            JobState& st = js[b];
+            for (int32_t i : st.rows) {
+                for (size_t j = c0; j < c1; ++j) {
+                    if (st.merged2[j]) { ++spec_merged_col_; continue; }
+                    ++st_.rep_comparisons;
+                    const uint8_t bb = bits[q + (j - c0)];
+                    if (!(bb & kSim)) continue;
+                    if (bb & kT21) {            // cluster2 absorbs cluster1; the row leaves the loop
+                        jobs[b].events.push_back({kAbsorb21, i, static_cast<int32_t>(j)});
+                        st.broken[i] = 1;
+                        spec_after_break_ += static_cast<int64_t>(c1 - j - 1);
+                        break;
+                    }
+                    if (bb & kT12) {            // cluster1 absorbs cluster2
+                        jobs[b].events.push_back({kAbsorb12, i, static_cast<int32_t>(j)});
+                        st.merged2[j] = 1;
+                        continue;
+                    }
+                    jobs[b].events.push_back({kExchange, i, static_cast<int32_t>(j)});
+                }
+                q += c1 - c0;
+            }
+        }
+        const auto q4 = Clock::now();
+        t_prep_ += secs(q0, q1);
+        t_submit_ += secs(q1, q2);
+        t_wait_ += secs(q2, q3);
+        t_bits_ += secs(q3, q4);
+    }
+    for (size_t b = 0; b < jobs.size(); ++b) {
+        MergeJob& job = jobs[b];
+        std::stable_sort(job.events.begin(), job.events.end(),
+                         [](const Event& x, const Event& y) { return x.i != y.i ? x.i < y.i : x.j < y.j; });
+        const std::vector<int32_t>& cs1 = sets_[job.set1];
+        const std::vector<int32_t>& cs2 = sets_[job.set2];
+        for (size_t i = 0; i < cs1.size(); ++i)
+            if (!js[b].broken[i]) job.result.push_back(cs1[i]);
+        for (size_t j = 0; j < cs2.size(); ++j)
+            if (!js[b].merged2[j]) job.result.push_back(cs2[j]);
+    }
+    return CM_OK;
+}
+
+// All representative pairs of the level in one batch, oriented (cs1 rep, cs2
+// rep), with end and start cells for those above mT.
+cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
+    const auto t0 = Clock::now();
+    std::vector<int32_t> pairs;
     pairs.resize(2 * total);
     for (const MergeJob& job : jobs) {
         size_t k = job.rep_off;
@@ -1095,36 +1273,10 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     }
     for (MergeJob& job : jobs) simulate(job, bits.data() + job.rep_off);
     const auto t2 = Clock::now();
-    // exchange waves
-    std::vector<int32_t> req;
-    int waves = 0;
-    double t_rep = 0, t_al = 0;
-    size_t n_req = 0;
-    while (true) {
-        bool any_blocked = false;
-        auto q0 = Clock::now();
-        for (MergeJob& job : jobs)
-            if (!job.done && replay(job, req)) any_blocked = true;
-        auto q1 = Clock::now();
-        t_rep += secs(q0, q1);
-        if (!any_blocked) break;
-        n_req += req.size() / 2;
-        s = align_requests(req);
-        if (s != CM_OK) return s;
-        t_al += secs(q1, Clock::now());
-        ++waves;
-    }
-    const auto t3 = Clock::now();
-    if (log_)
-        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs (prep %.3f submit %.3f wait %.3f) "
-                "bits+simulate=%.3fs exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f) "
-                "not compared: %lld past a break, %lld absorbed columns\n",
-                jobs.size(), total, secs(t0, t1), secs(t0, ta), secs(ta, tb), secs(tb, t1), secs(t1, t2),
-                secs(t2, t3), waves, n_req, t_rep, t_spec_, t_al, static_cast<long long>(spec_after_break_),
-                static_cast<long long>(spec_merged_col_));
-    t_spec_ = 0;
-    spec_after_break_ = 0;
-    spec_merged_col_ = 0;
+    t_prep_ = secs(t0, ta);
+    t_submit_ = secs(ta, tb);
+    t_wait_ = secs(tb, t1);
+    t_bits_ = secs(t1, t2);
     return CM_OK;
 }
 

@@ -27,9 +27,9 @@ def dev_store(ds):
     return res, torch.from_numpy(ds.offsets.copy()).cuda()
 
 
-def run_both(cm, ds, T=120, mT=166, mU=15, ctx=None):
+def run_both(cm, ds, T=120, mT=166, mU=15, ctx=None, rep_chunk_pairs=0):
     res, off = dev_store(ds)
-    g = cm.clustermerge_run(res, off, ds.matrix, T=T, mT=mT, mU=mU, ctx=ctx)
+    g = cm.clustermerge_run(res, off, ds.matrix, T=T, mT=mT, mU=mU, ctx=ctx, rep_chunk_pairs=rep_chunk_pairs)
     clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix, T=T, mT=mT, mU=mU)
     return g, clusters, pairs, st
 
@@ -74,6 +74,24 @@ def test_zipf_families_exact(cm, score_plan):
     assert_same(g, clusters, pairs, st)
     assert st.full_merges > 0 and st.exchanges > 0
     ctx.close()
+
+
+@pytest.mark.parametrize("chunk", [-1, 1, 7, 300])
+def test_chunked_representative_waves_exact(cm, chunk):
+    """The representative pairs of a level aligned in column chunks (rows that
+    left Algorithm 1's loop dropped from later chunks) give the oracle's result
+    exactly; chunking only removes alignments that the replay never reads."""
+    ds = cmgen.clustermerge_families(n_seqs=500, n_families=50, seed=212, median=120, hi=400)
+    g, clusters, pairs, st = run_both(cm, ds, rep_chunk_pairs=chunk)
+    assert_same(g, clusters, pairs, st)
+    one = cm.clustermerge_run(*dev_store(ds), ds.matrix, rep_chunk_pairs=-1)
+    assert g["stats"]["speculative_pairs"] <= one["stats"]["speculative_pairs"]
+    if chunk in (1, 7):
+        assert g["stats"]["aligned_pairs"] < one["stats"]["aligned_pairs"]
+    for mT, mU in ((10**6, 15), (120, 400)):
+        d2 = cmgen.clustermerge_families(n_seqs=160, n_families=20, seed=213, median=100, hi=300)
+        g2, c2, p2, s2 = run_both(cm, d2, mT=mT, mU=mU, rep_chunk_pairs=chunk)
+        assert_same(g2, c2, p2, s2)
 
 
 @pytest.mark.parametrize("mT,mU", [(10**6, 15), (120, 400), (166, 0)])
@@ -205,8 +223,8 @@ def test_graph_replay_exact(cm):
     ctx.set_graphs(True)
     res, off = dev_store(ds)
     clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix)
-    for _ in range(3):
-        g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+    for chunk in (0, 0, 3):
+        g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx, rep_chunk_pairs=chunk)
         assert_same(g, clusters, pairs, st)
     ctx.close()
 
