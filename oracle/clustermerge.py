@@ -221,6 +221,31 @@ def clustermerge(residues, offsets, M, T=120, mT=166, mU=15, go=-11, ge=-1):
     return clusters, pairs, stats
 
 
+def clustermerge_extend(residues, offsets, M, prev, n_prev, T=120, mT=166, mU=15, go=-11, ge=-1):
+    """Incremental classification of new elements against an existing
+    clustering (the concluding remark of the paper: new sequences classified
+    against the clusters already formed).  Reading: elements 0..n_prev-1 are
+    clustered by `prev` (a list of (rep, members), e.g. a previous final set);
+    the new elements n_prev..n-1 are clustered among themselves with
+    Algorithm 2, and that set is merged into the previous one with one
+    Algorithm 1 merge, the previous set first; then the final stage over the
+    combined clusters.  Returns (clusters, similar pairs, stats of the new
+    work)."""
+    n = len(offsets) - 1
+    judge = ProteinJudge(residues, offsets, M, T, mT, mU, go, ge)
+    stats = Stats()
+    q = deque([[Cluster(e, [e])] for e in range(n_prev, n)])
+    while len(q) > 1:
+        cs1 = q.popleft()
+        cs2 = q.popleft()
+        q.append(merge(cs1, cs2, judge, stats))
+    new_set = q.popleft() if q else []
+    prev_set = [Cluster(int(r), [int(x) for x in m]) for r, m in prev]
+    final = merge(prev_set, new_set, judge, stats) if new_set else prev_set
+    pairs = similar_pairs(final, judge.score, T)
+    return final, pairs, stats
+
+
 def allvsall(residues, offsets, M, T=120, go=-11, ge=-1):
     """Ground truth: every (x, y), x < y, with score >= T."""
     from .sw import sw_batch

@@ -145,3 +145,54 @@ def test_generator_divergence_parameter():
     assert 0.45 < diff < 0.55
     lo = cmgen.family_dataset(4, [5] * 4, lambda r: 300, 30, 2000, 17, sub_rate=0.2)
     assert np.array_equal(lo.offsets, base.offsets) and not np.array_equal(lo.residues, base.residues)
+
+
+def _as_prev(clusters):
+    return [(c.rep, list(c.objs)) for c in clusters]
+
+
+def test_extend_from_nothing_is_clustermerge():
+    """With no previous elements, incremental classification is ClusterMerge."""
+    ds = cmgen.clustermerge_families(n_seqs=40, n_families=6, seed=221, median=90, hi=200)
+    c1, p1, s1 = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    c2, p2, s2 = cm.clustermerge_extend(ds.residues, ds.offsets, ds.matrix, [], 0)
+    assert _as_prev(c1) == _as_prev(c2) and p1 == p2
+    assert (s1.rep_comparisons, s1.exchange_alignments, s1.full_merges, s1.exchanges) == \
+           (s2.rep_comparisons, s2.exchange_alignments, s2.full_merges, s2.exchanges)
+
+
+def test_extend_without_new_elements_keeps_the_clustering():
+    ds = cmgen.clustermerge_families(n_seqs=40, n_families=6, seed=222, median=90, hi=200)
+    c1, p1, _ = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    c2, p2, s2 = cm.clustermerge_extend(ds.residues, ds.offsets, ds.matrix, _as_prev(c1), ds.n)
+    assert _as_prev(c2) == _as_prev(c1) and p2 == p1 and s2.rep_comparisons == 0
+
+
+def test_extend_with_a_copy_of_a_representative():
+    """A new protein identical to a representative covers it completely with a
+    score far above mT, so the new singleton absorbs that representative's
+    cluster (the second set's cluster is tested as absorber first) and becomes
+    its representative; the number of clusters is unchanged."""
+    ds = cmgen.clustermerge_families(n_seqs=30, n_families=5, seed=223, median=150, hi=300)
+    c1, _, _ = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    big = max(c1, key=lambda c: len(c.objs))
+    copy = ds.seq(big.rep).copy()
+    d2 = cmgen.from_list([ds.seq(i) for i in range(ds.n)] + [copy], ds.matrix)
+    c2, _, s2 = cm.clustermerge_extend(d2.residues, d2.offsets, d2.matrix, _as_prev(c1), ds.n)
+    assert len(c2) == len(c1)
+    mine = [c for c in c2 if c.rep == ds.n]
+    assert len(mine) == 1 and mine[0].objs == [ds.n] + big.objs
+    assert s2.full_merges >= 1
+
+
+def test_extend_never_transitive_compares_every_pair_once():
+    """mT out of reach: no full merge, so every new element meets every other
+    new element and every previous cluster exactly once as representatives."""
+    ds = cmgen.clustermerge_families(n_seqs=36, n_families=6, seed=224, median=80, hi=160)
+    n_prev = 24
+    c1, _, _ = cm.clustermerge(ds.residues[: ds.offsets[n_prev]], ds.offsets[: n_prev + 1], ds.matrix, mT=10**6)
+    assert len(c1) == n_prev
+    c2, pairs, s2 = cm.clustermerge_extend(ds.residues, ds.offsets, ds.matrix, _as_prev(c1), n_prev, mT=10**6)
+    n_new = ds.n - n_prev
+    assert s2.rep_comparisons == n_new * (n_new - 1) // 2 + n_prev * n_new
+    assert s2.full_merges == 0 and len(c2) == ds.n
