@@ -203,6 +203,26 @@ def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
             f"{row['missed_pairs']} missed (median score {row['missed_median_score']}), {row['n_clusters']} clusters")
         return row
 
+    # incremental classification: the last 5% of the proteins against a
+    # clustering of the first 95%
+    n_prev = n - n // 20
+    prev = cm.clustermerge_run(res, off[: n_prev + 1].contiguous(), M)
+    t = time.perf_counter()
+    ext = cm.clustermerge_extend(res, off, M, prev["clusters"], n_prev, prev["pairs"], prev["scores"])
+    t_ext = time.perf_counter() - t
+    sel = ts >= 120
+    fp = np.asarray(ext["pairs"], np.int64)
+    fkey = np.sort(fp[:, 0] * n + fp[:, 1])
+    hit = np.isin(tkey[sel], fkey, assume_unique=True)
+    new_truth = sel & (ty >= n_prev)                 # true pairs involving a new protein
+    hit_new = np.isin(tkey[new_truth], fkey, assume_unique=True)
+    st = ext["stats"]
+    incremental = dict(n_prev=n_prev, n_new=n - n_prev, time_s=t_ext, prev_time_s=prev["stats"]["t_total_s"],
+                       recall=float(hit.mean()), recall_pairs_with_new=float(hit_new.mean()),
+                       n_clusters=int(st["n_clusters"]), rep_comparisons=int(st["rep_comparisons"]),
+                       aligned_pairs=int(st["aligned_pairs"]), cache_hits=int(st["cache_hits"]))
+    log(f"incremental: {n - n_prev} proteins against {n_prev} in {t_ext:.2f} s, recall {incremental['recall']:.6f} "
+        f"(pairs with a new protein {incremental['recall_pairs_with_new']:.6f})")
     rows = [one(T, mT, 15) for T in (100, 120, 140) for mT in (140, 166, 200, 250)]
     rows += [one(120, 166, mU) for mU in (5, 30, 60)]
     comp = []
@@ -225,7 +245,7 @@ def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
         log(f"composition sub_rate={sub}: {dt:.2f} s, {row['n_clusters']} clusters, recall {row['recall']:.6f}")
         comp.append(row)
     return dict(workload=ds.meta.get("workload"), truth_scoring_s=t_truth, all_pairs=all_pairs,
-                parameters=rows, composition=comp)
+                incremental=incremental, parameters=rows, composition=comp)
 
 
 def main():

@@ -230,6 +230,27 @@ typedef struct cm_screen cm_screen;
 cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets,
                               int32_t n_seqs, const cm_params* params, const cm_screen* screen,
                               cm_result** out);
+/* Classify new proteins against an existing clustering (the paper's
+ * Conclusion: new sequences classified against the clusters already formed;
+ * the procedure is this library's reading).  Elements 0..n_prev-1 of the
+ * store are clustered by the previous result, given as host arrays in the
+ * layout of cm_result_clusters (n_clusters clusters; cluster c has
+ * representative reps[c] and members members[member_offsets[c] ..
+ * member_offsets[c+1]), each previous element in at least one cluster, the
+ * representative among the members, no member twice in a cluster).  The new
+ * elements n_prev..n_seqs-1 are clustered among themselves with Algorithm 2;
+ * that set is merged into the previous set with one Algorithm 1 merge (the
+ * previous set first); the final stage then runs over all resulting clusters.
+ * known_pairs / known_scores (host, n_known rows, e.g. the previous result's
+ * similar pairs) are scores already computed: they are reused, not realigned.
+ * Same parameters, screen and result as cm_clustermerge_run; the statistics
+ * count the new work.  CM_EINVAL for an inconsistent previous clustering. */
+cm_status cm_clustermerge_extend(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets,
+                                 int32_t n_seqs, const cm_params* params, const cm_screen* screen,
+                                 int32_t n_prev, int32_t n_clusters, const int32_t* reps,
+                                 const int64_t* member_offsets, const int32_t* members,
+                                 int64_t n_known, const int32_t* known_pairs,
+                                 const int32_t* known_scores, cm_result** out);
 /* Final clusters in final-set order; members of cluster k are
  * members[member_offsets[k] .. member_offsets[k+1]) in cluster order. */
 cm_status cm_result_clusters(const cm_result* r, int32_t* n_clusters, const int32_t** reps,

@@ -77,6 +77,9 @@ class CMStats(ctypes.Structure):
 
 _lib.cm_clustermerge_run.restype = _i32
 _lib.cm_clustermerge_run.argtypes = [_P, _P, _P, _i32, ctypes.POINTER(CMParams), _P, ctypes.POINTER(_P)]
+_lib.cm_clustermerge_extend.restype = _i32
+_lib.cm_clustermerge_extend.argtypes = [_P, _P, _P, _i32, ctypes.POINTER(CMParams), _P, _i32, _i32, _P, _P, _P,
+                                        _i64, _P, _P, ctypes.POINTER(_P)]
 _lib.cm_result_clusters.restype = _i32
 _lib.cm_result_clusters.argtypes = [_P, ctypes.POINTER(_i32), ctypes.POINTER(_P), ctypes.POINTER(_P),
                                     ctypes.POINTER(_P)]
@@ -312,6 +315,11 @@ def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-
     _check(_lib.cm_clustermerge_run(ctx.handle, residues.data_ptr() if residues.numel() else None,
                                     offsets.data_ptr(), offsets.numel() - 1, ctypes.byref(p),
                                     screen.handle if screen is not None else None, ctypes.byref(res)))
+    return _take_result(res)
+
+
+def _take_result(res):
+    """Copy a library-owned cm_result into Python objects and free it."""
     try:
         nc = _i32()
         reps, moff, mem = _P(), _P(), _P()
@@ -332,6 +340,42 @@ def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-
     finally:
         _lib.cm_result_free(res)
     return dict(clusters=clusters, pairs=pairs, scores=scores, stats=stats)
+
+
+def clustermerge_extend(residues, offsets, matrix, prev_clusters, n_prev, known_pairs=None, known_scores=None,
+                        T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, screen=None,
+                        screen_stages=CM_STAGE_REP | CM_STAGE_EXCHANGE, screen_tau=0.0, max_result_pairs=1 << 62,
+                        screen_min_product=0, rep_chunk_pairs=0, ctx: Context | None = None):
+    """Classify proteins n_prev.. of the store against a previous clustering of
+    proteins 0..n_prev-1 (prev_clusters: [(rep, members)], e.g. the "clusters"
+    of a clustermerge_run result); known_pairs [k,2] / known_scores [k] (e.g.
+    its "pairs" / "scores") are reused.  Returns the same dict as
+    clustermerge_run.  Synchronous."""
+    import torch
+    ctx = ctx or context()
+    residues = _dev(residues, torch.uint8, "residues")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    torch.cuda.current_stream().synchronize()
+    p = make_params(matrix, T, mT, mU, gap_open, gap_extend, screen_stages if screen else 0, screen_tau,
+                    max_result_pairs, screen_min_product, rep_chunk_pairs)
+    reps = np.ascontiguousarray([int(r) for r, _ in prev_clusters], dtype=np.int32)
+    sizes = np.array([len(m) for _, m in prev_clusters], dtype=np.int64)
+    moff = np.zeros(len(prev_clusters) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=moff[1:])
+    mem = (np.ascontiguousarray(np.concatenate([np.asarray(m, np.int32) for _, m in prev_clusters]))
+           if len(prev_clusters) else np.zeros(1, np.int32))
+    kp = np.ascontiguousarray(known_pairs if known_pairs is not None else np.zeros((0, 2)), dtype=np.int32)
+    ks = np.ascontiguousarray(known_scores if known_scores is not None else np.zeros(0), dtype=np.int32)
+    if len(kp) != len(ks):
+        raise ValueError("known_pairs and known_scores differ in length")
+    res = _P()
+    _check(_lib.cm_clustermerge_extend(ctx.handle, residues.data_ptr() if residues.numel() else None,
+                                       offsets.data_ptr(), offsets.numel() - 1, ctypes.byref(p),
+                                       screen.handle if screen is not None else None, int(n_prev),
+                                       len(prev_clusters), reps.ctypes.data, moff.ctypes.data, mem.ctypes.data,
+                                       len(ks), kp.ctypes.data if len(kp) else None,
+                                       ks.ctypes.data if len(ks) else None, ctypes.byref(res)))
+    return _take_result(res)
 
 
 def allvsall_count(residues, offsets, matrix, T=120, gap_open=-11, gap_extend=-1, ctx: Context | None = None):

@@ -632,8 +632,22 @@ struct MergeJob {
     std::vector<int32_t> result;  // clusters of the new set, in Algorithm 1 order
 };
 
+// A previous clustering of elements 0..n_prev-1 (host arrays, validated by the
+// caller) and the scores it already knows.
+struct PrevClustering {
+    int32_t n_prev = 0, n_clusters = 0;
+    const int32_t* reps = nullptr;
+    const int64_t* member_offsets = nullptr;
+    const int32_t* members = nullptr;
+    int64_t n_known = 0;
+    const int32_t* known_pairs = nullptr;
+    const int32_t* known_scores = nullptr;
+};
+
 class Driver {
 public:
+    // classify elements prev.n_prev..n-1 against `prev` instead of clustering from singletons
+    void set_prev(const PrevClustering* prev) { prev_ = prev; }
     Driver(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n, const cm_params* p,
            const cm_screen* scr)
         : ctx_(ctx), n_(n), p_(*p), scr_(scr) {
@@ -695,6 +709,7 @@ private:
     Aligner al_;
     cm_stats st_{};
     bool log_ = false;
+    const PrevClustering* prev_ = nullptr;
     // speculate's scratch: slot per touched cluster (-1: none), lists and sets
     std::vector<int32_t> spec_slot_;
     std::vector<std::vector<int32_t>> spec_list_;
@@ -1461,33 +1476,59 @@ cm_status Driver::run(cm_result** out) {
         if (s != CM_OK) return s;
         if (hipStreamSynchronize(al_.st) != hipSuccess) return fail(CM_EDEVICE, "features");
     }
-    // Algorithm 2: singleton sets 0..n-1, FIFO merge order, grouped by tree level
-    cl_.resize(n_);
-    sets_.assign(n_, {});
-    std::vector<int32_t> level(n_, 0);
-    for (int32_t e = 0; e < n_; ++e) {
-        cl_[e].rep = e;
-        cl_[e].add(e);
-        sets_[e].push_back(e);
+    // Algorithm 2: singleton sets of the elements to cluster, FIFO merge
+    // order, grouped by tree level.  Classifying new elements against a
+    // previous clustering: the new elements' tree, then one merge of the
+    // previous final set (first) with its result.
+    const int32_t first = prev_ ? prev_->n_prev : 0;
+    const int32_t n_new = n_ - first;
+    const int32_t n_old_cl = prev_ ? prev_->n_clusters : 0;
+    cl_.resize(static_cast<size_t>(n_old_cl) + n_new);
+    for (int32_t c = 0; c < n_old_cl; ++c) {
+        cl_[c].rep = prev_->reps[c];
+        for (int64_t k = prev_->member_offsets[c]; k < prev_->member_offsets[c + 1]; ++k)
+            cl_[c].add(prev_->members[k]);
+    }
+    sets_.assign(n_new, {});
+    std::vector<int32_t> level(n_new, 0);
+    for (int32_t e = 0; e < n_new; ++e) {
+        const int32_t cid = n_old_cl + e;
+        cl_[cid].rep = first + e;
+        cl_[cid].add(first + e);
+        sets_[e].push_back(cid);
     }
     std::vector<std::vector<MergeJob>> by_level;
+    auto add_job = [&](int32_t x, int32_t y) {
+        const int32_t z = static_cast<int32_t>(level.size());
+        const int32_t lv = std::max(level[x], level[y]) + 1;
+        level.push_back(lv);
+        sets_.emplace_back();
+        if (static_cast<int32_t>(by_level.size()) < lv) by_level.resize(lv);
+        MergeJob job;
+        job.set1 = x;
+        job.set2 = y;
+        job.out = z;
+        by_level[lv - 1].push_back(job);
+        return z;
+    };
     {
-        std::vector<int32_t> q(n_);
-        for (int32_t e = 0; e < n_; ++e) q[e] = e;
+        std::vector<int32_t> q(n_new);
+        for (int32_t e = 0; e < n_new; ++e) q[e] = e;
         size_t head = 0;
         while (q.size() - head > 1) {
             const int32_t x = q[head++], y = q[head++];
-            const int32_t z = static_cast<int32_t>(level.size());
-            const int32_t lv = std::max(level[x], level[y]) + 1;
-            level.push_back(lv);
+            q.push_back(add_job(x, y));
+        }
+        if (prev_) {
+            const int32_t p_set = static_cast<int32_t>(sets_.size());
             sets_.emplace_back();
-            q.push_back(z);
-            if (static_cast<int32_t>(by_level.size()) < lv) by_level.resize(lv);
-            MergeJob job;
-            job.set1 = x;
-            job.set2 = y;
-            job.out = z;
-            by_level[lv - 1].push_back(job);
+            level.push_back(0);
+            for (int32_t c = 0; c < n_old_cl; ++c) sets_[p_set].push_back(c);
+            if (n_new > 0) add_job(p_set, q[head]);
+            // the previous run's scores (similar pairs) are known
+            for (int64_t k = 0; k < prev_->n_known; ++k)
+                cache_.put(unordered_key(prev_->known_pairs[2 * k], prev_->known_pairs[2 * k + 1]),
+                           prev_->known_scores[k]);
         }
     }
     st_.rounds = static_cast<int64_t>(by_level.size());
@@ -1500,7 +1541,7 @@ cm_status Driver::run(cm_result** out) {
             std::vector<int32_t>().swap(sets_[job.set2]);
         }
     }
-    if (n_ == 0) sets_.emplace_back();
+    if (sets_.empty()) sets_.emplace_back();
     const auto t1 = Clock::now();
     cm_result* res = new cm_result();
     s = final_stage(res);
@@ -1560,11 +1601,7 @@ __global__ void k_count_ge(const int32_t* scores, int64_t count, int32_t T, unsi
 
 extern "C" {
 
-cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
-                              const cm_params* params, const cm_screen* screen, cm_result** out) {
-    if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
-    if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
-    *out = nullptr;
+static cm_status check_run_params(const cm_params* params) {
     cm_status s = cmrt::check_gaps(params->gap_open, params->gap_extend);
     if (s != CM_OK) return s;
     int8_t mat8[cmk::kNRes * cmk::kMatStride];
@@ -1579,8 +1616,75 @@ cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_
                                   x, y, y, x);
     if (params->T < 1 || params->mT < 0 || params->mU < 0 || params->max_result_pairs < 0)
         return cmrt::fail(CM_EINVAL, "T must be >= 1; mT, mU and max_result_pairs >= 0");
+    return CM_OK;
+}
+
+cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                              const cm_params* params, const cm_screen* screen, cm_result** out) {
+    if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
+    if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
+    *out = nullptr;
+    cm_status s = check_run_params(params);
+    if (s != CM_OK) return s;
     if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");
     cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params, screen);
+    return drv.run(out);
+}
+
+cm_status cm_clustermerge_extend(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                                 const cm_params* params, const cm_screen* screen, int32_t n_prev,
+                                 int32_t n_clusters, const int32_t* reps, const int64_t* member_offsets,
+                                 const int32_t* members, int64_t n_known, const int32_t* known_pairs,
+                                 const int32_t* known_scores, cm_result** out) {
+    if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
+    if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
+    *out = nullptr;
+    cm_status s = check_run_params(params);
+    if (s != CM_OK) return s;
+    if (n_prev < 0 || n_prev > n_seqs || n_clusters < 0 || n_known < 0)
+        return cmrt::fail(CM_EINVAL, "n_prev must be in [0, n_seqs]; n_clusters, n_known >= 0");
+    if (n_prev > 0 && n_clusters == 0) return cmrt::fail(CM_EINVAL, "previous elements without clusters");
+    if (n_clusters > 0 && (!reps || !member_offsets || !members))
+        return cmrt::fail(CM_EINVAL, "NULL previous clustering");
+    if (n_known > 0 && (!known_pairs || !known_scores)) return cmrt::fail(CM_EINVAL, "NULL known pairs");
+    // every previous element in at least one cluster, members in range and
+    // unique within their cluster, each representative a member of its cluster
+    if (n_clusters > 0 && member_offsets[0] != 0) return cmrt::fail(CM_EINVAL, "member_offsets[0] != 0");
+    std::vector<int32_t> seen(static_cast<size_t>(n_prev), -1);
+    std::vector<uint8_t> covered(static_cast<size_t>(n_prev), 0);
+    for (int32_t c = 0; c < n_clusters; ++c) {
+        const int64_t b = member_offsets[c], e = member_offsets[c + 1];
+        if (e <= b) return cmrt::fail(CM_EINVAL, "cluster %d is empty or its offsets decrease", c);
+        bool rep_in = false;
+        for (int64_t k = b; k < e; ++k) {
+            const int32_t x = members[k];
+            if (x < 0 || x >= n_prev) return cmrt::fail(CM_EINVAL, "cluster %d: member %d outside [0, n_prev)", c, x);
+            if (seen[x] == c) return cmrt::fail(CM_EINVAL, "cluster %d: member %d listed twice", c, x);
+            seen[x] = c;
+            covered[x] = 1;
+            rep_in |= (x == reps[c]);
+        }
+        if (!rep_in) return cmrt::fail(CM_EINVAL, "cluster %d: representative %d is not a member", c, reps[c]);
+    }
+    for (int32_t x = 0; x < n_prev; ++x)
+        if (!covered[x]) return cmrt::fail(CM_EINVAL, "previous element %d is in no cluster", x);
+    for (int64_t k = 0; k < n_known; ++k) {
+        const int32_t x = known_pairs[2 * k], y = known_pairs[2 * k + 1];
+        if (x < 0 || y < 0 || x >= n_prev || y >= n_prev || x == y)
+            return cmrt::fail(CM_EINVAL, "known pair %lld out of range", static_cast<long long>(k));
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");
+    cmdrv::PrevClustering prev;
+    prev.n_prev = n_prev;
+    prev.n_clusters = n_clusters;
+    prev.reps = reps;
+    prev.member_offsets = member_offsets;
+    prev.members = members;
+    prev.n_known = n_known;
+    prev.known_pairs = known_pairs;
+    prev.known_scores = known_scores;
+    cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params, screen);
+    drv.set_prev(&prev);
     return drv.run(out);
 }
 

@@ -116,6 +116,46 @@ def test_identical_proteins(cm):
     assert len(g["pairs"]) == 6
 
 
+@pytest.mark.parametrize("n_prev", [0, 1, 150, 400, 500])
+def test_extend_exact(cm, n_prev):
+    """New proteins classified against a previous clustering (Algorithm 2 over
+    the new ones, one Algorithm 1 merge into the previous set, final stage):
+    the GPU gives the oracle's clusters, pairs and statistics, and reuses the
+    previous run's scores."""
+    ds = cmgen.clustermerge_families(n_seqs=500, n_families=50, seed=212, median=120, hi=400)
+    res, off = dev_store(ds)
+    prev = cm.clustermerge_run(res, off[: n_prev + 1].contiguous(), ds.matrix) if n_prev else None
+    pc = [(r, list(m)) for r, m in prev["clusters"]] if prev else []
+    kw = dict(known_pairs=prev["pairs"], known_scores=prev["scores"]) if prev else {}
+    g = cm.clustermerge_extend(res, off, ds.matrix, pc, n_prev, **kw)
+    clusters, pairs, st = ocm.clustermerge_extend(ds.residues, ds.offsets, ds.matrix, pc, n_prev)
+    assert_same(g, clusters, pairs, st)
+    if 0 < n_prev < ds.n:
+        assert g["stats"]["cache_hits"] >= len(prev["pairs"]) // 2
+    if n_prev == 0:
+        full = cm.clustermerge_run(res, off, ds.matrix)
+        assert [(r, list(m)) for r, m in full["clusters"]] == [(r, list(m)) for r, m in g["clusters"]]
+
+
+def test_extend_rejects_inconsistent_clustering(cm):
+    ds = cmgen.clustermerge_families(n_seqs=60, n_families=8, seed=215, median=100, hi=200)
+    res, off = dev_store(ds)
+    prev = cm.clustermerge_run(res, off[:41].contiguous(), ds.matrix)
+    pc = [(r, list(m)) for r, m in prev["clusters"]]
+    bad_cases = [
+        pc[1:] if len(pc) > 1 else [],                                  # an element in no cluster
+        [(pc[0][0], [x for x in pc[0][1] if x != pc[0][0]] or [45])] + pc[1:],   # rep not a member / out of range
+        [(pc[0][0], pc[0][1] + [pc[0][1][0]])] + pc[1:],               # a member listed twice
+    ]
+    for bad in bad_cases:
+        with pytest.raises(cm.CMError):
+            cm.clustermerge_extend(res, off, ds.matrix, bad, 40)
+    with pytest.raises(cm.CMError):
+        cm.clustermerge_extend(res, off, ds.matrix, pc, 40, known_pairs=np.array([[0, 50]]), known_scores=[7])
+    g = cm.clustermerge_extend(res, off, ds.matrix, pc, 40)           # the consistent one runs
+    assert g["stats"]["n_clusters"] >= 1
+
+
 def test_asymmetric_matrix_rejected(cm):
     """One score serves both orientations of a pair, so ClusterMerge refuses an
     asymmetric matrix before any work is enqueued."""
