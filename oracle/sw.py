@@ -32,6 +32,8 @@ def _lib():
         L.oracle_sw_batch.argtypes = [P, P, P, i64, P, i32, i32, P, P, P]
         L.oracle_span_batch.restype = i64
         L.oracle_span_batch.argtypes = [P, P, P, i64, P, i32, i32, P]
+        L.oracle_traceback_batch.restype = i64
+        L.oracle_traceback_batch.argtypes = [P, P, P, i64, P, i32, i32, P, P, P, P]
         _LIB = L
     return _LIB
 
@@ -101,3 +103,30 @@ def span_batch(residues, offsets, pairs, M, go=-11, ge=-1):
         if bad:
             raise AssertionError(f"oracle reverse pass failed on {bad} pairs")
     return out
+
+
+def traceback_batch(residues, offsets, pairs, M, go=-11, ge=-1, span=None):
+    """Alignment columns ('M', 'I', 'D', start to end) of each pair's optimal
+    local alignment between its start and end cells (``sw_oracle.c``,
+    oracle_sw_traceback).  span: the [n][5] rows of span_batch (computed when
+    None).  Returns (list of str, span rows)."""
+    res = np.ascontiguousarray(residues, dtype=np.uint8)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    if span is None:
+        span = span_batch(res, off, pr, M, go, ge)
+    span = np.ascontiguousarray(span, dtype=np.int32)
+    cap = np.where(span[:, 0] > 0, (span[:, 1] - span[:, 3] + 1) + (span[:, 2] - span[:, 4] + 1), 0)
+    op_off = np.zeros(len(pr) + 1, np.int64)
+    np.cumsum(cap, out=op_off[1:])
+    ops = np.zeros(max(int(op_off[-1]), 1), np.uint8)
+    n_ops = np.zeros(len(pr), np.int32)
+    if len(pr):
+        bad = _lib().oracle_traceback_batch(res.ctypes.data if len(res) else None, off.ctypes.data,
+                                            pr.ctypes.data, len(pr), _mat(M).ctypes.data, go, ge,
+                                            span.ctypes.data, op_off.ctypes.data, ops.ctypes.data,
+                                            n_ops.ctypes.data)
+        if bad:
+            raise AssertionError(f"oracle traceback failed on {bad} pairs")
+    out = [bytes(ops[op_off[p]:op_off[p] + n_ops[p]]).decode() for p in range(len(pr))]
+    return out, span

@@ -138,3 +138,103 @@ int64_t oracle_span_batch(const uint8_t* res, const int64_t* off, const int32_t*
     }
     return bad;
 }
+
+/* Traceback of the optimal local alignment between its start cell (sa, sb)
+ * and end cell (ea, eb), score S > 0 (a reading: the paper's final stage
+ * records scores only and leaves alignments to later analysis).  Every optimal
+ * local alignment with these ends begins and ends with an aligned pair (a
+ * leading or trailing gap only lowers the score), so it is a global alignment
+ * of a[sa..ea] with b[sb..eb] that starts and ends with aligned pairs, and
+ * the best such global alignment scores exactly S.  Three Gotoh states over
+ * the box (r = i - sa, c = j - sb):
+ *   Mt[r][c] = s(a_i, b_j) + max(Mt, X, Y)[r-1][c-1]    (Mt[0][0] = s: the start)
+ *   X[r][c]  = max(Mt[r-1][c] + go, X[r-1][c] + ge, Y[r-1][c] + go)   a_i against a gap ('I')
+ *   Y[r][c]  = max(Mt[r][c-1] + go, Y[r][c-1] + ge, X[r][c-1] + go)   a gap against b_j ('D')
+ * Cells outside the box are -infinity.  The walk starts in Mt at the end cell
+ * and, where several predecessors give a state's value, takes Mt first, then
+ * the state's own extension, then the other gap state.  The columns are
+ * written start to end as 'M', 'I', 'D'.  Returns the number of columns, -1
+ * if the end value is not S, -2 if cap is too small. */
+int32_t oracle_sw_traceback(const uint8_t* a, const uint8_t* b, const int32_t* M, int32_t go, int32_t ge,
+                            int32_t S, int32_t sa, int32_t sb, int32_t ea, int32_t eb, char* ops, int32_t cap)
+{
+    const int32_t R = ea - sa + 1, C = eb - sb + 1;
+    const size_t cells = (size_t)R * (size_t)C;
+    int32_t* Mt = (int32_t*)malloc(cells * sizeof(int32_t));
+    int32_t* X = (int32_t*)malloc(cells * sizeof(int32_t));
+    int32_t* Y = (int32_t*)malloc(cells * sizeof(int32_t));
+#define AT(T, r, c) (((r) < 0 || (c) < 0) ? ORACLE_NEG_INF : (T)[(size_t)(r) * C + (c)])
+    for (int32_t r = 0; r < R; ++r) {
+        for (int32_t c = 0; c < C; ++c) {
+            const int32_t s = M[20 * a[sa + r] + b[sb + c]];
+            int32_t d;
+            if (r == 0 && c == 0) d = 0;
+            else d = imax(imax(AT(Mt, r - 1, c - 1), AT(X, r - 1, c - 1)), AT(Y, r - 1, c - 1));
+            Mt[(size_t)r * C + c] = d <= ORACLE_NEG_INF ? ORACLE_NEG_INF : d + s;
+            X[(size_t)r * C + c] = imax(imax(AT(Mt, r - 1, c) + go, AT(X, r - 1, c) + ge), AT(Y, r - 1, c) + go);
+            Y[(size_t)r * C + c] = imax(imax(AT(Mt, r, c - 1) + go, AT(Y, r, c - 1) + ge), AT(X, r, c - 1) + go);
+            if (X[(size_t)r * C + c] < ORACLE_NEG_INF) X[(size_t)r * C + c] = ORACLE_NEG_INF;
+            if (Y[(size_t)r * C + c] < ORACLE_NEG_INF) Y[(size_t)r * C + c] = ORACLE_NEG_INF;
+        }
+    }
+    int32_t n_ops = -1;
+    if (Mt[cells - 1] == S) {
+        char* rev = (char*)malloc((size_t)(R + C));
+        int32_t k = 0, r = R - 1, c = C - 1, state = 0;   /* 0 = Mt, 1 = X, 2 = Y */
+        for (;;) {
+            if (state == 0) {
+                rev[k++] = 'M';
+                if (r == 0 && c == 0) break;
+                const int32_t v = Mt[(size_t)r * C + c] - M[20 * a[sa + r] + b[sb + c]];
+                if (AT(Mt, r - 1, c - 1) == v) state = 0;
+                else if (AT(X, r - 1, c - 1) == v) state = 1;
+                else state = 2;
+                --r; --c;
+            } else if (state == 1) {
+                rev[k++] = 'I';
+                const int32_t v = X[(size_t)r * C + c];
+                if (AT(Mt, r - 1, c) + go == v) state = 0;
+                else if (AT(X, r - 1, c) + ge == v) state = 1;
+                else state = 2;
+                --r;
+            } else {
+                rev[k++] = 'D';
+                const int32_t v = Y[(size_t)r * C + c];
+                if (AT(Mt, r, c - 1) + go == v) state = 0;
+                else if (AT(Y, r, c - 1) + ge == v) state = 2;
+                else state = 1;
+                --c;
+            }
+        }
+        if (k > cap) n_ops = -2;
+        else {
+            for (int32_t q = 0; q < k; ++q) ops[q] = rev[k - 1 - q];
+            n_ops = k;
+        }
+        free(rev);
+    }
+#undef AT
+    free(Mt);
+    free(X);
+    free(Y);
+    return n_ops;
+}
+
+/* Batch: out5 rows are (score, end_a, end_b, start_a, start_b) as written by
+ * oracle_span_batch; pair p's columns go to ops[op_off[p] ..], their number to
+ * n_ops[p] (0 when the score is 0).  Returns the number of failed pairs. */
+int64_t oracle_traceback_batch(const uint8_t* res, const int64_t* off, const int32_t* pairs, int64_t n_pairs,
+                               const int32_t* M, int32_t go, int32_t ge, const int32_t* out5,
+                               const int64_t* op_off, char* ops, int32_t* n_ops)
+{
+    int64_t bad = 0;
+    for (int64_t p = 0; p < n_pairs; ++p) {
+        const int32_t* q = out5 + 5 * p;
+        if (q[0] <= 0) { n_ops[p] = 0; continue; }
+        const int32_t x = pairs[2 * p], y = pairs[2 * p + 1];
+        n_ops[p] = oracle_sw_traceback(res + off[x], res + off[y], M, go, ge, q[0], q[3], q[4], q[1], q[2],
+                                       ops + op_off[p], (int32_t)(op_off[p + 1] - op_off[p]));
+        bad += n_ops[p] < 0;
+    }
+    return bad;
+}

@@ -209,3 +209,137 @@ def test_family_members_are_similar():
     anc = rng.integers(0, 20, size=350).astype(np.uint8)
     s = [sw(cmgen.mutate(rng, anc), cmgen.mutate(rng, anc), M0)[0] for _ in range(6)]
     assert min(s) > 200, s
+
+
+# ---- traceback (alignment columns between the start and end cells) ----
+
+def _columns_score(a, b, cols, sa, sb, M, go, ge):
+    """Score of an alignment given as columns, summed directly: matrix entries
+    of aligned pairs, go + (k-1) ge for every maximal run of k gap columns of
+    one kind.  Also returns the end cell reached."""
+    i, j, s, prev = sa, sb, 0, None
+    for ch in cols:
+        if ch == "M":
+            s += int(M[a[i], b[j]])
+            i += 1
+            j += 1
+        elif ch == "I":
+            s += ge if prev == "I" else go
+            i += 1
+        else:
+            s += ge if prev == "D" else go
+            j += 1
+        prev = ch
+    return s, i - 1, j - 1
+
+
+def test_traceback_columns_score_and_box():
+    """Random related and unrelated pairs: the columns start and end with an
+    aligned pair, consume exactly the [start, end] box, and score S."""
+    import cmgen
+    from oracle import traceback_batch
+    rng = np.random.default_rng(301)
+    fam = cmgen.family_dataset(6, [4] * 6, lambda r: int(r.integers(30, 300)), 1, 400, 302)
+    pairs = cmgen.random_pairs(rng, fam.n, 150)
+    for go, ge in ((-11, -1), (-5, -5), (-3, 0)):
+        ops, span = traceback_batch(fam.residues, fam.offsets, pairs, fam.matrix, go, ge)
+        for (x, y), cols, (S, ea, eb, sa, sb) in zip(pairs, ops, span):
+            if S == 0:
+                assert cols == ""
+                continue
+            assert cols[0] == "M" and cols[-1] == "M"
+            s, ei, ej = _columns_score(fam.seq(x), fam.seq(y), cols, sa, sb, fam.matrix, go, ge)
+            assert (s, ei, ej) == (S, ea, eb)
+
+
+def test_traceback_identical_sequences_all_aligned():
+    import cmgen
+    from oracle import traceback_batch
+    rng = np.random.default_rng(303)
+    a = rng.integers(0, 20, size=120).astype(np.uint8)
+    ds = cmgen.from_list([a, a.copy()])
+    ops, span = traceback_batch(ds.residues, ds.offsets, np.array([[0, 1]], np.int32), ds.matrix)
+    assert ops[0] == "M" * 120 and tuple(span[0][3:]) == (0, 0)
+
+
+def _all_alignments(R, C):
+    """Every global alignment of an R x C box as a column string."""
+    out = []
+
+    def rec(r, c, acc):
+        if r == R and c == C:
+            out.append("".join(acc))
+            return
+        if r < R and c < C:
+            acc.append("M"); rec(r + 1, c + 1, acc); acc.pop()
+        if r < R:
+            acc.append("I"); rec(r + 1, c, acc); acc.pop()
+        if c < C:
+            acc.append("D"); rec(r, c + 1, acc); acc.pop()
+    rec(0, 0, [])
+    return out
+
+
+def _preferred(u, v):
+    """The walk from the end keeps, at the first column (from the end) where
+    two optimal alignments differ, an aligned pair first, then the gap kind of
+    the column after it, then the other kind (after an aligned pair: 'I' before
+    'D')."""
+    ru, rv = u[::-1], v[::-1]
+    for k in range(min(len(ru), len(rv))):
+        if ru[k] != rv[k]:
+            state = ru[k - 1] if k else "M"
+            order = {"M": "MID", "I": "MID", "D": "MDI"}[state]
+            return u if order.index(ru[k]) < order.index(rv[k]) else v
+    return u if len(u) <= len(v) else v
+
+
+def test_traceback_brute_force_tie_break():
+    """Tiny pairs, ties provoked (zero-score residue pairs, repeats): the oracle's
+    columns are the optimal alignment of the box chosen by the walk's
+    preference among all global alignments of the box."""
+    import cmgen
+    from oracle import traceback_batch
+    M = cmgen.make_matrix().copy()
+    M[0, 1] = M[1, 0] = 0
+    M[2, 3] = M[3, 2] = 0
+    rng = np.random.default_rng(304)
+    seqs = [rng.integers(0, 4, size=int(rng.integers(1, 7))).astype(np.uint8) for _ in range(40)]
+    seqs += [np.array([5, 5, 0, 5, 5], np.uint8), np.array([5, 5, 5, 5], np.uint8)]
+    # repeats around a gap make its position ambiguous (several optimal alignments)
+    crafted = [([6, 5, 5, 7], [6, 5, 7]), ([6, 5, 5, 5, 7], [6, 5, 7]), ([6, 8, 8, 7], [6, 8, 7]),
+               ([6, 5, 7], [6, 5, 5, 7]), ([6, 5, 5, 7, 9, 9], [6, 5, 7, 9]), ([9, 6, 6, 9], [9, 6, 9, 9]),
+               ([6, 5, 5, 7, 8, 8, 9], [6, 5, 7, 8, 9])]
+    # a very negative mismatch between cheap gaps: 'I' then 'D' ties 'D' then 'I'
+    off = M.astype(np.int64) + 1000 * np.eye(20, dtype=np.int64)
+    u, v = (int(t) for t in np.unravel_index(np.argmin(off[4:, 4:]), (16, 16)))
+    u, v = u + 4, v + 4
+    crafted += [([6, u, 7], [6, v, 7]), ([6, u, u, 7], [6, v, v, 7]), ([9, u, 9, 9], [9, v, 9, 9])]
+    base = len(seqs)
+    for u, v in crafted:
+        seqs += [np.array(u, np.uint8), np.array(v, np.uint8)]
+    ds = cmgen.from_list(seqs, M)
+    pairs = cmgen.random_pairs(rng, ds.n, 300)
+    extra = [(base + 2 * k, base + 2 * k + 1) for k in range(len(crafted))]
+    pairs = np.concatenate([pairs, np.array(extra + [(y, x) for x, y in extra], np.int32)])
+    checked = 0
+    several = 0
+    for go, ge in ((-11, -1), (-2, -1), (-3, -3), (-1, -1)):
+        ops, span = traceback_batch(ds.residues, ds.offsets, pairs, M, go, ge)
+        for (x, y), cols, (S, ea, eb, sa, sb) in zip(pairs, ops, span):
+            if S == 0:
+                continue
+            a, b = ds.seq(x), ds.seq(y)
+            best, n_opt = None, 0
+            for cand in _all_alignments(ea - sa + 1, eb - sb + 1):
+                if cand[0] != "M" or cand[-1] != "M":
+                    continue
+                s, _, _ = _columns_score(a, b, cand, sa, sb, M, go, ge)
+                assert s <= S
+                if s == S:
+                    n_opt += 1
+                    best = cand if best is None else _preferred(best, cand)
+            assert best == cols, (x, y, go, ge, cols, best)
+            checked += 1
+            several += n_opt > 1
+    assert checked > 200 and several >= 10
