@@ -151,6 +151,50 @@ def truth_pairs(cm, res, off, M, n, T_min, chunk=1 << 24):
     return np.concatenate(xs), np.concatenate(ys), np.concatenate(ss)
 
 
+def traceback_rate(cm, ds, res, off, found, n_gpu=200000, n_cpu=300, seed=11):
+    """Alignment columns of found pairs: GPU rate on a sample of n_gpu pairs
+    (score + end, start, columns timed separately) and the oracle's rate on
+    n_cpu of them; rates in box cells per second."""
+    import numpy as np
+    import torch
+    from oracle import traceback_batch
+    rng = np.random.default_rng(seed)
+    pick = found[rng.choice(len(found), size=min(n_gpu, len(found)), replace=False)]
+    pr = torch.from_numpy(np.ascontiguousarray(pick, dtype=np.int32)).cuda()
+    M = ds.matrix
+    times = {}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sc, ea, eb = cm.sw_score_batch(res, off, pr, M, return_end=True)
+    torch.cuda.synchronize()
+    times["score_end_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    sa, sb = cm.sw_span_batch(res, off, pr, M, sc, ea, eb, 0)
+    torch.cuda.synchronize()
+    times["span_s"] = time.perf_counter() - t
+    t = time.perf_counter()
+    ops, op_off, n_ops = cm.sw_traceback_batch(res, off, pr, M, sc, ea, eb, sa, sb)
+    torch.cuda.synchronize()
+    times["traceback_s"] = time.perf_counter() - t
+    cm.sync()
+    box = ((ea - sa + 1).double() * (eb - sb + 1).double() * (sc > 0).double()).sum().item()
+    cols = int(n_ops.clamp(min=0).sum().item())
+    sub = pick[:n_cpu]
+    t = time.perf_counter()
+    want, _ = traceback_batch(ds.residues, ds.offsets, sub, M)
+    t_cpu = time.perf_counter() - t
+    spans = torch.stack([sc, ea, eb, sa, sb], 1)[:n_cpu].cpu().numpy().astype(np.float64)
+    cpu_box = float(((spans[:, 1] - spans[:, 3] + 1) * (spans[:, 2] - spans[:, 4] + 1) * (spans[:, 0] > 0)).sum())
+    got = cm.columns_as_strings(ops[: int(op_off[n_cpu].item()) or 1], op_off[: n_cpu + 1], n_ops[:n_cpu])
+    out = dict(pairs=int(len(pick)), box_cells=box, columns=cols, gpu_box_cells_per_s=box / times["traceback_s"],
+               cpu_baseline=dict(value=cpu_box / t_cpu, unit="box cells/s", cores=1, kind="oracle",
+                                 sample=f"the first {len(sub)} sampled pairs, C oracle traceback"),
+               agrees_with_oracle_on_sample=bool(got == want), **times)
+    log(f"traceback: {len(pick)} found pairs, {box:.3g} box cells in {times['traceback_s']:.3f} s "
+        f"({out['gpu_box_cells_per_s'] / 1e9:.1f} G cells/s); oracle {cpu_box / t_cpu / 1e6:.1f} M cells/s")
+    return out
+
+
 def cluster_profile(clusters):
     import numpy as np
     sz = np.array([len(m) for _, m in clusters], np.int64)
@@ -170,6 +214,7 @@ def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
     n = ds.n
     all_pairs = n * (n - 1) // 2
     g = cm.clustermerge_run(res, off, M)                          # warm
+    traceback = traceback_rate(cm, ds, res, off, g["pairs"])
     t0 = time.perf_counter()
     tx, ty, ts = truth_pairs(cm, res, off, M, n, 100)
     t_truth = time.perf_counter() - t0
@@ -245,7 +290,7 @@ def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
         log(f"composition sub_rate={sub}: {dt:.2f} s, {row['n_clusters']} clusters, recall {row['recall']:.6f}")
         comp.append(row)
     return dict(workload=ds.meta.get("workload"), truth_scoring_s=t_truth, all_pairs=all_pairs,
-                incremental=incremental, parameters=rows, composition=comp)
+                incremental=incremental, traceback=traceback, parameters=rows, composition=comp)
 
 
 def main():

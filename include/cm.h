@@ -147,6 +147,31 @@ cm_status cm_sw_span_batch(cm_context* ctx,
                            int32_t min_score, int32_t* start_a, int32_t* start_b,
                            void* stream);
 
+/* Alignment columns of found pairs (the final stage records scores; the
+ * alignments themselves are left to later analysis, Section 6.1): for every
+ * pair with score > 0 (inputs as written by cm_sw_score_batch and
+ * cm_sw_span_batch: score, end cell, start cell; device i32 [n_pairs] each),
+ * the optimal local alignment between its start and end cells, as the Gotoh
+ * global alignment of a[start_a..end_a] with b[start_b..end_b] that begins
+ * and ends with an aligned pair (it scores exactly the pair's score).  Where
+ * several such alignments tie, the walk back from the end prefers an aligned
+ * pair, then the gap kind it is in, then the other kind.  Columns are written
+ * start to end to ops[op_offsets[p] ..] as bytes 'M' (aligned pair), 'I'
+ * (a residue of a against a gap) and 'D' (a gap against a residue of b), and
+ * their number to n_ops[p] (0 when the score is 0, -1 when the pair was
+ * rejected).  op_offsets (device i64 [n_pairs + 1], caller-computed) must give
+ * every pair with score > 0 at least (end_a - start_a + 1) + (end_b - start_b
+ * + 1) bytes.  The call waits for its work on `stream` (scratch of one byte per
+ * box cell, bounded per launch).  Bad indices, cells or capacities make the
+ * pair's n_ops -1 and are reported by cm_context_sync as CM_ERANGE. */
+cm_status cm_sw_traceback_batch(cm_context* ctx,
+                                const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                                const int32_t* pairs, int64_t n_pairs,
+                                const int32_t* matrix, int32_t gap_open, int32_t gap_extend,
+                                const int32_t* scores, const int32_t* end_a, const int32_t* end_b,
+                                const int32_t* start_a, const int32_t* start_b,
+                                const int64_t* op_offsets, uint8_t* ops, int32_t* n_ops, void* stream);
+
 
 /* ---------------------------------------------------------------------------
  * ClusterMerge (Algorithm 2 "BottomUpMerge" over Algorithm 1 "Cluster Set

@@ -77,6 +77,9 @@ class CMStats(ctypes.Structure):
 
 _lib.cm_clustermerge_run.restype = _i32
 _lib.cm_clustermerge_run.argtypes = [_P, _P, _P, _i32, ctypes.POINTER(CMParams), _P, ctypes.POINTER(_P)]
+_lib.cm_sw_traceback_batch.restype = _i32
+_lib.cm_sw_traceback_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                       _P]
 _lib.cm_clustermerge_extend.restype = _i32
 _lib.cm_clustermerge_extend.argtypes = [_P, _P, _P, _i32, ctypes.POINTER(CMParams), _P, _i32, _i32, _P, _P, _P,
                                         _i64, _P, _P, ctypes.POINTER(_P)]
@@ -269,6 +272,41 @@ def sw_span_batch(residues, offsets, pairs, matrix, scores, end_a, end_b, min_sc
                                  end_a.data_ptr(), end_b.data_ptr(), int(min_score), sa.data_ptr(),
                                  sb.data_ptr(), _stream_ptr(stream)))
     return sa, sb
+
+
+def sw_traceback_batch(residues, offsets, pairs, matrix, scores, end_a, end_b, start_a, start_b,
+                       gap_open: int = -11, gap_extend: int = -1, ctx: Context | None = None, stream=None):
+    """Alignment columns ('M', 'I', 'D', start to end) of the pairs' optimal
+    local alignments between their start and end cells.  Returns (ops u8,
+    op_offsets i64 [n+1], n_ops i32) as tensors on the pairs' device; pair p's
+    columns are ops[op_offsets[p] : op_offsets[p] + n_ops[p]]."""
+    import torch
+    ctx = ctx or context()
+    residues = _dev(residues, torch.uint8, "residues")
+    offsets = _dev(offsets, torch.int64, "offsets")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    n_pairs = pairs.numel() // 2
+    cap = torch.where(scores > 0, (end_a - start_a + 1) + (end_b - start_b + 1), torch.zeros_like(scores))
+    op_off = torch.zeros(n_pairs + 1, dtype=torch.int64, device=pairs.device)
+    if n_pairs:
+        op_off[1:] = torch.cumsum(cap.clamp(min=0).to(torch.int64), 0)
+    ops = torch.zeros(max(int(op_off[-1].item()), 1), dtype=torch.uint8, device=pairs.device)
+    n_ops = torch.zeros(n_pairs, dtype=torch.int32, device=pairs.device)
+    m = _matrix_host(matrix)
+    _check(_lib.cm_sw_traceback_batch(ctx.handle, residues.data_ptr() if residues.numel() else None,
+                                      offsets.data_ptr(), offsets.numel() - 1, pairs.data_ptr(), n_pairs,
+                                      m.ctypes.data, int(gap_open), int(gap_extend), scores.data_ptr(),
+                                      end_a.data_ptr(), end_b.data_ptr(), start_a.data_ptr(), start_b.data_ptr(),
+                                      op_off.data_ptr(), ops.data_ptr(), n_ops.data_ptr(), _stream_ptr(stream)))
+    return ops, op_off, n_ops
+
+
+def columns_as_strings(ops, op_off, n_ops):
+    """Host strings of sw_traceback_batch's output."""
+    o = ops.cpu().numpy()
+    off = op_off.cpu().numpy()
+    n = n_ops.cpu().numpy()
+    return [bytes(o[off[p]:off[p] + max(n[p], 0)]).decode() for p in range(len(n))]
 
 
 def sync(ctx: Context | None = None):

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcm.so")
-SOURCES = ["cm_api.hip", "sw_kernels.hip", "cm_driver.hip", "cm_screen.hip", "screen_kernels.hip", "cm_tune.hip"]
+SOURCES = ["cm_api.hip", "sw_kernels.hip", "cm_driver.hip", "cm_screen.hip", "screen_kernels.hip", "cm_tune.hip",
+           "cm_traceback.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -546,11 +546,14 @@ cm_status cm_context_sync(cm_context* ctx) {
         const uint32_t zero = 0;
         (void)hipMemcpy(ctx->err_flag, &zero, sizeof(zero), hipMemcpyHostToDevice);
         if (flag & cmk::kErrPlan) return fail(CM_EDEVICE, "internal error: an item's pairs do not share its query");
-        return fail(CM_ERANGE, "device flagged bad input:%s%s%s%s",
+        if (flag & cmk::kErrTrace)
+            return fail(CM_EDEVICE, "traceback: a box does not reproduce its pair's score (inconsistent cells)");
+        return fail(CM_ERANGE, "device flagged bad input:%s%s%s%s%s",
                     (flag & cmk::kErrResidue) ? " residue>=20" : "",
                     (flag & cmk::kErrIndex) ? " index out of range" : "",
                     (flag & cmk::kErrLength) ? " sequence longer than CM_MAX_LEN" : "",
-                    (flag & cmk::kErrCell) ? " end cell outside its sequence" : "");
+                    (flag & cmk::kErrCell) ? " end cell outside its sequence" : "",
+                    (flag & cmk::kErrCapacity) ? " column buffer too small" : "");
     }
     return CM_OK;
 }

@@ -45,6 +45,8 @@ constexpr uint32_t kErrIndex = 2u;       // pair index outside [0, n_seqs)
 constexpr uint32_t kErrLength = 4u;      // sequence longer than CM_MAX_LEN
 constexpr uint32_t kErrCell = 8u;        // span input end cell outside its sequence
 constexpr uint32_t kErrPlan = 16u;       // internal: an item's pairs do not share the shape the plan promised
+constexpr uint32_t kErrCapacity = 32u;   // traceback: a pair's share of the column buffer is too small
+constexpr uint32_t kErrTrace = 64u;      // traceback: the box does not reproduce the pair's score
 
 // Counters block in device memory.
 struct Counters {

@@ -61,6 +61,7 @@ struct cm_context {
     cmrt::DeviceBuf bnd;                // boundary rows between strips
     cmrt::DeviceBuf over;               // saturated pairs of the packed kernel
     cmrt::DeviceBuf q_start, q_len, q_flags, q_lists;   // shared-query plan scratch
+    cmrt::DeviceBuf tb_meta, tb_offs, tb_dir, tb_rows;  // traceback scratch
     int32_t bnd_stride = 0;
     // buffers of the ClusterMerge driver and the screen (released with the context)
     cmrt::DeviceBuf drv[12];
@@ -72,6 +73,10 @@ struct cm_context {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void extra_release() {
         for (auto& b : drv) b.release();
+        tb_meta.release();
+        tb_offs.release();
+        tb_dir.release();
+        tb_rows.release();
     }
 };
 
