@@ -14,9 +14,9 @@
 // state; the walk back from Mt at the end cell gives the columns, written
 // start to end as 'M', 'I', 'D'.
 //
-// Not a hot-path kernel: one thread per pair runs the box row by row, keeps
-// one row of the three states and one predecessor byte per cell in scratch,
-// then walks back.  Batches are split so that the scratch stays bounded.
+// Not a hot-path kernel: one lane per pair runs the box row by row, keeps one
+// row of the three states and one predecessor byte per cell in scratch, then
+// walks back.  Batches are split so that the scratch stays bounded.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,7 +30,10 @@
 namespace cmtb {
 
 constexpr int32_t kNegInf = -(1 << 30);
-constexpr int64_t kScratchCells = int64_t(1) << 30;   // predecessor bytes per launch
+// predecessor bytes per launch: one byte per cell of every lane's share of its
+// wavefront's largest box, so the bound sets how many wavefronts run at once
+// (the buffer is released when the call returns)
+constexpr int64_t kScratchCells = int64_t(16) << 30;
 
 struct Matrix { int32_t m[400]; };
 
@@ -71,60 +74,117 @@ __global__ void k_tb_box(TbArgs a, int64_t n, int64_t* cells, int32_t* cols) {
     cols[p] = static_cast<int32_t>(C);
 }
 
-// one thread per pair of [p0, p1): the box, then the walk back
-__global__ void k_tb(TbArgs a, Matrix mat, int64_t p0, int64_t p1, const int64_t* cells, const int64_t* dir_off,
-                     const int64_t* row_off, uint8_t* dir_base, int32_t* row_base) {
-    const int64_t p = p0 + blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (p >= p1 || cells[p] == 0) return;
-    const int32_t x = a.pairs[2 * p], y = a.pairs[2 * p + 1];
-    const int32_t sa = a.start_a[p], sb = a.start_b[p];
-    const int32_t R = a.end_a[p] - sa + 1, C = a.end_b[p] - sb + 1;
-    const uint8_t* A = a.seqs + a.offsets[x] + sa;
-    const uint8_t* B = a.seqs + a.offsets[y] + sb;
-    uint8_t* dir = dir_base + dir_off[p - p0];
-    int32_t* rM = row_base + row_off[p - p0];
-    int32_t* rX = rM + C;
-    int32_t* rY = rX + C;
+// One wavefront per 64 pairs of like box shape (sorted on the host), one pair
+// per lane, all lanes stepping through the wavefront's largest box together.
+// The box is swept in strips of kStrip columns: within a strip the three
+// states of the row above live in registers, and only the strip's left
+// boundary column (three values per row) goes through memory, written by the
+// previous strip and read one row ahead.  Boundary columns and predecessor
+// bytes are interleaved by lane ([r][lane], [r][c][lane]), so every access of
+// a step is one contiguous line.  A lane outside its own box only waits; then
+// each lane walks back through its own predecessor bytes.
+constexpr int kStrip = 16;
+struct Wave { int64_t dir_off, row_off; int32_t rmax, cmax; };
+
+__global__ __launch_bounds__(64) void k_tb(TbArgs a, Matrix mat, const int32_t* lane_pair, const Wave* waves,
+                                           uint8_t* dir_base, int32_t* row_base) {
+    const int lane = threadIdx.x;
+    __shared__ int32_t s_mat[400];
+    for (int k = lane; k < 400; k += 64) s_mat[k] = mat.m[k];
+    __syncthreads();
+    const Wave w = waves[blockIdx.x];
+    const int32_t p = lane_pair[static_cast<int64_t>(blockIdx.x) * 64 + lane];
+    int32_t R = 0, C = 0;
+    const uint8_t* A = a.seqs;
+    const uint8_t* B = a.seqs;
+    if (p >= 0) {
+        const int32_t sa = a.start_a[p], sb = a.start_b[p];
+        R = a.end_a[p] - sa + 1;
+        C = a.end_b[p] - sb + 1;
+        A = a.seqs + a.offsets[a.pairs[2 * p]] + sa;
+        B = a.seqs + a.offsets[a.pairs[2 * p + 1]] + sb;
+    }
+    uint8_t* dir = dir_base + w.dir_off + lane;
+    // two boundary columns (read / write), each three planes of rmax rows
+    const int64_t plane = static_cast<int64_t>(w.rmax) * 64;
+    int32_t* bnd[2] = {row_base + w.row_off + lane, row_base + w.row_off + 3 * plane + lane};
     const int32_t go = a.go, ge = a.ge;
     auto clamp = [](int32_t v) { return v < kNegInf ? kNegInf : v; };
     int32_t last = kNegInf;
-    for (int32_t r = 0; r < R; ++r) {
-        const int32_t ar = A[r];
-        if (ar > 19) { atomicOr(a.err, cmk::kErrResidue); a.n_ops[p] = -1; return; }
-        int32_t dM = kNegInf, dX = kNegInf, dY = kNegInf;      // previous row, column c - 1
-        int32_t lM = kNegInf, lX = kNegInf, lY = kNegInf;      // this row, column c - 1
-        for (int32_t c = 0; c < C; ++c) {
-            const int32_t bc = B[c];
-            if (bc > 19) { atomicOr(a.err, cmk::kErrResidue); a.n_ops[p] = -1; return; }
-            const int32_t uM = r ? rM[c] : kNegInf, uX = r ? rX[c] : kNegInf, uY = r ? rY[c] : kNegInf;
-            // aligned pair: predecessor state at the diagonal (3 = the start)
-            int32_t d, pm;
-            if (r == 0 && c == 0) {
-                d = 0;
-                pm = 3;
-            } else {
-                d = dM; pm = 0;
-                if (dX > d) { d = dX; pm = 1; }
-                if (dY > d) { d = dY; pm = 2; }
-            }
-            const int32_t m = d <= kNegInf ? kNegInf : d + mat.m[20 * ar + bc];
-            // a_i against a gap, from the row above: 0 Mt, 1 X, 2 Y
-            int32_t vx = uM + go, px = 0;
-            if (uX + ge > vx) { vx = uX + ge; px = 1; }
-            if (uY + go > vx) { vx = uY + go; px = 2; }
-            vx = clamp(vx);
-            // a gap against b_j, from the left: 0 Mt, 1 Y, 2 X
-            int32_t vy = lM + go, py = 0;
-            if (lY + ge > vy) { vy = lY + ge; py = 1; }
-            if (lX + go > vy) { vy = lX + go; py = 2; }
-            vy = clamp(vy);
-            dir[static_cast<int64_t>(r) * C + c] = static_cast<uint8_t>(pm | (px << 2) | (py << 4));
-            dM = uM; dX = uX; dY = uY;
-            rM[c] = m; rX[c] = vx; rY[c] = vy;
-            lM = m; lX = vx; lY = vy;
-            last = m;
+    bool bad = false;
+    int cur = 0;
+    for (int32_t c0 = 0; c0 < w.cmax; c0 += kStrip) {
+        const int32_t* in = bnd[cur];
+        int32_t* outb = bnd[1 - cur];
+        int32_t uM[kStrip], uX[kStrip], uY[kStrip];           // row above, columns c0 .. c0 + kStrip - 1
+        uint32_t bcode[kStrip];
+#pragma unroll
+        for (int k = 0; k < kStrip; ++k) {
+            uM[k] = kNegInf; uX[k] = kNegInf; uY[k] = kNegInf;
+            const int32_t c = c0 + k;
+            const uint32_t v = c < C ? B[c] : 0u;
+            bad |= v > 19;
+            bcode[k] = min(v, 19u);
         }
+        // left boundary (column c0 - 1) of row 0, and of the row above (for the diagonal)
+        int32_t nM = kNegInf, nX = kNegInf, nY = kNegInf;
+        if (c0 > 0 && 0 < R) { nM = in[0]; nX = in[plane]; nY = in[2 * plane]; }
+        int32_t pM = kNegInf, pX = kNegInf, pY = kNegInf;      // (r - 1, c0 - 1)
+        for (int32_t r = 0; r < w.rmax; ++r) {
+            const bool row_in = r < R;
+            int32_t lM = nM, lX = nX, lY = nY;                 // (r, c0 - 1)
+            // the next row's left boundary, loaded a row ahead
+            nM = kNegInf; nX = kNegInf; nY = kNegInf;
+            if (c0 > 0 && r + 1 < R) {
+                const int64_t q = static_cast<int64_t>(r + 1) * 64;
+                nM = in[q]; nX = in[plane + q]; nY = in[2 * plane + q];
+            }
+            const uint32_t ar = row_in ? A[r] : 0u;
+            bad |= row_in && ar > 19;
+            const int32_t* srow = s_mat + 20 * min(ar, 19u);
+            int32_t dM = pM, dX = pX, dY = pY;                 // diagonal of column c0
+            pM = lM; pX = lX; pY = lY;
+#pragma unroll
+            for (int k = 0; k < kStrip; ++k) {
+                const int32_t c = c0 + k;
+                if (!row_in || c >= C) continue;
+                const int32_t oM = uM[k], oX = uX[k], oY = uY[k];   // (r - 1, c)
+                int32_t d, pm;
+                if (r == 0 && c == 0) {
+                    d = 0;
+                    pm = 3;
+                } else {
+                    d = dM; pm = 0;
+                    if (dX > d) { d = dX; pm = 1; }
+                    if (dY > d) { d = dY; pm = 2; }
+                }
+                const int32_t m = d <= kNegInf ? kNegInf : d + srow[bcode[k]];
+                // a_i against a gap, from the row above: 0 Mt, 1 X, 2 Y
+                int32_t vx = oM + go, px = 0;
+                if (oX + ge > vx) { vx = oX + ge; px = 1; }
+                if (oY + go > vx) { vx = oY + go; px = 2; }
+                vx = clamp(vx);
+                // a gap against b_j, from the left: 0 Mt, 1 Y, 2 X
+                int32_t vy = lM + go, py = 0;
+                if (lY + ge > vy) { vy = lY + ge; py = 1; }
+                if (lX + go > vy) { vy = lX + go; py = 2; }
+                vy = clamp(vy);
+                dir[(static_cast<int64_t>(r) * w.cmax + c) * 64] = static_cast<uint8_t>(pm | (px << 2) | (py << 4));
+                dM = oM; dX = oX; dY = oY;
+                uM[k] = m; uX[k] = vx; uY[k] = vy;
+                lM = m; lX = vx; lY = vy;
+                last = m;
+            }
+            // this row's last strip column is the next strip's left boundary
+            if (row_in && c0 + kStrip < C) {
+                const int64_t q = static_cast<int64_t>(r) * 64;
+                outb[q] = lM; outb[plane + q] = lX; outb[2 * plane + q] = lY;
+            }
+        }
+        cur = 1 - cur;
     }
+    if (p < 0) return;
+    if (bad) { atomicOr(a.err, cmk::kErrResidue); a.n_ops[p] = -1; return; }
     if (last != a.scores[p]) { atomicOr(a.err, cmk::kErrTrace); a.n_ops[p] = -1; return; }
     // walk back twice: count the columns, then write them start to end
     int32_t len = 0;
@@ -134,7 +194,7 @@ __global__ void k_tb(TbArgs a, Matrix mat, int64_t p0, int64_t p1, const int64_t
         bool ok = true;
         while (true) {
             if (r < 0 || c < 0 || k >= R + C) { ok = false; break; }
-            const uint8_t byte = dir[static_cast<int64_t>(r) * C + c];
+            const uint8_t byte = dir[(static_cast<int64_t>(r) * w.cmax + c) * 64];
             uint8_t op;
             bool done = false;
             if (state == 0) {
@@ -144,8 +204,7 @@ __global__ void k_tb(TbArgs a, Matrix mat, int64_t p0, int64_t p1, const int64_t
                 else { state = pm; --r; --c; }
             } else if (state == 1) {
                 op = 'I';
-                const int px = (byte >> 2) & 3;
-                state = px;                      // 0 Mt, 1 X, 2 Y
+                state = (byte >> 2) & 3;         // 0 Mt, 1 X, 2 Y
                 --r;
             } else {
                 op = 'D';
@@ -207,37 +266,58 @@ extern "C" cm_status cm_sw_traceback_batch(cm_context* ctx, const uint8_t* seqs,
     if (e == hipSuccess) e = hipMemcpyAsync(cols.data(), d_cols, n * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return cmrt::hip_fail(e, "traceback sizes");
-    // launches over runs of pairs whose predecessor bytes fit the scratch bound
-    std::vector<int64_t> offs;
-    size_t p0 = 0;
-    while (p0 < n) {
-        size_t p1 = p0;
+    // pairs with a box, sorted by shape, 64 to a wavefront; launches over
+    // runs of wavefronts whose predecessor bytes fit the scratch bound
+    std::vector<int32_t> order;
+    for (size_t p = 0; p < n; ++p)
+        if (cells[p] > 0) order.push_back(static_cast<int32_t>(p));
+    auto rows_of = [&](int32_t p) { return static_cast<int32_t>(cells[p] / cols[p]); };
+    std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return cols[x] != cols[y] ? cols[x] < cols[y] : (rows_of(x) != rows_of(y) ? rows_of(x) < rows_of(y) : x < y);
+    });
+    const size_t n_waves = (order.size() + 63) / 64;
+    std::vector<cmtb::Wave> waves;
+    std::vector<int32_t> lane_pair;
+    size_t w0 = 0;
+    while (w0 < n_waves) {
+        waves.clear();
+        lane_pair.clear();
         int64_t dir_bytes = 0, row_ints = 0;
-        offs.clear();
-        while (p1 < n && (p1 == p0 || dir_bytes + cells[p1] <= cmtb::kScratchCells)) {
-            offs.push_back(dir_bytes);
-            dir_bytes += cells[p1];
-            ++p1;
+        size_t w1 = w0;
+        while (w1 < n_waves) {
+            int32_t rmax = 0, cmax = 0;
+            for (size_t k = 64 * w1; k < std::min(order.size(), 64 * w1 + 64); ++k) {
+                rmax = std::max(rmax, rows_of(order[k]));
+                cmax = std::max(cmax, cols[order[k]]);
+            }
+            const int64_t wd = static_cast<int64_t>(rmax) * cmax * 64;
+            if (w1 > w0 && dir_bytes + wd > cmtb::kScratchCells) break;
+            waves.push_back({dir_bytes, row_ints, rmax, cmax});
+            for (size_t k = 64 * w1; k < 64 * w1 + 64; ++k) lane_pair.push_back(k < order.size() ? order[k] : -1);
+            dir_bytes += wd;
+            row_ints += 6 * static_cast<int64_t>(rmax) * 64;     // two boundary columns, three states
+            ++w1;
         }
-        const size_t m = p1 - p0;
-        for (size_t q = 0; q < m; ++q) {
-            offs.push_back(row_ints);
-            row_ints += 3 * static_cast<int64_t>(cols[p0 + q]);
-        }
+        const size_t m = w1 - w0;
+        const size_t meta_bytes = m * sizeof(cmtb::Wave) + lane_pair.size() * 4;
         if (!ctx->tb_dir.ensure(static_cast<size_t>(std::max<int64_t>(dir_bytes, 1))) ||
             !ctx->tb_rows.ensure(static_cast<size_t>(std::max<int64_t>(row_ints, 1)) * 4) ||
-            !ctx->tb_offs.ensure(offs.size() * 8))
-            return fail(CM_ENOMEM, "traceback scratch (%lld cells)", static_cast<long long>(dir_bytes));
-        int64_t* d_offs = static_cast<int64_t*>(ctx->tb_offs.ptr);
-        e = hipMemcpyAsync(d_offs, offs.data(), offs.size() * 8, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return cmrt::hip_fail(e, "traceback offsets");
-        hipLaunchKernelGGL(cmtb::k_tb, dim3(static_cast<unsigned>((m + 63) / 64)), dim3(64), 0, st, a, mat,
-                           static_cast<int64_t>(p0), static_cast<int64_t>(p1), d_cells, d_offs, d_offs + m,
+            !ctx->tb_offs.ensure(meta_bytes))
+            return fail(CM_ENOMEM, "traceback scratch (%lld bytes)", static_cast<long long>(dir_bytes));
+        cmtb::Wave* d_waves = static_cast<cmtb::Wave*>(ctx->tb_offs.ptr);
+        int32_t* d_lanes = reinterpret_cast<int32_t*>(d_waves + m);
+        e = hipMemcpyAsync(d_waves, waves.data(), m * sizeof(cmtb::Wave), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_lanes, lane_pair.data(), lane_pair.size() * 4, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return cmrt::hip_fail(e, "traceback plan");
+        hipLaunchKernelGGL(cmtb::k_tb, dim3(static_cast<unsigned>(m)), dim3(64), 0, st, a, mat, d_lanes, d_waves,
                            static_cast<uint8_t*>(ctx->tb_dir.ptr), static_cast<int32_t*>(ctx->tb_rows.ptr));
         e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host offsets and scratch are reused
+        if (e == hipSuccess) e = hipStreamSynchronize(st);   // the host tables and scratch are reused
         if (e != hipSuccess) return cmrt::hip_fail(e, "traceback");
-        p0 = p1;
+        w0 = w1;
     }
+    ctx->tb_dir.release();
+    ctx->tb_rows.release();
     return CM_OK;
 }
