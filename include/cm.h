@@ -209,8 +209,8 @@ typedef struct {
                                        chunks of about this many pairs (at most 8 chunks), a row
                                        leaving Algorithm 1's loop is not aligned against later
                                        chunks; 0 = about 2^25, < 0 = one batch per level.  Not
-                                       used while a screen covers CM_STAGE_REP.  Results do not
-                                       depend on it. */
+                                       used while a screen covers CM_STAGE_REP under graph
+                                       capture.  Results do not depend on it. */
 } cm_params;
 
 #define CM_STAGE_REP       1u       /* representative vs representative */

@@ -671,6 +671,11 @@ private:
     // screen when it covers this stage), or the columns in chunks
     cm_status wave_a(std::vector<MergeJob>& jobs, size_t total);
     cm_status wave_a_chunked(std::vector<MergeJob>& jobs, int chunks);
+    // a representative pair of clusters this large is aligned without the screen
+    bool rep_guarded(int32_t a, int32_t b) const {
+        const int64_t prod = static_cast<int64_t>(cl_[a].objs.size()) * cl_[b].objs.size();
+        return p_.screen_min_product > 0 && prod >= p_.screen_min_product;
+    }
     void simulate(MergeJob& job, const uint8_t* bits);
     // apply events until done or blocked on missing scores; true when blocked
     bool replay(MergeJob& job, std::vector<int32_t>& req);
@@ -989,7 +994,7 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
     // (each chunk pays the latency of its end-cell and start-cell launches,
     // so only waves of tens of millions of pairs gain)
     int chunks = 1;
-    if (!screened(CM_STAGE_REP) && p_.rep_chunk_pairs >= 0) {
+    if ((!screened(CM_STAGE_REP) || !ctx_->graphs) && p_.rep_chunk_pairs >= 0) {
         const int64_t per = p_.rep_chunk_pairs > 0 ? p_.rep_chunk_pairs : (int64_t(1) << 25);
         chunks = static_cast<int>(std::min<int64_t>(8, (static_cast<int64_t>(total) + per - 1) / per));
         if (chunks < 1) chunks = 1;
@@ -1051,13 +1056,17 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
         jobs[b].events.clear();
         jobs[b].result.clear();
     }
+    // under the screen (graphs off), the device screens each chunk's pairs
+    // (the size guard as for one batch) and aligns the kept ones
+    const bool dev_screen = screened(CM_STAGE_REP);
     std::vector<int32_t> pairs, out;
     std::vector<EndRec> ends;
-    std::vector<uint8_t> bits;
+    std::vector<uint8_t> bits, guard, keep;
     std::vector<size_t> deferred;
     for (int c = 0; c < chunks; ++c) {
         const auto q0 = Clock::now();
         pairs.clear();
+        guard.clear();
         for (size_t b = 0; b < jobs.size(); ++b) {
             const std::vector<int32_t>& cs1 = sets_[jobs[b].set1];
             const std::vector<int32_t>& cs2 = sets_[jobs[b].set2];
@@ -1071,26 +1080,54 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
                 for (size_t j = c0; j < c1; ++j) {
                     pairs.push_back(ra);
                     pairs.push_back(cl_[cs2[j]].rep);
+                    if (dev_screen) guard.push_back(rep_guarded(cs1[i], cs2[j]) ? 1 : 0);
                 }
             }
         }
         const size_t n = pairs.size() / 2;
         if (n == 0) continue;
         const auto q1 = Clock::now();
-        cm_status s = al_.submit(0, pairs.data(), static_cast<int64_t>(n), true);
+        cm_status s = dev_screen ? al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(n), scr_,
+                                                       static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau)
+                                 : al_.submit(0, pairs.data(), static_cast<int64_t>(n), true);
         if (s != CM_OK) return s;
         const auto q2 = Clock::now();
         s = al_.wait_scores(0, out);
         if (s != CM_OK) return s;
+        keep.assign(n, 1);
+        if (dev_screen) {
+            const uint8_t* kf = al_.keep_flags();
+            int64_t n_kept = 0, n_guard = 0;
+            double cells = 0;
+            for (size_t k = 0; k < n; ++k) {
+                keep[k] = kf[k];
+                n_guard += guard[k];
+                if (keep[k]) {
+                    ++n_kept;
+                    cells += static_cast<double>(len_[pairs[2 * k]]) * len_[pairs[2 * k + 1]];
+                } else {
+                    ++st_.screened_out;
+                }
+            }
+            st_.screened_pairs += static_cast<int64_t>(n) - n_guard;
+            st_.t_screen_s += al_.screen_seconds();
+            al_.set_kept(n_kept, cells);
+        }
+        // scores of the kept pairs come in order; end records are indexed by
+        // the kept pair's rank
         bits.assign(n, 0);
         deferred.clear();
+        std::vector<int32_t> rank;
+        size_t q = 0;
         for (size_t k = 0; k < n; ++k) {
-            const int32_t sc = out[k];
+            if (!keep[k]) continue;             // dropped by the screen: not similar
+            const int32_t sc = out[q];
             if (sc >= p_.T) {
                 bits[k] = kSim;
                 cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
             }
-            if (sc > p_.mT) deferred.push_back(k);
+            if (sc > p_.mT) { deferred.push_back(k); rank.push_back(static_cast<int32_t>(q)); }
+            ++q;
         }
         s = al_.wait(0, out, &ends);
         if (s != CM_OK) return s;
@@ -1099,7 +1136,7 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
             return fail(CM_EDEVICE, "end records: %zu of %zu", ends.size(), deferred.size());
         for (size_t qe = 0; qe < deferred.size(); ++qe) {
             const size_t k = deferred[qe];
-            if (ends[qe].idx != static_cast<int32_t>(k)) return fail(CM_EDEVICE, "missing end record for pair %zu", k);
+            if (ends[qe].idx != rank[qe]) return fail(CM_EDEVICE, "missing end record for pair %zu", k);
             const int32_t u1 = len_[pairs[2 * k]] - (ends[qe].ea - ends[qe].sa + 1);
             const int32_t u2 = len_[pairs[2 * k + 1]] - (ends[qe].eb - ends[qe].sb + 1);
             if (u1 < p_.mU) bits[k] |= kT21;
@@ -1107,7 +1144,7 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
             ++st_.end_pairs;
         }
         // Algorithm 1 over this slice, rows in order
-        size_t q = 0;
+        q = 0;
         for (size_t b = 0; b < jobs.size(); ++b) {
             const size_t n2 = sets_[jobs[b].set2].size();
             const size_t c0 = n2 * c / chunks, c1 = n2 * (c + 1) / chunks;
@@ -1181,10 +1218,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     // the device screens, compacts and aligns in one stream (host-side
     // screening under graph capture)
     const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
-    auto guarded = [&](int32_t a, int32_t b) {
-        const int64_t prod = static_cast<int64_t>(cl_[a].objs.size()) * cl_[b].objs.size();
-        return p_.screen_min_product > 0 && prod >= p_.screen_min_product;
-    };
+    auto guarded = [&](int32_t a, int32_t b) { return rep_guarded(a, b); };
     std::vector<uint8_t> guard;
     int64_t n_guard = 0;
     if (dev_screen) {

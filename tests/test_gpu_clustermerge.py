@@ -233,8 +233,9 @@ def ternary_weights(seed):
     return S.flatten(p).astype(np.float32)
 
 
-@pytest.mark.parametrize("stages,min_product", [(1, 0), (2, 0), (3, 0), (7, 0), (3, 4), (1, 2)])
-def test_screened_exact_vs_oracle_replay(cm, stages, min_product):
+@pytest.mark.parametrize("stages,min_product,chunk", [(1, 0, 0), (2, 0, 0), (3, 0, 0), (7, 0, 0), (3, 4, 0), (1, 2, 0),
+                                                     (3, 0, 5), (1, 4, 40)])
+def test_screened_exact_vs_oracle_replay(cm, stages, min_product, chunk):
     """Same weights (drawn on the CPU) on both sides; keep decisions from each side's own MLP."""
     ds = cmgen.clustermerge_families(n_seqs=160, n_families=20, seed=213, median=100, hi=300)
     w = ternary_weights(21)
@@ -248,7 +249,7 @@ def test_screened_exact_vs_oracle_replay(cm, stages, min_product):
     zg = scr.infer(cm.kmer_features(res, off), torch.from_numpy(np.stack([a, b], 1).astype(np.int32)).cuda())
     assert np.array_equal(zg.cpu().numpy(), z.astype(np.float32))
     g = cm.clustermerge_run(res, off, ds.matrix, screen=scr, screen_stages=stages, screen_tau=tau,
-                            screen_min_product=min_product)
+                            screen_min_product=min_product, rep_chunk_pairs=chunk)
     keep = lambda x, y: tab[x, y] >= tau  # noqa: E731
     clusters, pairs, st = ocm.clustermerge_screened(ds.residues, ds.offsets, ds.matrix, keep, stages,
                                                     min_product=min_product)
