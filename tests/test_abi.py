@@ -20,10 +20,26 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("cm_sw_score_batch", "cm_sw_span_batch", "cm_clustermerge_run", "cm_allvsall_count",
-                     "cm_kmer_features", "cm_screen_infer", "cm_screen_train_step", "cm_context_create"):
+    for required in ("cm_sw_score_batch", "cm_sw_span_batch", "cm_sw_traceback_batch", "cm_clustermerge_run",
+                     "cm_clustermerge_extend", "cm_allvsall_count", "cm_kmer_features", "cm_screen_infer",
+                     "cm_screen_train_step", "cm_context_create"):
         assert required in names
-    assert len(names) >= 25
+    assert len(names) >= 27
+
+
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as C99 on its own (no C++ or HIP types)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "cm.h"\nint main(void) { return 0; }\n')
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                        "-I", os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
 
 
 def test_library_exports_every_declared_symbol():
