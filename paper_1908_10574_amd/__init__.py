@@ -4,6 +4,12 @@ Argument marshalling only: every step of the path runs in the HIP kernels of
 ``libcm.so`` (see ``include/cm.h`` for the C ABI).  PyTorch supplies device
 memory and streams.  There is no CPU fallback: if the library is not built,
 importing this package raises.
+
+Entry points: ``sw_score_batch`` (score, end cell), ``sw_span_batch`` (start
+cell), ``sw_traceback_batch`` (alignment columns), ``clustermerge_run``,
+``clustermerge_extend`` (new proteins against a previous clustering),
+``allvsall_count``, ``kmer_features`` and the ``Screen`` (learned pair screen:
+inference and training), ``Context`` (plans, autotuning, graphs, timing).
 """
 from __future__ import annotations
 
@@ -16,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcm.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1908_10574_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python {os.path.join(_HERE, 'build.py')}` "
                       "(hipcc, gfx950); there is no fallback path")
 
 _lib = ctypes.CDLL(LIB_PATH)
