@@ -95,6 +95,45 @@ def test_found_pairs_of_clustermerge(cm):
     check(cm, ds, pick, label="clustermerge pairs")
 
 
+def test_full_scale_found_pairs(cm):
+    """The 20,000-protein ClusterMerge workload: 200,000 of its found pairs
+    sampled as the benchmark's traceback leg does (one call) plus the 500
+    largest boxes.  Every pair: its columns are an alignment of its box that
+    scores exactly its Smith-Waterman score (the batch checker); a sample:
+    the oracle's columns, spans and scores."""
+    from alignment_columns import check_columns
+    ds = cmgen.clustermerge_families()
+    res = torch.from_numpy(ds.residues).cuda()
+    off = torch.from_numpy(ds.offsets).cuda()
+    g = cm.clustermerge_run(res, off, ds.matrix)
+    found, fscore = g["pairs"], g["scores"]
+    rng = np.random.default_rng(11)
+    lens = np.diff(ds.offsets)
+    idx = np.concatenate([rng.choice(len(found), size=min(200000, len(found)), replace=False),
+                          np.argsort(lens[found[:, 0]] * lens[found[:, 1]], kind="stable")[-500:]])
+    pick = np.ascontiguousarray(found[idx], dtype=np.int32)
+    print(f"full-scale traceback: {len(pick)} pairs", flush=True)
+    pr = torch.from_numpy(pick).cuda()
+    sc, ea, eb = cm.sw_score_batch(res, off, pr, ds.matrix, return_end=True)
+    sa, sb = cm.sw_span_batch(res, off, pr, ds.matrix, sc, ea, eb, 0)
+    ops, op_off, n_ops = cm.sw_traceback_batch(res, off, pr, ds.matrix, sc, ea, eb, sa, sb)
+    cm.sync()
+    span = torch.stack([sc, ea, eb, sa, sb], 1).cpu().numpy()
+    assert np.array_equal(span[:, 0], fscore[idx])     # the scores ClusterMerge recorded
+    ops_h, off_h, n_h = ops.cpu().numpy(), op_off.cpu().numpy(), n_ops.cpu().numpy()
+    step = 25000
+    for k in range(0, len(pick), step):
+        e = min(k + step, len(pick))
+        bad = check_columns(ds.residues, ds.offsets, pick[k:e], ds.matrix, -11, -1, span[k:e], ops_h,
+                            off_h[k:e + 1], n_h[k:e])
+        assert not bad, {name: (len(v), pick[k + v[0]].tolist()) for name, v in bad.items()}
+    sub = np.r_[0:200, len(pick) - 20:len(pick)]
+    want, ospan = traceback_batch(ds.residues, ds.offsets, pick[sub], ds.matrix)
+    assert np.array_equal(ospan, span[sub])
+    got = [bytes(ops_h[off_h[p]:off_h[p] + n_h[p]]).decode() for p in sub]
+    assert got == want
+
+
 def test_errors(cm):
     ds = cmgen.family_dataset(2, [2, 2], lambda r: 80, 30, 200, 607)
     res = torch.from_numpy(ds.residues).cuda()

@@ -252,6 +252,76 @@ def test_traceback_columns_score_and_box():
             assert (s, ei, ej) == (S, ea, eb)
 
 
+def _flat_columns(cols):
+    n = np.array([len(c) for c in cols], np.int32)
+    cap = n + 3                                   # slack: offsets need not be tight
+    off = np.zeros(len(cols) + 1, np.int64)
+    np.cumsum(cap, out=off[1:])
+    ops = np.zeros(max(int(off[-1]), 1), np.uint8)
+    for p, c in enumerate(cols):
+        ops[off[p]:off[p] + len(c)] = np.frombuffer(c.encode(), np.uint8)
+    return ops, off, n
+
+
+def test_vectorised_column_checker():
+    """The batch checker used on full-size GPU output: the oracle's columns
+    pass it under several gap models, and planted mistakes (a wrong gap cost,
+    a shifted start cell, a first column that is a gap, a swapped interior
+    pair of columns, a truncated alignment) are caught in the pairs where they
+    were planted and nowhere else."""
+    from alignment_columns import check_columns
+    from oracle import traceback_batch
+    rng = np.random.default_rng(331)
+    fam = cmgen.family_dataset(8, [5] * 8, lambda r: int(r.integers(20, 300)), 1, 400, 332)
+    pairs = cmgen.random_pairs(rng, fam.n, 400)
+    for go, ge in ((-11, -1), (-5, -5), (-3, 0)):
+        cols, span = traceback_batch(fam.residues, fam.offsets, pairs, fam.matrix, go, ge)
+        ops, off, n = _flat_columns(cols)
+        assert check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, span, ops, off, n) == {}
+    gapped = [p for p, c in enumerate(cols) if "II" in c or "DD" in c]
+    assert len(gapped) > 20
+    # extension cost off by one: exactly the alignments with a gap longer than one column
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge - 1, span, ops, off, n)
+    assert list(bad) == ["score"] and sorted(bad["score"]) == gapped
+    pos = [p for p in range(len(cols)) if span[p, 0] > 0]
+    # start cell moved by one row
+    sp = span.copy()
+    sp[pos[0], 3] += 1
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, sp, ops, off, n)
+    assert set(bad) <= {"consumes_a", "score", "inside_sequences"} and list(bad["consumes_a"]) == [pos[0]]
+    # a gap as the first column
+    c2 = list(cols)
+    c2[pos[1]] = "D" + cols[pos[1]][1:]
+    o2, f2, n2 = _flat_columns(c2)
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, span, o2, f2, n2)
+    assert list(bad["begins_with_M"]) == [pos[1]] and all(set(v) == {pos[1]} for v in bad.values())
+    # an interior "MI" swapped to "IM" where the moved residue changes the aligned value
+    c3, planted = list(cols), []
+    for p in pos:
+        k = cols[p].find("MI", 1)
+        if k > 0:
+            c3[p] = cols[p][:k] + "IM" + cols[p][k + 2:]
+            planted.append(p)
+    o3, f3, n3 = _flat_columns(c3)
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, span, o3, f3, n3)
+    flagged = set().union(*[set(v) for v in bad.values()]) if bad else set()
+    assert planted and flagged <= set(planted) and len(flagged) >= len(planted) // 2
+    # the last column dropped
+    c4 = list(cols)
+    c4[pos[2]] = cols[pos[2]][:-1]
+    o4, f4, n4 = _flat_columns(c4)
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, span, o4, f4, n4)
+    assert all(set(v) == {pos[2]} for v in bad.values()) and "consumes_a" in bad and "consumes_b" in bad
+    # a count past its capacity, and columns for a pair whose score is 0
+    n5 = n.copy()
+    n5[pos[3]] = off[pos[3] + 1] - off[pos[3]] + 1
+    sp = span.copy()
+    sp[pos[4], 0] = 0
+    bad = check_columns(fam.residues, fam.offsets, pairs, fam.matrix, go, ge, sp, ops, off, n5)
+    assert sorted(bad) == ["capacity", "count_sign"]
+    assert list(bad["capacity"]) == [pos[3]] and list(bad["count_sign"]) == [pos[4]]
+
+
 def test_traceback_identical_sequences_all_aligned():
     import cmgen
     from oracle import traceback_batch
