@@ -137,6 +137,50 @@ def test_extend_exact(cm, n_prev):
         assert [(r, list(m)) for r, m in full["clusters"]] == [(r, list(m)) for r, m in g["clusters"]]
 
 
+def test_extend_full_scale_properties(cm):
+    """The 20,000-protein workload: its last 1,000 proteins classified against
+    a clustering of the first 19,000.  Checks that hold at any size: a full
+    merge moves whole clusters and an exchange copies members, so two members
+    of a previous cluster always end in a common cluster and every previously
+    found pair is found again, with the reused score; scores of pairs with a
+    new protein equal the oracle's on a sample; the result repeats."""
+    ds = cmgen.clustermerge_families()
+    res, off = dev_store(ds)
+    n_prev = 19000
+    prev = cm.clustermerge_run(res, off[: n_prev + 1].contiguous(), ds.matrix)
+    pc = [(r, list(m)) for r, m in prev["clusters"]]
+    kw = dict(known_pairs=prev["pairs"], known_scores=prev["scores"])
+    g = cm.clustermerge_extend(res, off, ds.matrix, pc, n_prev, **kw)
+    s = g["stats"]
+    pairs, scores = g["pairs"], g["scores"]
+    assert (pairs[:, 0] < pairs[:, 1]).all() and (scores >= 120).all()
+    key = pairs[:, 0].astype(np.int64) * ds.n + pairs[:, 1]
+    assert (np.diff(key) > 0).all()
+    pkey = prev["pairs"][:, 0].astype(np.int64) * ds.n + prev["pairs"][:, 1]
+    at = np.searchsorted(key, pkey)
+    assert (at < len(key)).all() and np.array_equal(key[at], pkey)
+    assert np.array_equal(scores[at], prev["scores"])
+    assert s["cache_hits"] >= len(pkey)
+    seen = np.zeros(ds.n, bool)
+    for r, m in g["clusters"]:
+        ml = m.tolist()
+        assert r in set(ml) and len(set(ml)) == len(ml)
+        seen[m] = True
+    assert seen.all()
+    assert s["n_clusters"] <= len(pc) + (ds.n - n_prev)
+    new = np.flatnonzero(pairs[:, 1] >= n_prev)
+    assert len(new) > 0
+    rng = np.random.default_rng(7)
+    pick = new[rng.choice(len(new), size=min(300, len(new)), replace=False)]
+    osc = sw_batch(ds.residues, ds.offsets, pairs[pick], ds.matrix, with_end=False)
+    assert np.array_equal(osc, scores[pick])
+    g2 = cm.clustermerge_extend(res, off, ds.matrix, pc, n_prev, **kw)
+    assert g2["stats"]["pair_set_hash"] == s["pair_set_hash"]
+    assert [(r, list(m)) for r, m in g2["clusters"]] == [(r, list(m)) for r, m in g["clusters"]]
+    print({k: s[k] for k in ("n_clusters", "n_similar_pairs", "cache_hits", "final_candidates", "t_total_s")},
+          len(prev["pairs"]), len(new))
+
+
 def test_extend_rejects_inconsistent_clustering(cm):
     ds = cmgen.clustermerge_families(n_seqs=60, n_families=8, seed=215, median=100, hi=200)
     res, off = dev_store(ds)
