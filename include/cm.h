@@ -12,7 +12,9 @@
  *    k is residues[offsets[k] .. offsets[k+1]) (int64 offsets, n_seqs+1 of them).
  *    A sequence is referred to by its int32 index.  Empty sequences are legal.
  *  - A pair row (a, b) aligns sequence a (rows, index i) with sequence b
- *    (columns, index j).  Cells are 0-based and inclusive.
+ *    (columns, index j).  Cells are 0-based and inclusive.  One call of the
+ *    Smith-Waterman batch entry points (score, span, columns, autotune) takes
+ *    at most 2^31 - 1 pairs (CM_EINVAL beyond).
  *  - The matrix is 400 int32 values, row-major, M[x][y] = score of residue x
  *    (row sequence) against residue y (column sequence); |M| <= 127.
  *  - Gap arguments are negative as written: a run of k gap columns of one kind

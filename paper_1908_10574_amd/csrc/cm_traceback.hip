@@ -14,9 +14,11 @@
 // state; the walk back from Mt at the end cell gives the columns, written
 // start to end as 'M', 'I', 'D'.
 //
-// Not a hot-path kernel: one lane per pair runs the box row by row, keeps one
-// row of the three states and one predecessor byte per cell in scratch, then
-// walks back.  Batches are split so that the scratch stays bounded.
+// Not a hot-path kernel: one lane per pair, 64 pairs of like box shape per
+// wavefront, the box swept in strips of columns with the row above in
+// registers; each strip's left boundary column and one predecessor byte per
+// cell go to scratch, then every lane walks back through its own bytes.
+// Batches are split into launches so that the scratch stays bounded.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -235,6 +237,7 @@ extern "C" cm_status cm_sw_traceback_batch(cm_context* ctx, const uint8_t* seqs,
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative size");
     if (n_pairs == 0) return CM_OK;
+    if (n_pairs > static_cast<int64_t>(0x7fffffff)) return fail(CM_EINVAL, "n_pairs too large");
     if (!offsets || !pairs || !matrix || !scores || !end_a || !end_b || !start_a || !start_b || !op_offsets ||
         !ops || !n_ops)
         return fail(CM_EINVAL, "NULL argument");
