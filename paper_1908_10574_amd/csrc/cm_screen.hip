@@ -19,6 +19,7 @@ struct cm_screen {
     DeviceBuf w1, w2, w2t, w3;             // bf16 copies
     // per-batch workspace, sized for cap rows
     DeviceBuf h1, h1t, h2, z, dz, loss, dh2, dh2t, dh1t, xt;
+    DeviceBuf gpart;                       // fp32 [cap / 64][kHidden]: layer-3 gradient partials
     int cap = 0;
     int step = 0;
 };
@@ -38,15 +39,16 @@ cm_status alloc_params(cm_screen* s) {
     return CM_OK;
 }
 
-cm_status ensure_workspace(cm_screen* s, int mb, bool training) {
-    if (mb <= s->cap && (!training || s->xt.ptr)) return CM_OK;
-    const int c = mb > s->cap ? mb : s->cap;
+// training workspace for mb rows (every buffer sized for s->cap rows)
+cm_status ensure_workspace(cm_screen* s, int mb) {
+    if (mb <= s->cap) return CM_OK;
+    const int c = mb;
     const size_t hb = static_cast<size_t>(c) * cms::kHidden * 2;
     bool ok = s->z.ensure(static_cast<size_t>(c) * 4);
-    if (training)
-        ok = ok && s->h1.ensure(hb) && s->h1t.ensure(hb) && s->h2.ensure(hb) && s->dz.ensure(c * 4) &&
-             s->loss.ensure(c * 4) && s->dh2.ensure(hb) && s->dh2t.ensure(hb) && s->dh1t.ensure(hb) &&
-             s->xt.ensure(static_cast<size_t>(c) * cms::kIn * 2);
+    ok = ok && s->h1.ensure(hb) && s->h1t.ensure(hb) && s->h2.ensure(hb) && s->dz.ensure(c * 4) &&
+         s->loss.ensure(c * 4) && s->dh2.ensure(hb) && s->dh2t.ensure(hb) && s->dh1t.ensure(hb) &&
+         s->xt.ensure(static_cast<size_t>(c) * cms::kIn * 2) &&
+         s->gpart.ensure(static_cast<size_t>(c / 64) * cms::kHidden * 4);
     if (!ok) return fail(CM_ENOMEM, "screen workspace for %d rows", c);
     s->cap = c;
     return CM_OK;
@@ -72,7 +74,7 @@ cms::FwdArgs fwd_args(const cm_screen* s, const uint16_t* feat, const int32_t* p
 cm_status forward_backward(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels, int n,
                            float* loss_out) {
     const int mb = static_cast<int>(round_up(n, 64));
-    cm_status r = ensure_workspace(s, mb, true);
+    cm_status r = ensure_workspace(s, mb);
     if (r != CM_OK) return r;
     hipStream_t st = s->st;
     uint16_t* h1 = static_cast<uint16_t*>(s->h1.ptr);
@@ -92,7 +94,8 @@ cm_status forward_backward(cm_screen* s, const uint16_t* feat, const int32_t* pa
     if ((r = chk(cms::launch_pair_xt(feat, pairs, n, mb, xt, st), "pair inputs")) != CM_OK) return r;
     if ((r = chk(cms::launch_backward_tail(static_cast<float*>(s->z.ptr), labels, n, mb, h2,
                                            static_cast<uint16_t*>(s->w3.ptr), static_cast<float*>(s->dz.ptr),
-                                           static_cast<float*>(s->loss.ptr), dh2, dh2t, g + cms::kOffW3,
+                                           static_cast<float*>(s->loss.ptr), dh2, dh2t,
+                                           static_cast<float*>(s->gpart.ptr), g + cms::kOffW3,
                                            g + cms::kOffB3, st),
                  "layer-3 backward")) != CM_OK)
         return r;

@@ -59,7 +59,7 @@ hipError_t launch_pair_xt(const uint16_t* feat, const int32_t* pairs, int n, int
 hipError_t launch_gemm(const GemmArgs& g, int epi, hipStream_t s);
 hipError_t launch_backward_tail(const float* z, const uint8_t* y, int n, int mb, const uint16_t* h2,
                                 const uint16_t* w3, float* dz, float* loss, uint16_t* dh2, uint16_t* dh2t,
-                                float* gw3, float* gb3, hipStream_t s);
+                                float* gpart, float* gw3, float* gb3, hipStream_t s);
 hipError_t launch_rowsum(const uint16_t* x, int rows, int mb, float* out, hipStream_t s);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);

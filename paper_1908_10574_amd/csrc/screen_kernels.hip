@@ -417,37 +417,55 @@ __global__ void k_bce(const float* z, const uint8_t* y, int n, int mb, float* dz
     loss[m] = fmaxf(v, 0.f) - v * t + log1pf(expf(-fabsf(v)));
 }
 
-// dH2 = bf16(dz * W3 * [h2 > 0]) in both layouts
+// dH2 = bf16(dz * W3 * [h2 > 0]) in both layouts; the same pass leaves the
+// layer-3 weight gradient's partial sums of its 64 rows,
+// gpart[row tile][j] = sum over the tile's m of dz[m] h2[m][j]
 __global__ __launch_bounds__(256) void k_dh2(const float* dz, const uint16_t* h2, const uint16_t* w3, int mb,
-                                             uint16_t* dh2, uint16_t* dh2t) {
+                                             uint16_t* dh2, uint16_t* dh2t, float* gpart) {
     __shared__ uint16_t t[64][66];
+    __shared__ float part[4][64];
     const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    float acc = 0.f;
     for (int rr = ty; rr < 64; rr += 4) {
         const int m = m0 + rr, n = n0 + tx;
         const uint16_t hv = h2[static_cast<int64_t>(m) * kHidden + n];
-        const uint16_t v = hv ? f2bf(dz[m] * bf2f(w3[n])) : static_cast<uint16_t>(0);
+        const float d = dz[m];
+        const uint16_t v = hv ? f2bf(d * bf2f(w3[n])) : static_cast<uint16_t>(0);
         dh2[static_cast<int64_t>(m) * kHidden + n] = v;
         t[rr][tx] = v;
+        acc += d * bf2f(hv);
     }
+    part[ty][tx] = acc;
     __syncthreads();
     for (int nn = ty; nn < 64; nn += 4) dh2t[static_cast<int64_t>(n0 + nn) * mb + m0 + tx] = t[tx][nn];
+    if (ty == 0)
+        gpart[static_cast<int64_t>(blockIdx.x) * kHidden + n0 + tx] =
+            part[0][tx] + part[1][tx] + part[2][tx] + part[3][tx];
 }
 
-// gW3[j] = sum_m dz[m] h2[m][j]; gb3 = sum dz   (block per 64 columns, fixed order)
-__global__ __launch_bounds__(256) void k_gw3(const float* dz, const uint16_t* h2, int mb, float* gw3, float* gb3) {
-    __shared__ float part[4][64];
-    const int n = blockIdx.x * 64 + (threadIdx.x & 63), w = threadIdx.x >> 6;
-    float s = 0.f;
-    for (int m = w; m < mb; m += 4) s += dz[m] * bf2f(h2[static_cast<int64_t>(m) * kHidden + n]);
-    part[w][threadIdx.x & 63] = s;
-    __syncthreads();
-    if (w == 0) gw3[n] = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        float t = 0.f;
-        for (int m = 0; m < mb; ++m) t += dz[m];
-        gb3[0] = t;
+// gW3[j] = sum of k_dh2's row-tile partials in tile order (the first
+// kHidden / 256 blocks, a thread per column); gb3 = sum dz as a fixed tree
+// over 256 threads (the last block)
+__global__ __launch_bounds__(256) void k_gw3(const float* dz, const float* gpart, int mb, float* gw3, float* gb3) {
+    __shared__ float part[256];
+    const int tiles = mb / 64;
+    if (blockIdx.x < kHidden / 256) {
+        const int n = blockIdx.x * 256 + threadIdx.x;
+        float s = 0.f;
+        for (int k = 0; k < tiles; ++k) s += gpart[static_cast<int64_t>(k) * kHidden + n];
+        gw3[n] = s;
+        return;
     }
+    float s = 0.f;
+    for (int m = threadIdx.x; m < mb; m += 256) s += dz[m];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb3[0] = part[0];
 }
 
 // row sums of a bf16 [R][mb] matrix (bias gradients), block per row
@@ -521,10 +539,10 @@ hipError_t launch_gemm(const GemmArgs& g, int epi, hipStream_t s) {
 }
 hipError_t launch_backward_tail(const float* z, const uint8_t* y, int n, int mb, const uint16_t* h2,
                                 const uint16_t* w3, float* dz, float* loss, uint16_t* dh2, uint16_t* dh2t,
-                                float* gw3, float* gb3, hipStream_t s) {
+                                float* gpart, float* gw3, float* gb3, hipStream_t s) {
     hipLaunchKernelGGL(k_bce, dim3((mb + 255) / 256), dim3(256), 0, s, z, y, n, mb, dz, loss);
-    hipLaunchKernelGGL(k_dh2, dim3(mb / 64, kHidden / 64), dim3(256), 0, s, dz, h2, w3, mb, dh2, dh2t);
-    hipLaunchKernelGGL(k_gw3, dim3(kHidden / 64), dim3(256), 0, s, dz, h2, mb, gw3, gb3);
+    hipLaunchKernelGGL(k_dh2, dim3(mb / 64, kHidden / 64), dim3(256), 0, s, dz, h2, w3, mb, dh2, dh2t, gpart);
+    hipLaunchKernelGGL(k_gw3, dim3(kHidden / 256 + 1), dim3(256), 0, s, dz, gpart, mb, gw3, gb3);
     return hipGetLastError();
 }
 hipError_t launch_rowsum(const uint16_t* x, int rows, int mb, float* out, hipStream_t s) {
