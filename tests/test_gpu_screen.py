@@ -80,15 +80,17 @@ def test_gradients_match_reference(cm, data):
     w = S.init_params(13)
     scr = cm.Screen(0)
     scr.set_weights(w)
-    pairs, y = _batch(ds, 300, 14)
-    g, loss = scr.grads(feat, torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda())
-    z, cache = S.forward(w, S.pair_input(feat_bits(feat), pairs))
-    gr = S.backward(z, y, cache)
-    assert abs(loss - S.bce(z, y)) < 1e-3
-    gp, rp = S.unflatten(g), S.unflatten(gr)
-    for name, _ in S.SHAPES:
-        rel = np.linalg.norm(gp[name] - rp[name]) / max(np.linalg.norm(rp[name]), 1e-30)
-        assert rel < 1e-2, (name, rel)
+    # the second batch, larger and ragged, makes the same screen grow its workspace
+    for n, seed in ((300, 14), (1000, 17)):
+        pairs, y = _batch(ds, n, seed)
+        g, loss = scr.grads(feat, torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda())
+        z, cache = S.forward(w, S.pair_input(feat_bits(feat), pairs))
+        gr = S.backward(z, y, cache)
+        assert abs(loss - S.bce(z, y)) < 1e-3
+        gp, rp = S.unflatten(g), S.unflatten(gr)
+        for name, _ in S.SHAPES:
+            rel = np.linalg.norm(gp[name] - rp[name]) / max(np.linalg.norm(rp[name]), 1e-30)
+            assert rel < 1e-2, (n, name, rel)
 
 
 def test_training_reduces_loss_and_adam_matches(cm, data):
