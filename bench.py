@@ -322,8 +322,8 @@ def main():
                     help="representative pairs of clusters whose sizes multiply to at least this bypass the screen")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; the sharding it "
+              "would take is described in the design notes (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
