@@ -1,7 +1,7 @@
 """CPU reference of the learned pair screen.  Test infrastructure only.
 
 The screen is not in the paper: it is a learned pre-filter placed in front of
-the exact similarity function f of Section 4 (which stays the judge of every
+the exact similarity function f of Section 4 (which still decides every
 pair it lets through).  Its definition here:
 
 * features: for every protein, the counts of its 3-mers hashed into 1,024
