@@ -1,5 +1,5 @@
 """The C oracle under AddressSanitizer and UndefinedBehaviorSanitizer (CPU):
-oracle/sanitize_check.c links sw_oracle.c and drives every entry point; any
+tests/oracle_sanitize_check.c links oracle/sw_oracle.c and drives every entry point; any
 out-of-bounds access, undefined operation or leak ends it with an error."""
 import os
 import shutil
@@ -16,7 +16,7 @@ def test_oracle_clean_under_sanitizers(tmp_path):
     exe = str(tmp_path / "sanitize_check")
     flags = ["-O1", "-g", "-std=c99", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
              "-fno-sanitize-recover=undefined"]
-    subprocess.run(["gcc", *flags, "-o", exe, os.path.join(ORACLE, "sanitize_check.c"),
+    subprocess.run(["gcc", *flags, "-o", exe, os.path.join(ROOT, "tests", "oracle_sanitize_check.c"),
                     os.path.join(ORACLE, "sw_oracle.c")], check=True, capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300, env=env)
