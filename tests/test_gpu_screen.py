@@ -100,11 +100,19 @@ def test_training_reduces_loss_and_adam_matches(cm, data):
     scr.set_weights(w)
     pairs, y = _batch(ds, 512, 16)
     tp, ty = torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda()
-    g, _ = scr.grads(feat, tp, ty)
-    first = scr.train_step(feat, tp, ty, lr=1e-3)
-    m1, _ = scr.get_weights()
-    want, _, _ = S.adam(w, g, np.zeros_like(w), np.zeros_like(w), 1, lr=1e-3)
-    assert np.abs(m1 - want).max() < 1e-6
+    # four Adam steps, each compared with the reference update from the same
+    # gradient (the GPU's gradient is deterministic, so grads() before a step
+    # returns the gradient that step uses)
+    want, m, v = w.copy(), np.zeros_like(w), np.zeros_like(w)
+    first = None
+    for t in range(1, 5):
+        g, _ = scr.grads(feat, tp, ty)
+        loss = scr.train_step(feat, tp, ty, lr=1e-3)
+        first = loss if first is None else first
+        got, _ = scr.get_weights()
+        want, m, v = S.adam(want, g, m, v, t, lr=1e-3)
+        assert np.abs(got - want).max() < 1e-6, (t, np.abs(got - want).max())
+        want = got   # next step starts from the GPU's weights
     losses = [scr.train_step(feat, tp, ty, lr=1e-3) for _ in range(40)]
     assert losses[-1] < 0.5 * first, (first, losses[-1])
 
@@ -139,7 +147,7 @@ def test_trained_screen_quality_and_screened_recall(cm):
                                       "t_total_s")})
     assert ss["screened_out"] > 0
     assert ss["aligned_cells"] < ps["aligned_cells"]
-    assert ss["n_similar_pairs"] >= 0.99 * ps["n_similar_pairs"]
+    assert ss["n_similar_pairs"] >= 0.995 * ps["n_similar_pairs"]
     # screened output is still exact: every reported pair is a true similar pair
     found = {(int(x), int(y)) for x, y in plain["pairs"]}
     assert all((int(x), int(y)) in found for x, y in scr_run["pairs"][:: max(1, len(scr_run["pairs"]) // 5000)])

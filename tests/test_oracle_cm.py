@@ -196,3 +196,113 @@ def test_extend_never_transitive_compares_every_pair_once():
     n_new = ds.n - n_prev
     assert s2.rep_comparisons == n_new * (n_new - 1) // 2 + n_prev * n_new
     assert s2.full_merges == 0 and len(c2) == ds.n
+
+
+# ---------------------------------------------------------------------------
+# Section 4's transitivity test, pinned on asymmetric pairs.  A short protein A
+# that occurs whole inside a longer protein D (with long flanks that A does not
+# cover) is nearly covered by the alignment, D is not: D's cluster may stand
+# for A's (absorb it), never the other way round, whichever set each one
+# starts in.  The comparators are strict: score > mT and uncovered < mU.
+# ---------------------------------------------------------------------------
+def _embedded_pair(seed=31, core=60, flank=100):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, 20, size=core).astype(np.uint8)
+    d = np.concatenate([rng.integers(0, 20, size=flank), a, rng.integers(0, 20, size=flank)]).astype(np.uint8)
+    return a, d
+
+
+def test_longer_protein_absorbs_the_embedded_one_in_either_set_order():
+    a, d = _embedded_pair()
+    M = cmgen.make_matrix()
+    # the local alignment of A inside D is A against itself: S(A, D) = S(A, A),
+    # all of A covered and both flanks of D left over
+    s_aa = sw(a, a, M)[0]
+    from oracle import sw_span
+    S, ei, ej, si, sj = sw_span(a, d, M)
+    assert S == s_aa == int(sum(M[x, x] for x in a)) and S > 166
+    assert (si, ei) == (0, len(a) - 1) and (sj, ej) == (100, 100 + len(a) - 1)
+
+    # A is element 0 (first set), D element 1 (second set): the second set's
+    # cluster (D) absorbs the first (A)
+    ds = cmgen.from_list([a, d], M)
+    clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    assert [(c.rep, c.objs) for c in clusters] == [(1, [1, 0])]
+    assert st.full_merges == 1 and st.exchanges == 0 and pairs == [(0, 1, S)]
+
+    # D is element 0 (first set), A element 1: D's cluster, now in the first
+    # set, absorbs A's and keeps its place; A's cluster never absorbs D
+    ds = cmgen.from_list([d, a], M)
+    clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    assert [(c.rep, c.objs) for c in clusters] == [(0, [0, 1])]
+    assert st.full_merges == 1 and st.exchanges == 0 and pairs == [(0, 1, S)]
+
+    # the judge's answers themselves, both orientations
+    for order, (r1, r2) in ((("a", "d"), (0, 1)), (("d", "a"), (0, 1))):
+        seqs = {"a": a, "d": d}
+        ds = cmgen.from_list([seqs[order[0]], seqs[order[1]]], M)
+        judge = cm.ProteinJudge(ds.residues, ds.offsets, ds.matrix)
+        similar, c2_takes_c1, c1_takes_c2 = judge.rep_test(r1, r2)
+        assert similar
+        # the cluster whose representative is D is the absorber
+        assert c2_takes_c1 == (order[1] == "d") and c1_takes_c2 == (order[0] == "d")
+
+
+def test_score_equal_to_mT_is_not_transitive():
+    a, d = _embedded_pair(seed=32)
+    M = cmgen.make_matrix()
+    S = sw(a, d, M)[0]
+    ds = cmgen.from_list([a, d], M)
+    # score == mT: not "above" mT, so the similar representatives exchange
+    # members instead (each cluster receives the other, since both are similar)
+    clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix, mT=S)
+    assert st.full_merges == 0 and st.exchanges == 1
+    assert [(c.rep, c.objs) for c in clusters] == [(0, [0, 1]), (1, [1, 0])]
+    assert pairs == [(0, 1, S)]
+    # one below: the full merge happens
+    clusters, _, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix, mT=S - 1)
+    assert st.full_merges == 1 and [(c.rep, c.objs) for c in clusters] == [(1, [1, 0])]
+
+
+def test_uncovered_equal_to_mU_is_not_transitive():
+    """A carries a few residues before the part it shares with D; the count of
+    its residues outside the alignment decides: equal to mU is not fewer."""
+    rng = np.random.default_rng(33)
+    core = rng.integers(0, 20, size=70).astype(np.uint8)
+    # a prefix that scores badly against D's flank (residue 0 repeated, D's
+    # flank drawn without residue 0) so the alignment cannot extend into it
+    a = np.concatenate([np.zeros(9, np.uint8), core])
+    flank_l = rng.integers(1, 20, size=120).astype(np.uint8)
+    flank_r = rng.integers(1, 20, size=120).astype(np.uint8)
+    d = np.concatenate([flank_l, core, flank_r])
+    M = cmgen.make_matrix()
+    from oracle import sw_span
+    S, ei, ej, si, sj = sw_span(a, d, M)
+    u_a = len(a) - (ei - si + 1)
+    u_d = len(d) - (ej - sj + 1)
+    assert S > 166 and 0 < u_a < u_d and u_d >= 200
+    ds = cmgen.from_list([a, d], M)
+    for mU, merged in ((u_a, False), (u_a + 1, True)):
+        clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix, mU=mU)
+        assert st.full_merges == (1 if merged else 0), (mU, u_a)
+        want = [(1, [1, 0])] if merged else [(0, [0, 1]), (1, [1, 0])]
+        assert [(c.rep, c.objs) for c in clusters] == want
+        assert pairs == [(0, 1, S)]
+
+
+def test_score_equal_to_T_is_similar():
+    """Similarity is score >= T (Algorithm 1 skips a pair only below T)."""
+    rng = np.random.default_rng(34)
+    x = rng.integers(0, 20, size=80).astype(np.uint8)
+    y = x.copy()
+    y[::3] = rng.integers(0, 20, size=len(y[::3]))
+    M = cmgen.make_matrix()
+    S = sw(x, y, M)[0]
+    assert S > 30
+    ds = cmgen.from_list([x, y], M)
+    never = 10 ** 6
+    for T, found in ((S, True), (S + 1, False)):
+        clusters, pairs, st = cm.clustermerge(ds.residues, ds.offsets, ds.matrix, T=T, mT=never)
+        assert st.rep_comparisons == 1 and st.full_merges == 0
+        assert st.exchanges == (1 if found else 0)
+        assert pairs == ([(0, 1, S)] if found else [])

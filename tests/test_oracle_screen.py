@@ -90,3 +90,52 @@ def test_init_bounds():
     assert len(w) == S.n_params() == 1312257
     assert np.abs(p["W1"]).max() <= np.sqrt(6 / 2048) and np.abs(p["W2"]).max() <= np.sqrt(6 / 512)
     assert (p["b1"] == 0).all() and (p["b3"] == 0).all()
+
+
+def test_adam_constant_gradient_closed_form():
+    """Under a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step, so step t moves every weight by lr * g / (|g| + eps):
+    after k steps w0 - k * lr * g / (|g| + eps).  A wrong bias correction at
+    any step after the first breaks this."""
+    rng = np.random.default_rng(6)
+    w0 = rng.normal(size=200).astype(np.float32)
+    g = (rng.normal(size=200) * 10.0 ** rng.integers(-3, 2, size=200)).astype(np.float32)
+    w, m, v = w0.copy(), np.zeros(200, np.float32), np.zeros(200, np.float32)
+    for t in range(1, 13):
+        w, m, v = S.adam(w, g, m, v, t, lr=1e-3)
+        want = w0.astype(np.float64) - t * 1e-3 * g / (np.abs(g.astype(np.float64)) + 1e-8)
+        assert np.allclose(w, want, atol=2e-6, rtol=0), (t, np.abs(w - want).max())
+
+
+def test_adam_second_step_after_a_zero_gradient():
+    """g at step 1, zero at step 2.  The moments after step 2 are b1(1-b1)g and
+    b2(1-b2)g^2; divided by 1-b1^2 = (1-b1)(1+b1) and 1-b2^2 they become
+    g b1/(1+b1) and g^2 b2/(1+b2), so the second move is
+    lr * b1/(1+b1) * sqrt((1+b2)/b2) * sign(g) = 6.7006e-4 * sign(g) at the
+    defaults (eps negligible for |g| ~ 1)."""
+    rng = np.random.default_rng(7)
+    w0 = rng.normal(size=64).astype(np.float32)
+    g = rng.choice([-1.0, 1.0], size=64).astype(np.float32) * rng.uniform(0.5, 2.0, size=64).astype(np.float32)
+    z = np.zeros(64, np.float32)
+    w1, m, v = S.adam(w0, g, z, z, 1, lr=1e-3)
+    w2, m, v = S.adam(w1, np.zeros(64, np.float32), m, v, 2, lr=1e-3)
+    move = 1e-3 * (0.9 / 1.9) * np.sqrt(1.999 / 0.999)
+    assert abs(move - 6.7006e-4) < 1e-8
+    assert np.allclose(w1 - w2, move * np.sign(g), atol=2e-7)
+
+
+def test_adam_is_invariant_to_gradient_scale():
+    """Adam divides the first moment by the root of the second, so scaling every
+    gradient by c > 0 leaves the trajectory unchanged (while eps is negligible);
+    a moment that mixes g and g^2 wrongly would not be."""
+    rng = np.random.default_rng(8)
+    w0 = rng.normal(size=128).astype(np.float32)
+    gs = [rng.normal(size=128).astype(np.float32) for _ in range(6)]
+    traj = []
+    for c in (1.0, 1000.0):
+        w, m, v = w0.copy(), np.zeros(128, np.float32), np.zeros(128, np.float32)
+        for t, g in enumerate(gs, 1):
+            w, m, v = S.adam(w, (g * c).astype(np.float32), m, v, t, lr=1e-3)
+        traj.append(w)
+    assert np.allclose(traj[0], traj[1], atol=1e-6)
+    assert np.abs(traj[0] - w0).max() > 1e-3
