@@ -32,7 +32,9 @@
  *    back into `stream` by events, so the call stays ordered on `stream`.  A
  *    context's scratch serves one call at a time: calls on different streams
  *    with one context must be ordered by the caller (or use one context each).
- *  - Errors: no C++ exception crosses this ABI.  Argument errors found on the
+ *  - Errors: no C++ exception crosses this ABI (a failed host allocation
+ *    inside the library returns CM_ENOMEM, any other internal exception
+ *    CM_EDEVICE; the context stays usable).  Argument errors found on the
  *    host are returned immediately and nothing is enqueued.  Data errors found
  *    on the device (residue code >= 20, sequence index out of range, sequence
  *    longer than CM_MAX_LEN, end cell outside its sequence) make the affected
@@ -41,6 +43,11 @@
  *    of the calling thread.
  *  - A context is not thread-safe; use one per host thread.  Results never
  *    depend on the launch plan (bit-identical across plans and runs).
+ *  - Test hook: with the environment variable CM_TEST_FAIL_ALLOC=device every
+ *    growth of a context's device scratch fails (CM_ENOMEM); with
+ *    CM_TEST_FAIL_ALLOC=host the ClusterMerge driver's final stage fails a
+ *    host allocation while a batch is on the device (CM_ENOMEM).  The variable
+ *    is read at each allocation, so unsetting it restores normal operation.
  */
 #ifndef CM_H
 #define CM_H
@@ -55,7 +62,7 @@ typedef int32_t cm_status;
 #define CM_OK            0
 #define CM_EINVAL       -1   /* bad scalar argument, NULL pointer, gap signs */
 #define CM_ERANGE       -2   /* residue >= 20, index >= n_seqs, length > CM_MAX_LEN */
-#define CM_ENOMEM       -3   /* device allocation failed */
+#define CM_ENOMEM       -3   /* device or host allocation failed */
 #define CM_EDEVICE      -4   /* HIP runtime error (see cm_last_error) */
 #define CM_EUNSUPPORTED -5   /* e.g. |matrix entry| > 127 */
 
@@ -328,6 +335,33 @@ cm_status cm_screen_infer(const cm_screen* s, const uint16_t* feat, const int32_
  * 1 = similar) into host fp32 [num_params]; loss (host, nullable). n <= 2^20. */
 cm_status cm_screen_grads(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
                           int64_t n_pairs, float* host_grads, float* loss);
+/* A training run (the learned screen's training on GPU-Smith-Waterman labels):
+ * epochs passes over the n_pairs rows; each epoch visits them in an order
+ * drawn from `seed` (Fisher-Yates over a splitmix64 stream seeded from the
+ * seed and the epoch number) or, with shuffle = 0, in the given order; every
+ * `batch` consecutive rows of that order make one Adam step (lr; beta 0.9 /
+ * 0.999, eps 1e-8), and a last partial batch is a smaller step unless
+ * drop_last = 1 skips it. */
+typedef struct {
+    int32_t epochs;       /* >= 1 */
+    int32_t batch;        /* pairs per step, 1 .. 2^20 */
+    float lr;             /* > 0 */
+    int32_t shuffle;      /* 0 or 1 */
+    uint64_t seed;
+    int32_t drop_last;    /* 0 or 1 */
+} cm_train_cfg;
+/* Number of steps (= loss-log entries) a training run makes; -1 for a bad config. */
+int64_t   cm_screen_train_steps(int64_t n_pairs, const cm_train_cfg* cfg);
+/* Run the whole training on the device (features as from cm_kmer_features,
+ * pairs device i32 [n_pairs][2], labels device u8 [n_pairs], 1 = similar):
+ * every step's gather, forward, backward, loss and Adam update are enqueued
+ * back to back on the screen's stream, with no host round trip between steps.
+ * loss_log (host, nullable, cm_screen_train_steps() floats) receives every
+ * step's mean loss before its update.  Synchronous: returns when the run is
+ * done.  Equivalent, bit for bit, to cm_screen_train_step over the same
+ * batches.  CM_EINVAL for a bad config or n_pairs outside [1, 2^31 - 1]. */
+cm_status cm_screen_train(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                          int64_t n_pairs, const cm_train_cfg* cfg, float* loss_log);
 /* Synchronous: one Adam step on the batch; loss (host, nullable) is the batch's
  * mean loss before the update. */
 cm_status cm_screen_train_step(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,

@@ -458,6 +458,17 @@ _lib.cm_screen_grads.restype = _i32
 _lib.cm_screen_grads.argtypes = [_P, _P, _P, _P, _i64, _P, ctypes.POINTER(_f32)]
 _lib.cm_screen_train_step.restype = _i32
 _lib.cm_screen_train_step.argtypes = [_P, _P, _P, _P, _i64, _f32, ctypes.POINTER(_f32)]
+
+
+class CMTrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", _i32), ("batch", _i32), ("lr", _f32), ("shuffle", _i32), ("seed", _u64),
+                ("drop_last", _i32)]
+
+
+_lib.cm_screen_train_steps.restype = _i64
+_lib.cm_screen_train_steps.argtypes = [_i64, ctypes.POINTER(CMTrainCfg)]
+_lib.cm_screen_train.restype = _i32
+_lib.cm_screen_train.argtypes = [_P, _P, _P, _P, _i64, ctypes.POINTER(CMTrainCfg), _P]
 _lib.cm_screen_save.restype = _i32
 _lib.cm_screen_save.argtypes = [_P, ctypes.c_char_p]
 _lib.cm_screen_load.restype = _i32
@@ -544,6 +555,24 @@ class Screen:
         _check(_lib.cm_screen_grads(self.handle, feat.data_ptr(), pairs.data_ptr(), labels.data_ptr(),
                                     pairs.numel() // 2, g.ctypes.data, ctypes.byref(loss)))
         return g, loss.value
+
+    def train(self, feat, pairs, labels, epochs: int = 5, batch: int = 4096, lr: float = 1e-3,
+              shuffle: bool = True, seed: int = 0, drop_last: bool = True) -> np.ndarray:
+        """A whole training run on the device (cm_screen_train); returns the
+        per-step mean loss log (numpy float32, one entry per Adam step)."""
+        import torch
+        torch.cuda.current_stream().synchronize()
+        pairs = _dev(pairs, torch.int32, "pairs")
+        labels = _dev(labels, torch.uint8, "labels")
+        cfg = CMTrainCfg(int(epochs), int(batch), float(lr), int(bool(shuffle)), int(seed), int(bool(drop_last)))
+        n = pairs.numel() // 2
+        steps = _lib.cm_screen_train_steps(n, ctypes.byref(cfg))
+        if steps < 1:
+            raise ValueError(f"training config makes no step ({steps}) for {n} pairs")
+        log = np.zeros(steps, np.float32)
+        _check(_lib.cm_screen_train(self.handle, feat.data_ptr(), pairs.data_ptr(), labels.data_ptr(), n,
+                                    ctypes.byref(cfg), log.ctypes.data))
+        return log
 
     def train_step(self, feat, pairs, labels, lr: float = 1e-3) -> float:
         import torch

@@ -4,6 +4,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -32,8 +33,18 @@ cm_status hip_fail(hipError_t e, const char* what) {
                 hipGetErrorString(e));
 }
 
+bool test_fail_alloc(const char* site) {
+    const char* v = getenv("CM_TEST_FAIL_ALLOC");
+    return v && std::strcmp(v, site) == 0;
+}
+
+void test_host_alloc_point() {
+    if (test_fail_alloc("host")) throw std::bad_alloc();
+}
+
 bool DeviceBuf::ensure(size_t bytes) {
     if (bytes <= cap) return true;
+    if (test_fail_alloc("device")) return false;
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     cap = 0;
@@ -100,6 +111,7 @@ static cm_status run_pass_q(cm_context* ctx, cmk::SwArgs& a, hipStream_t st, int
     const int64_t n = a.n_pairs;
     if (!ensure_plan_q(ctx, n)) return fail(CM_ENOMEM, "cannot allocate the shared-query plan for %lld pairs",
                                             static_cast<long long>(n));
+    a.over = static_cast<int32_t*>(ctx->over.ptr);
     const int ni = static_cast<int>(n);
     uint64_t* keys = static_cast<uint64_t*>(ctx->keys.ptr);
     uint64_t* keys_s = static_cast<uint64_t*>(ctx->keys_alt.ptr);
@@ -160,86 +172,119 @@ static cm_status run_pass_q(cm_context* ctx, cmk::SwArgs& a, hipStream_t st, int
     return CM_OK;
 }
 
-// plan -> sort -> persistent sweep for one pass
-cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st) {
-    if (a.n_pairs <= 0) return CM_OK;
-    if (a.n_pairs > (int64_t)0x7fffffff) return fail(CM_EINVAL, "n_pairs too large");
-    const size_t n = static_cast<size_t>(a.n_pairs);
-    if (!ctx->keys.ensure(n * 4) || !ctx->keys_alt.ensure(n * 4) || !ctx->vals.ensure(n * 4) ||
-        !ctx->vals_alt.ensure(n * 4))
-        return fail(CM_ENOMEM, "cannot allocate %zu plan entries", n);
-    size_t tmp = 0;
-    hipError_t e = hipcub::DeviceRadixSort::SortPairs(
-        nullptr, tmp, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<uint32_t*>(ctx->keys_alt.ptr),
-        static_cast<int32_t*>(ctx->vals.ptr), static_cast<int32_t*>(ctx->vals_alt.ptr),
-        static_cast<int>(n), 0, 32, st);
-    if (e != hipSuccess) return hip_fail(e, "sort size query");
-    if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
+// a timing event pair for the next launch (or -1 when timing is off)
+static cm_status timer_slot(cm_context* ctx, int* pair) {
+    KernelTimer& kt = ctx->timer;
+    *pair = -1;
+    if (!kt.on) return CM_OK;
+    if (kt.next * 2 + 2 > kt.pool.size()) {
+        hipEvent_t b, c;
+        if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&c) != hipSuccess)
+            return fail(CM_EDEVICE, "timing events");
+        kt.pool.push_back(b);
+        kt.pool.push_back(c);
+    }
+    *pair = static_cast<int>(kt.next++);
+    return CM_OK;
+}
 
-    const cm_context::Plan& plan = ctx->plan[static_cast<int>(pass)];
-    const bool packed = pass == cmk::Pass::Score && plan.packed;
+// plan -> sort -> persistent sweep of one pass (int32 or two-profile packed
+// kernel) on scratch the caller provides; allocates nothing
+cm_status run_pass_scratch(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, const PassScratch& ps,
+                           hipStream_t st) {
+    const int n = static_cast<int>(a.n_pairs);
+    const bool packed = pass == cmk::Pass::Score && ps.packed;
     if (packed) {
-        if (!ctx->over.ensure(n * 4)) return fail(CM_ENOMEM, "cannot allocate %zu saturation slots", n);
         a.packed = 1;
-        a.over = static_cast<int32_t*>(ctx->over.ptr);
+        a.over = ps.over;
         const uint32_t go = static_cast<uint32_t>(-static_cast<int64_t>(a.go) < 65535 ? -a.go : 65535);
         const uint32_t ge = static_cast<uint32_t>(-static_cast<int64_t>(a.ge) < 65535 ? -a.ge : 65535);
         a.go_pk = go * 0x10001u;
         a.ge_pk = ge * 0x10001u;
     }
-    a.rmax = plan.rmax;
-    a.ctr = ctx->counters;
+    a.rmax = ps.rmax;
+    a.ctr = ps.ctr;
     a.err = ctx->err_flag;
     a.dummy = ctx->dummy;
     a.bnd = static_cast<int2*>(ctx->bnd.ptr);
     a.bnd_stride = ctx->bnd_stride;
     a.zero = 0;
-    if (packed && plan.packed == 2) {
-        a.over = static_cast<int32_t*>(ctx->over.ptr);
-        int timer_pair = -1;
-        KernelTimer& kt = ctx->timer;
-        if (kt.on) {
-            if (kt.next * 2 + 2 > kt.pool.size()) {
-                hipEvent_t b, c;
-                if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&c) != hipSuccess)
-                    return fail(CM_EDEVICE, "timing events");
-                kt.pool.push_back(b);
-                kt.pool.push_back(c);
-            }
-            timer_pair = static_cast<int>(kt.next++);
-        }
-        return run_pass_q(ctx, a, st, timer_pair);
-    }
-    e = cmk::launch_plan(a, pass, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<int32_t*>(ctx->vals.ptr), st);
+    hipError_t e = cmk::launch_plan(a, pass, ps.keys, ps.vals, st);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
-    e = hipcub::DeviceRadixSort::SortPairs(
-        ctx->sort_tmp.ptr, tmp, static_cast<uint32_t*>(ctx->keys.ptr), static_cast<uint32_t*>(ctx->keys_alt.ptr),
-        static_cast<int32_t*>(ctx->vals.ptr), static_cast<int32_t*>(ctx->vals_alt.ptr),
-        static_cast<int>(n), 0, 32, st);
+    size_t tmp = ps.sort_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(ps.sort_tmp, tmp, ps.keys, ps.keys_alt, ps.vals, ps.vals_alt, n, 0, 32, st);
     if (e != hipSuccess) return hip_fail(e, "sort");
-    a.keys = static_cast<const uint32_t*>(ctx->keys_alt.ptr);
-    a.order = static_cast<const int32_t*>(ctx->vals_alt.ptr);
-    const int grid = ctx->n_cu * plan.blocks_per_cu;
-    KernelTimer& kt = ctx->timer;
+    a.keys = ps.keys_alt;
+    a.order = ps.vals_alt;
     int pair = -1;
-    if (kt.on) {
-        if (kt.next * 2 + 2 > kt.pool.size()) {
-            hipEvent_t b, c;
-            if (hipEventCreate(&b) != hipSuccess || hipEventCreate(&c) != hipSuccess)
-                return fail(CM_EDEVICE, "timing events");
-            kt.pool.push_back(b);
-            kt.pool.push_back(c);
-        }
-        pair = static_cast<int>(kt.next++);
-        (void)hipEventRecord(kt.pool[2 * pair], st);
+    if (ps.timed) {
+        cm_status r = timer_slot(ctx, &pair);
+        if (r != CM_OK) return r;
     }
-    e = packed ? cmk::launch_sw_pk(a, grid, ctx->n_cu * ctx->occ_over, st) : cmk::launch_sw(a, pass, grid, st);
+    KernelTimer& kt = ctx->timer;
+    if (pair >= 0) (void)hipEventRecord(kt.pool[2 * pair], st);
+    e = packed ? cmk::launch_sw_pk(a, ps.grid, ctx->n_cu * ctx->occ_over, st) : cmk::launch_sw(a, pass, ps.grid, st);
     if (e != hipSuccess) return hip_fail(e, "alignment launch");
     if (pair >= 0) {
         (void)hipEventRecord(kt.pool[2 * pair + 1], st);
         kt.pending.emplace_back(static_cast<int>(pass), pair);
     }
     return CM_OK;
+}
+
+size_t sort_temp_bytes(int64_t n) {
+    size_t tmp = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, static_cast<uint32_t*>(nullptr),
+                                             static_cast<uint32_t*>(nullptr), static_cast<int32_t*>(nullptr),
+                                             static_cast<int32_t*>(nullptr), static_cast<int>(n), 0, 32);
+    return tmp;
+}
+
+// plan -> sort -> persistent sweep for one pass
+cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t st) {
+    if (a.n_pairs <= 0) return CM_OK;
+    if (a.n_pairs > (int64_t)0x7fffffff) return fail(CM_EINVAL, "n_pairs too large");
+    const size_t n = static_cast<size_t>(a.n_pairs);
+    const cm_context::Plan& plan = ctx->plan[static_cast<int>(pass)];
+    const bool packed = pass == cmk::Pass::Score && plan.packed;
+    if (packed && plan.packed == 2) {
+        a.rmax = plan.rmax;
+        a.ctr = ctx->counters;
+        a.err = ctx->err_flag;
+        a.dummy = ctx->dummy;
+        a.bnd = static_cast<int2*>(ctx->bnd.ptr);
+        a.bnd_stride = ctx->bnd_stride;
+        a.zero = 0;
+        a.packed = 1;
+        const uint32_t go = static_cast<uint32_t>(-static_cast<int64_t>(a.go) < 65535 ? -a.go : 65535);
+        const uint32_t ge = static_cast<uint32_t>(-static_cast<int64_t>(a.ge) < 65535 ? -a.ge : 65535);
+        a.go_pk = go * 0x10001u;
+        a.ge_pk = ge * 0x10001u;
+        int timer_pair = -1;
+        cm_status r = timer_slot(ctx, &timer_pair);
+        if (r != CM_OK) return r;
+        return run_pass_q(ctx, a, st, timer_pair);
+    }
+    if (!ctx->keys.ensure(n * 4) || !ctx->keys_alt.ensure(n * 4) || !ctx->vals.ensure(n * 4) ||
+        !ctx->vals_alt.ensure(n * 4))
+        return fail(CM_ENOMEM, "cannot allocate %zu plan entries", n);
+    const size_t tmp = sort_temp_bytes(a.n_pairs);
+    if (!ctx->sort_tmp.ensure(tmp)) return fail(CM_ENOMEM, "cannot allocate sort scratch");
+    if (packed && !ctx->over.ensure(n * 4)) return fail(CM_ENOMEM, "cannot allocate %zu saturation slots", n);
+    PassScratch ps;
+    ps.packed = packed ? 1 : 0;
+    ps.rmax = plan.rmax;
+    ps.grid = ctx->n_cu * plan.blocks_per_cu;
+    ps.keys = static_cast<uint32_t*>(ctx->keys.ptr);
+    ps.keys_alt = static_cast<uint32_t*>(ctx->keys_alt.ptr);
+    ps.vals = static_cast<int32_t*>(ctx->vals.ptr);
+    ps.vals_alt = static_cast<int32_t*>(ctx->vals_alt.ptr);
+    ps.over = packed ? static_cast<int32_t*>(ctx->over.ptr) : nullptr;
+    ps.sort_tmp = ctx->sort_tmp.ptr;
+    ps.sort_bytes = ctx->sort_tmp.cap;
+    ps.ctr = ctx->counters;
+    ps.timed = true;
+    return run_pass_scratch(ctx, a, pass, ps, st);
 }
 
 void drain_timers(cm_context* ctx, bool blocking) {
@@ -321,10 +366,10 @@ cm_status reserve(cm_context* ctx, int64_t n) {
     return CM_OK;
 }
 
-cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
-                      const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
-                      int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
-                      hipStream_t stream) {
+cm_status score_args(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                     const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                     cmk::SwArgs& a) {
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative count");
     if (n_pairs == 0) return CM_OK;
@@ -332,7 +377,7 @@ cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offse
     if ((end_a == nullptr) != (end_b == nullptr)) return fail(CM_EINVAL, "end_a and end_b must both be set or both NULL");
     cm_status s = check_gaps(gap_open, gap_extend);
     if (s != CM_OK) return s;
-    cmk::SwArgs a{};
+    a = cmk::SwArgs{};
     s = check_matrix(matrix, a.mat);
     if (s != CM_OK) return s;
     hipError_t e = hipSetDevice(ctx->device);
@@ -348,6 +393,17 @@ cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offse
     a.scores = scores;
     a.end_a = end_a;
     a.end_b = end_b;
+    return CM_OK;
+}
+
+cm_status score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                      const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                      int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                      hipStream_t stream) {
+    cmk::SwArgs a{};
+    cm_status s = score_args(ctx, seqs, offsets, n_seqs, pairs, n_pairs, n_live, matrix, gap_open, gap_extend, scores,
+                             end_a, end_b, a);
+    if (s != CM_OK || n_pairs == 0) return s;
     return run_pass(ctx, a, end_a ? cmk::Pass::ScoreEnd : cmk::Pass::Score, stream);
 }
 
@@ -439,6 +495,7 @@ const char* cm_status_str(cm_status s) {
 const char* cm_last_error(void) { return g_last_error.c_str(); }
 
 cm_status cm_context_create(int device_ordinal, cm_context** out) {
+    CM_TRY
     if (!out) return fail(CM_EINVAL, "out is NULL");
     *out = nullptr;
     int ndev = 0;
@@ -507,9 +564,11 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     if (cache && *cache) (void)load_plans(ctx, cache);   // a missing or corrupt cache keeps the defaults
     *out = ctx;
     return CM_OK;
+    CM_CATCH
 }
 
 void cm_context_destroy(cm_context* ctx) {
+    CM_TRY
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
@@ -531,9 +590,11 @@ void cm_context_destroy(cm_context* ctx) {
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->small) (void)hipFree(ctx->small);
     delete ctx;
+    CM_CATCH_VOID
 }
 
 cm_status cm_context_sync(cm_context* ctx) {
+    CM_TRY
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -556,31 +617,39 @@ cm_status cm_context_sync(cm_context* ctx) {
                     (flag & cmk::kErrCapacity) ? " column buffer too small" : "");
     }
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_context_set_timing(cm_context* ctx, int on) {
+    CM_TRY
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     drain_timers(ctx, true);
     ctx->timer.on = on != 0;
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_context_set_graphs(cm_context* ctx, int on) {
+    CM_TRY
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     ctx->graphs = on != 0;
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds) {
+    CM_TRY
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
     drain_timers(ctx, true);
     if (launches) *launches = ctx->timer.launches[pass];
     if (seconds) *seconds = ctx->timer.secs[pass];
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t* rmax, int32_t* blocks_per_cu,
                       int32_t* max_blocks_per_cu) {
+    CM_TRY
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
     const cm_context::Plan& pl = ctx->plan[pass];
     if (packed) *packed = pl.packed;
@@ -588,9 +657,11 @@ cm_status cm_plan_get(const cm_context* ctx, int pass, int32_t* packed, int32_t*
     if (blocks_per_cu) *blocks_per_cu = pl.blocks_per_cu;
     if (max_blocks_per_cu) *max_blocks_per_cu = plan_limit(ctx, pass, pl.packed, pl.rmax);
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, int32_t blocks_per_cu) {
+    CM_TRY
     if (!ctx || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
     if (packed < 0 || packed > 2) return fail(CM_EINVAL, "packed must be 0, 1 or 2");
     if (packed && pass != CM_PASS_SCORE) return fail(CM_EINVAL, "the packed kernels serve the score pass only");
@@ -605,31 +676,40 @@ cm_status cm_plan_set(cm_context* ctx, int pass, int32_t packed, int32_t rmax, i
     ctx->plan[pass].rmax = rmax;
     ctx->plan[pass].blocks_per_cu = blocks_per_cu;
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_plan_save(const cm_context* ctx, const char* path) {
+    CM_TRY
     if (!ctx || !path) return fail(CM_EINVAL, "bad argument");
     return save_plans(ctx, path);
+    CM_CATCH
 }
 
 cm_status cm_plan_load(cm_context* ctx, const char* path) {
+    CM_TRY
     if (!ctx || !path) return fail(CM_EINVAL, "bad argument");
     return load_plans(ctx, path);
+    CM_CATCH
 }
 
 cm_status cm_sw_score_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                             const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
                             int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b, void* stream) {
+    CM_TRY
     return score_batch(ctx, seqs, offsets, n_seqs, pairs, n_pairs, nullptr, matrix, gap_open, gap_extend, scores,
                        end_a, end_b, static_cast<hipStream_t>(stream));
+    CM_CATCH
 }
 
 cm_status cm_sw_span_batch(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                            const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
                            int32_t gap_extend, const int32_t* scores, const int32_t* end_a, const int32_t* end_b,
                            int32_t min_score, int32_t* start_a, int32_t* start_b, void* stream) {
+    CM_TRY
     return span_batch(ctx, seqs, offsets, n_seqs, pairs, n_pairs, nullptr, matrix, gap_open, gap_extend, scores,
                       end_a, end_b, min_score, start_a, start_b, static_cast<hipStream_t>(stream));
+    CM_CATCH
 }
 
 }  // extern "C"

@@ -24,6 +24,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "../../include/cm.h"
@@ -218,6 +219,9 @@ struct Aligner {
         return CM_OK;
     }
     ~Aligner() {
+        // work still in flight (an error return or an exception between a
+        // submit and its wait) may write into the pinned staging: let it land
+        if (st) (void)hipStreamSynchronize(st);
         for (Graph& g : graphs) (void)hipGraphExecDestroy(g.exec);
         for (Slot& sl : slot) {
             if (sl.e0) (void)hipEventDestroy(sl.e0);
@@ -1400,6 +1404,8 @@ cm_status Driver::final_stage(cm_result* res) {
         }
         cm_status s = al_.submit(cur, c.gpu.data(), static_cast<int64_t>(c.gpu.size() / 2), false);
         if (s != CM_OK) return s;
+        // test hook: a host allocation failing while a chunk is on the device
+        cmrt::test_host_alloc_point();
         auto q1 = Clock::now();
         t_submit += secs(q0, q1);
         if (inflight) {
@@ -1494,7 +1500,13 @@ cm_status Driver::final_stage(cm_result* res) {
 cm_status Driver::run(cm_result** out) {
     const auto t0 = Clock::now();
     cmrt::drain_timers(ctx_, true);
-    const bool timer_was_on = ctx_->timer.on;
+    // every launch of the run is timed; the caller's setting comes back on
+    // every return, including errors
+    struct TimerRestore {
+        cm_context* ctx;
+        bool was_on;
+        ~TimerRestore() { ctx->timer.on = was_on; }
+    } restore{ctx_, ctx_->timer.on};
     ctx_->timer.on = true;
     const int64_t l0 = ctx_->timer.launches[0];
     const double k0 = ctx_->timer.secs[0];
@@ -1577,9 +1589,9 @@ cm_status Driver::run(cm_result** out) {
     }
     if (sets_.empty()) sets_.emplace_back();
     const auto t1 = Clock::now();
-    cm_result* res = new cm_result();
-    s = final_stage(res);
-    if (s != CM_OK) { delete res; return s; }
+    std::unique_ptr<cm_result> res(new cm_result());
+    s = final_stage(res.get());
+    if (s != CM_OK) return s;
     const auto t2 = Clock::now();
     int64_t needed = 0;
     // speculative work = aligned pairs the replay and the final stage never read
@@ -1593,9 +1605,8 @@ cm_status Driver::run(cm_result** out) {
     st_.sw_launches = ctx_->timer.launches[0] - l0;
     st_.sw_kernel_s = ctx_->timer.secs[0] - k0;
     st_.end_kernel_s = ctx_->timer.secs[1] + ctx_->timer.secs[2] - e0;
-    ctx_->timer.on = timer_was_on;
     res->stats = st_;
-    *out = res;
+    *out = res.release();
     return CM_OK;
 }
 
@@ -1655,6 +1666,7 @@ static cm_status check_run_params(const cm_params* params) {
 
 cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                               const cm_params* params, const cm_screen* screen, cm_result** out) {
+    CM_TRY
     if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
     if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
     *out = nullptr;
@@ -1663,6 +1675,7 @@ cm_status cm_clustermerge_run(cm_context* ctx, const uint8_t* seqs, const int64_
     if (hipSetDevice(ctx->device) != hipSuccess) return cmrt::fail(CM_EDEVICE, "hipSetDevice");
     cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params, screen);
     return drv.run(out);
+    CM_CATCH
 }
 
 cm_status cm_clustermerge_extend(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
@@ -1670,6 +1683,7 @@ cm_status cm_clustermerge_extend(cm_context* ctx, const uint8_t* seqs, const int
                                  int32_t n_clusters, const int32_t* reps, const int64_t* member_offsets,
                                  const int32_t* members, int64_t n_known, const int32_t* known_pairs,
                                  const int32_t* known_scores, cm_result** out) {
+    CM_TRY
     if (!ctx || !params || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
     if (!offsets || n_seqs < 0) return cmrt::fail(CM_EINVAL, "bad store");
     *out = nullptr;
@@ -1720,30 +1734,37 @@ cm_status cm_clustermerge_extend(cm_context* ctx, const uint8_t* seqs, const int
     cmdrv::Driver drv(ctx, seqs, offsets, n_seqs, params, screen);
     drv.set_prev(&prev);
     return drv.run(out);
+    CM_CATCH
 }
 
 cm_status cm_result_clusters(const cm_result* r, int32_t* n_clusters, const int32_t** reps,
                              const int64_t** member_offsets, const int32_t** members) {
+    CM_TRY
     if (!r) return cmrt::fail(CM_EINVAL, "result is NULL");
     if (n_clusters) *n_clusters = static_cast<int32_t>(r->reps.size());
     if (reps) *reps = r->reps.data();
     if (member_offsets) *member_offsets = r->member_offsets.data();
     if (members) *members = r->members.data();
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_result_pairs(const cm_result* r, int64_t* n_pairs, const int32_t** pairs, const int32_t** scores) {
+    CM_TRY
     if (!r) return cmrt::fail(CM_EINVAL, "result is NULL");
     if (n_pairs) *n_pairs = static_cast<int64_t>(r->pair_scores.size());
     if (pairs) *pairs = r->pairs.data();
     if (scores) *scores = r->pair_scores.data();
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_result_stats(const cm_result* r, cm_stats* out) {
+    CM_TRY
     if (!r || !out) return cmrt::fail(CM_EINVAL, "NULL argument");
     *out = r->stats;
     return CM_OK;
+    CM_CATCH
 }
 
 void cm_result_free(cm_result* r) { delete r; }
@@ -1751,6 +1772,7 @@ void cm_result_free(cm_result* r) { delete r; }
 cm_status cm_allvsall_count(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                             const int32_t* matrix, int32_t gap_open, int32_t gap_extend, int32_t T,
                             int64_t* count, double* cells) {
+    CM_TRY
     if (!ctx || !offsets || !count) return cmrt::fail(CM_EINVAL, "NULL argument");
     *count = 0;
     if (cells) *cells = 0;
@@ -1795,6 +1817,7 @@ cm_status cm_allvsall_count(cm_context* ctx, const uint8_t* seqs, const int64_t*
         *cells = (s1 * s1 - s2) / 2;
     }
     return CM_OK;
+    CM_CATCH
 }
 
 }  // extern "C"

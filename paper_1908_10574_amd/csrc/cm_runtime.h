@@ -7,6 +7,8 @@
 #include "../../include/cm.h"
 #include "cm_internal.h"
 
+#include <exception>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -22,6 +24,13 @@ struct DeviceBuf {
 
 cm_status fail(cm_status s, const char* fmt, ...);
 cm_status hip_fail(hipError_t e, const char* what);
+
+// Test hook: when the environment variable CM_TEST_FAIL_ALLOC equals `site`
+// ("host": a large host allocation of the ClusterMerge driver; "device":
+// every growth of a context's device scratch), the allocation fails.
+bool test_fail_alloc(const char* site);
+// throws std::bad_alloc when test_fail_alloc("host") holds
+void test_host_alloc_point();
 cm_status check_matrix(const int32_t* matrix, int8_t* mat8);
 cm_status check_gaps(int32_t go, int32_t ge);
 
@@ -36,6 +45,26 @@ struct KernelTimer {
 };
 
 }  // namespace cmrt
+
+// Every extern "C" body runs inside CM_TRY ... CM_CATCH so that no C++
+// exception crosses the ABI: a failed host allocation becomes CM_ENOMEM,
+// anything else CM_EDEVICE, with the detail in cm_last_error().
+#define CM_TRY try {
+#define CM_CATCH                                                                          \
+    }                                                                                     \
+    catch (const std::bad_alloc&) {                                                       \
+        return cmrt::fail(CM_ENOMEM, "host memory exhausted");                            \
+    }                                                                                     \
+    catch (const std::exception& ex_) {                                                   \
+        return cmrt::fail(CM_EDEVICE, "internal error: %s", ex_.what());                  \
+    }                                                                                     \
+    catch (...) {                                                                         \
+        return cmrt::fail(CM_EDEVICE, "internal error");                                  \
+    }
+#define CM_CATCH_VOID                                                                     \
+    }                                                                                     \
+    catch (...) {                                                                         \
+    }
 
 struct cm_context {
     int device = 0;
@@ -81,6 +110,29 @@ struct cm_context {
 };
 
 namespace cmrt {
+// Scratch of one plan -> sort -> sweep pass on the int32 or the two-profile
+// packed kernel (plan kinds 0 and 1): plan keys and values and their sorted
+// copies (n_pairs each), the saturated-pair list (packed), the radix-sort
+// temp and the counters block.
+struct PassScratch {
+    int packed = 0, rmax = 16, grid = 0;
+    uint32_t* keys = nullptr;
+    uint32_t* keys_alt = nullptr;
+    int32_t* vals = nullptr;
+    int32_t* vals_alt = nullptr;
+    int32_t* over = nullptr;
+    void* sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    cmk::Counters* ctr = nullptr;
+    bool timed = false;
+};
+cm_status run_pass_scratch(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, const PassScratch& ps, hipStream_t st);
+size_t sort_temp_bytes(int64_t n);
+// argument checks and SwArgs of a score / score+end batch (nothing enqueued)
+cm_status score_args(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                     const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
+                     cmk::SwArgs& a);
 // accumulate the durations of timed launches that have completed
 // (blocking = wait for all of them)
 void drain_timers(cm_context* ctx, bool blocking);

@@ -1,4 +1,5 @@
 // cm_screen.hip -- host side of the learned pair screen (C ABI in include/cm.h).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +21,8 @@ struct cm_screen {
     // per-batch workspace, sized for cap rows
     DeviceBuf h1, h1t, h2, z, dz, loss, dh2, dh2t, dh1t, xt;
     DeviceBuf gpart;                       // fp32 [cap / 64][kHidden]: layer-3 gradient partials
+    // training runs: epoch orders, the current batch's rows and labels, loss log
+    DeviceBuf perm, bpairs, blabels, losslog;
     int cap = 0;
     int step = 0;
 };
@@ -136,6 +139,25 @@ uint64_t splitmix(uint64_t& x) {
     return z ^ (z >> 31);
 }
 
+// the order of epoch `e`: 0..n-1 shuffled by Fisher-Yates with a splitmix64
+// stream seeded from (seed, e), or the identity
+void epoch_order(int64_t n, bool shuffle, uint64_t seed, int64_t e, int32_t* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = static_cast<int32_t>(i);
+    if (!shuffle) return;
+    uint64_t x = seed ^ (0xd1b54a32d192ed03ull * static_cast<uint64_t>(e + 1));
+    for (int64_t i = n - 1; i > 0; --i) {
+        // uniform j in [0, i] by rejection on the top bits
+        const uint64_t bound = static_cast<uint64_t>(i) + 1;
+        const uint64_t lim = UINT64_MAX - UINT64_MAX % bound;
+        uint64_t r;
+        do { r = splitmix(x); } while (r >= lim);
+        const int64_t j = static_cast<int64_t>(r % bound);
+        const int32_t t = out[i];
+        out[i] = out[j];
+        out[j] = t;
+    }
+}
+
 cm_status upload_master(cm_screen* s, const float* host) {
     cm_status r = chk(hipMemcpyAsync(s->master.ptr, host, cms::kParams * 4, hipMemcpyHostToDevice, s->st), "weights");
     if (r != CM_OK) return r;
@@ -145,6 +167,24 @@ cm_status upload_master(cm_screen* s, const float* host) {
             "pack");
     if (r != CM_OK) return r;
     return chk(hipStreamSynchronize(s->st), "upload");
+}
+
+// one Adam update of the master weights from s->grad, then the bf16 copies
+cm_status adam_step(cm_screen* s, float lr) {
+    s->step += 1;
+    cm_status r = chk(cms::launch_adam(static_cast<float*>(s->master.ptr), static_cast<const float*>(s->grad.ptr),
+                                       static_cast<float*>(s->mom.ptr), static_cast<float*>(s->vel.ptr), cms::kParams,
+                                       lr, 0.9f, 0.999f, 1e-8f, s->step, s->st),
+                      "adam");
+    if (r != CM_OK) return r;
+    return chk(cms::launch_pack(static_cast<const float*>(s->master.ptr), static_cast<uint16_t*>(s->w1.ptr),
+                                static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
+                                static_cast<uint16_t*>(s->w3.ptr), s->st),
+               "pack");
+}
+
+int64_t train_steps(int64_t n, const cm_train_cfg* c) {
+    return c->drop_last ? n / c->batch : (n + c->batch - 1) / c->batch;
 }
 
 cm_status reset_adam(cm_screen* s) {
@@ -160,15 +200,18 @@ extern "C" {
 
 cm_status cm_kmer_features(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                            uint16_t* feat, void* stream) {
+    CM_TRY
     if (!ctx || !offsets || !feat || n_seqs < 0) return fail(CM_EINVAL, "bad argument");
     if (n_seqs == 0) return CM_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
     return chk(cms::launch_kmer(seqs ? seqs : ctx->dummy, offsets, n_seqs, feat, ctx->err_flag,
                                 static_cast<hipStream_t>(stream)),
                "features");
+    CM_CATCH
 }
 
 cm_status cm_screen_create(cm_context* ctx, uint64_t seed, cm_screen** out) {
+    CM_TRY
     if (!ctx || !out) return fail(CM_EINVAL, "bad argument");
     *out = nullptr;
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
@@ -196,28 +239,35 @@ cm_status cm_screen_create(cm_context* ctx, uint64_t seed, cm_screen** out) {
     if (r != CM_OK) { cm_screen_destroy(s); return r; }
     *out = s;
     return CM_OK;
+    CM_CATCH
 }
 
 void cm_screen_destroy(cm_screen* s) {
+    CM_TRY
     if (!s) return;
     if (s->st) { (void)hipStreamSynchronize(s->st); (void)hipStreamDestroy(s->st); }
     for (DeviceBuf* b : {&s->master, &s->mom, &s->vel, &s->grad, &s->w1, &s->w2, &s->w2t, &s->w3, &s->h1, &s->h1t,
-                         &s->h2, &s->z, &s->dz, &s->loss, &s->dh2, &s->dh2t, &s->dh1t, &s->xt})
+                         &s->h2, &s->z, &s->dz, &s->loss, &s->dh2, &s->dh2t, &s->dh1t, &s->xt, &s->gpart,
+                         &s->perm, &s->bpairs, &s->blabels, &s->losslog})
         b->release();
     delete s;
+    CM_CATCH_VOID
 }
 
 int64_t cm_screen_num_params(void) { return cms::kParams; }
 
 cm_status cm_screen_set_weights(cm_screen* s, const float* host_fp32_master) {
+    CM_TRY
     if (!s || !host_fp32_master) return fail(CM_EINVAL, "bad argument");
     cm_status r = upload_master(s, host_fp32_master);
     if (r == CM_OK) r = reset_adam(s);
     if (r == CM_OK) r = chk(hipStreamSynchronize(s->st), "set weights");
     return r;
+    CM_CATCH
 }
 
 cm_status cm_screen_get_weights(const cm_screen* s, float* host_fp32_master, uint16_t* host_bf16) {
+    CM_TRY
     if (!s) return fail(CM_EINVAL, "bad argument");
     if (host_fp32_master) {
         cm_status r = chk(hipMemcpy(host_fp32_master, s->master.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "get");
@@ -233,10 +283,12 @@ cm_status cm_screen_get_weights(const cm_screen* s, float* host_fp32_master, uin
         if (r != CM_OK) return r;
     }
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_screen_infer(const cm_screen* s_, const uint16_t* feat, const int32_t* pairs, int64_t n_pairs,
                           float* logits, void* stream) {
+    CM_TRY
     cm_screen* s = const_cast<cm_screen*>(s_);
     if (!s || !feat || !pairs || !logits || n_pairs < 0) return fail(CM_EINVAL, "bad argument");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -248,38 +300,91 @@ cm_status cm_screen_infer(const cm_screen* s_, const uint16_t* feat, const int32
         if (r != CM_OK) return r;
     }
     return CM_OK;
+    CM_CATCH
 }
 
 cm_status cm_screen_grads(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
                           int64_t n_pairs, float* host_grads, float* loss) {
+    CM_TRY
     if (!s || !feat || !pairs || !labels || n_pairs <= 0 || n_pairs > (1 << 20)) return fail(CM_EINVAL, "bad argument");
     cm_status r = forward_backward(s, feat, pairs, labels, static_cast<int>(n_pairs), loss);
     if (r != CM_OK) return r;
     if (host_grads) r = chk(hipMemcpy(host_grads, s->grad.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "grads");
     return r;
+    CM_CATCH
 }
 
 cm_status cm_screen_train_step(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
                                int64_t n_pairs, float lr, float* loss) {
+    CM_TRY
     if (!s || !feat || !pairs || !labels || n_pairs <= 0 || n_pairs > (1 << 20) || !(lr > 0.f))
         return fail(CM_EINVAL, "bad argument");
     cm_status r = forward_backward(s, feat, pairs, labels, static_cast<int>(n_pairs), loss);
     if (r != CM_OK) return r;
-    s->step += 1;
-    r = chk(cms::launch_adam(static_cast<float*>(s->master.ptr), static_cast<const float*>(s->grad.ptr),
-                             static_cast<float*>(s->mom.ptr), static_cast<float*>(s->vel.ptr), cms::kParams, lr, 0.9f,
-                             0.999f, 1e-8f, s->step, s->st),
-            "adam");
-    if (r != CM_OK) return r;
-    r = chk(cms::launch_pack(static_cast<const float*>(s->master.ptr), static_cast<uint16_t*>(s->w1.ptr),
-                             static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
-                             static_cast<uint16_t*>(s->w3.ptr), s->st),
-            "pack");
+    r = adam_step(s, lr);
     if (r != CM_OK) return r;
     return chk(hipStreamSynchronize(s->st), "train step");
+    CM_CATCH
+}
+
+int64_t cm_screen_train_steps(int64_t n_pairs, const cm_train_cfg* cfg) {
+    if (!cfg || n_pairs < 0 || cfg->batch < 1 || cfg->epochs < 0) return -1;
+    return static_cast<int64_t>(cfg->epochs) * train_steps(n_pairs, cfg);
+}
+
+cm_status cm_screen_train(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels,
+                          int64_t n_pairs, const cm_train_cfg* cfg, float* loss_log) {
+    CM_TRY
+    if (!s || !feat || !pairs || !labels || !cfg) return fail(CM_EINVAL, "NULL argument");
+    if (n_pairs < 1 || n_pairs > 0x7fffffff) return fail(CM_EINVAL, "n_pairs must be in [1, 2^31 - 1]");
+    if (cfg->epochs < 1 || cfg->batch < 1 || cfg->batch > (1 << 20) || !(cfg->lr > 0.f) ||
+        (cfg->shuffle != 0 && cfg->shuffle != 1) || (cfg->drop_last != 0 && cfg->drop_last != 1))
+        return fail(CM_EINVAL, "training config: epochs >= 1, batch in [1, 2^20], lr > 0, shuffle and drop_last 0/1");
+    const int64_t per_epoch = train_steps(n_pairs, cfg);
+    if (per_epoch < 1) return fail(CM_EINVAL, "no full batch of %d pairs in %lld", cfg->batch,
+                                   static_cast<long long>(n_pairs));
+    const int64_t steps = per_epoch * cfg->epochs;
+    const int mb_max = static_cast<int>(round_up(std::min<int64_t>(cfg->batch, n_pairs), 64));
+    cm_status r = ensure_workspace(s, mb_max);
+    if (r != CM_OK) return r;
+    if (!s->perm.ensure(static_cast<size_t>(n_pairs) * 4 * cfg->epochs) ||
+        !s->bpairs.ensure(static_cast<size_t>(mb_max) * 8) || !s->blabels.ensure(static_cast<size_t>(mb_max)) ||
+        !s->losslog.ensure(static_cast<size_t>(steps) * 4))
+        return fail(CM_ENOMEM, "training run buffers");
+    // every epoch's order, uploaded once (the host copy lives until the end)
+    std::vector<int32_t> order(static_cast<size_t>(n_pairs) * cfg->epochs);
+    for (int e = 0; e < cfg->epochs; ++e)
+        epoch_order(n_pairs, cfg->shuffle != 0, cfg->seed, e, order.data() + static_cast<size_t>(e) * n_pairs);
+    hipStream_t st = s->st;
+    r = chk(hipMemcpyAsync(s->perm.ptr, order.data(), order.size() * 4, hipMemcpyHostToDevice, st), "orders");
+    if (r != CM_OK) return r;
+    int32_t* bp = static_cast<int32_t*>(s->bpairs.ptr);
+    uint8_t* by = static_cast<uint8_t*>(s->blabels.ptr);
+    float* log = static_cast<float*>(s->losslog.ptr);
+    int64_t k = 0;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        const int32_t* perm = static_cast<const int32_t*>(s->perm.ptr) + static_cast<size_t>(e) * n_pairs;
+        for (int64_t b = 0; b < per_epoch; ++b, ++k) {
+            const int64_t first = b * cfg->batch;
+            const int n = static_cast<int>(std::min<int64_t>(cfg->batch, n_pairs - first));
+            const int mb = static_cast<int>(round_up(n, 64));
+            r = chk(cms::launch_gather_batch(perm + first, pairs, labels, n, mb, bp, by, st), "batch gather");
+            if (r == CM_OK) r = forward_backward(s, feat, bp, by, n, nullptr);
+            if (r == CM_OK) r = chk(cms::launch_mean(static_cast<const float*>(s->loss.ptr), n, log + k, st), "loss");
+            if (r == CM_OK) r = adam_step(s, cfg->lr);
+            if (r != CM_OK) return r;
+        }
+    }
+    if (loss_log) {
+        r = chk(hipMemcpyAsync(loss_log, log, static_cast<size_t>(steps) * 4, hipMemcpyDeviceToHost, st), "loss log");
+        if (r != CM_OK) return r;
+    }
+    return chk(hipStreamSynchronize(st), "training run");
+    CM_CATCH
 }
 
 cm_status cm_screen_save(const cm_screen* s, const char* path) {
+    CM_TRY
     if (!s || !path) return fail(CM_EINVAL, "bad argument");
     std::vector<float> buf(3 * cms::kParams);
     cm_status r = chk(hipMemcpy(buf.data(), s->master.ptr, cms::kParams * 4, hipMemcpyDeviceToHost), "save");
@@ -295,9 +400,11 @@ cm_status cm_screen_save(const cm_screen* s, const char* path) {
               fwrite(buf.data(), 4, buf.size(), f) == buf.size();
     ok = (fclose(f) == 0) && ok;
     return ok ? CM_OK : fail(CM_EINVAL, "write failed: %s", path);
+    CM_CATCH
 }
 
 cm_status cm_screen_load(cm_context* ctx, const char* path, cm_screen** out) {
+    CM_TRY
     if (!ctx || !path || !out) return fail(CM_EINVAL, "bad argument");
     *out = nullptr;
     FILE* f = fopen(path, "rb");
@@ -322,6 +429,7 @@ cm_status cm_screen_load(cm_context* ctx, const char* path, cm_screen** out) {
     s->step = static_cast<int>(hdr[1]);
     *out = s;
     return CM_OK;
+    CM_CATCH
 }
 
 }  // extern "C"

@@ -234,6 +234,7 @@ extern "C" cm_status cm_sw_traceback_batch(cm_context* ctx, const uint8_t* seqs,
                                            const int32_t* scores, const int32_t* end_a, const int32_t* end_b,
                                            const int32_t* start_a, const int32_t* start_b,
                                            const int64_t* op_offsets, uint8_t* ops, int32_t* n_ops, void* stream) {
+    CM_TRY
     if (!ctx) return fail(CM_EINVAL, "ctx is NULL");
     if (n_pairs < 0 || n_seqs < 0) return fail(CM_EINVAL, "negative size");
     if (n_pairs == 0) return CM_OK;
@@ -323,4 +324,5 @@ extern "C" cm_status cm_sw_traceback_batch(cm_context* ctx, const uint8_t* seqs,
     ctx->tb_dir.release();
     ctx->tb_rows.release();
     return CM_OK;
+    CM_CATCH
 }

@@ -21,6 +21,7 @@ using cmrt::hip_fail;
 extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
                                  const int32_t* pairs, int64_t n_pairs, const int32_t* matrix, int32_t gap_open,
                                  int32_t gap_extend, int pass, double* table, int32_t* n_rows) {
+    CM_TRY
     if (!ctx || !pairs || n_pairs <= 0 || (pass != CM_PASS_SCORE && pass != CM_PASS_SCORE_END))
         return fail(CM_EINVAL, "bad argument");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(CM_EDEVICE, "hipSetDevice");
@@ -98,4 +99,5 @@ extern "C" cm_status cm_autotune(cm_context* ctx, const uint8_t* seqs, const int
     ctx->plan[pass] = st == CM_OK ? best : saved;
     if (n_rows) *n_rows = rows < kMaxRows ? rows : kMaxRows;
     return st;
+    CM_CATCH
 }

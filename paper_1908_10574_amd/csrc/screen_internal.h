@@ -64,5 +64,10 @@ hipError_t launch_rowsum(const uint16_t* x, int rows, int mb, float* out, hipStr
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, int step, hipStream_t s);
 hipError_t launch_pack(const float* master, uint16_t* w1, uint16_t* w2, uint16_t* w2t, uint16_t* w3, hipStream_t s);
+// rows m < n: pair and label perm[m]; rows n..mb-1: padding (label 0)
+hipError_t launch_gather_batch(const int32_t* perm, const int32_t* pairs, const uint8_t* labels, int n, int mb,
+                               int32_t* bp, uint8_t* by, hipStream_t s);
+// out[0] = mean of loss[0..n), fixed summation order
+hipError_t launch_mean(const float* loss, int n, float* out, hipStream_t s);
 
 }  // namespace cms

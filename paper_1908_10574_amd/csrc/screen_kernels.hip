@@ -511,6 +511,40 @@ __global__ void k_pack(const float* master, uint16_t* w1, uint16_t* w2, uint16_t
 }
 
 // ---------------------------------------------------------------------------
+// training-run helpers: the batch's pair rows and labels gathered through the
+// epoch's permutation, and the batch's mean loss written to the loss log
+// ---------------------------------------------------------------------------
+__global__ void k_gather_batch(const int32_t* perm, const int32_t* pairs, const uint8_t* labels, int n, int mb,
+                               int32_t* bp, uint8_t* by) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= mb) return;
+    if (m < n) {
+        const int64_t src = perm[m];
+        bp[2 * m] = pairs[2 * src];
+        bp[2 * m + 1] = pairs[2 * src + 1];
+        by[m] = labels[src];
+    } else {   // padding rows of the last tile: a valid pair, masked out by k_bce
+        bp[2 * m] = bp[0];
+        bp[2 * m + 1] = bp[1];
+        by[m] = 0;
+    }
+}
+
+// fixed-order mean of loss[0..n): per-thread strided partial sums, then a tree
+__global__ __launch_bounds__(256) void k_mean(const float* loss, int n, float* out) {
+    __shared__ float part[256];
+    float t = 0.f;
+    for (int m = threadIdx.x; m < n; m += 256) t += loss[m];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = part[0] / static_cast<float>(n);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_kmer(const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs, uint16_t* feat, uint32_t* err,
@@ -555,6 +589,15 @@ hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, 
     const float c2 = 1.f - powf(b2, static_cast<float>(step));
     hipLaunchKernelGGL(k_adam, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, w, g, m, v, n, lr, b1,
                        b2, eps, c1, c2);
+    return hipGetLastError();
+}
+hipError_t launch_gather_batch(const int32_t* perm, const int32_t* pairs, const uint8_t* labels, int n, int mb,
+                               int32_t* bp, uint8_t* by, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_batch, dim3((mb + 255) / 256), dim3(256), 0, s, perm, pairs, labels, n, mb, bp, by);
+    return hipGetLastError();
+}
+hipError_t launch_mean(const float* loss, int n, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_mean, dim3(1), dim3(256), 0, s, loss, n, out);
     return hipGetLastError();
 }
 hipError_t launch_pack(const float* master, uint16_t* w1, uint16_t* w2, uint16_t* w2t, uint16_t* w3, hipStream_t s) {

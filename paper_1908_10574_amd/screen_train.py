@@ -37,22 +37,17 @@ def screen_logits(scr: Screen, feat, pairs: np.ndarray, chunk: int = 1 << 21) ->
 
 def train(scr: Screen, feat, pairs: np.ndarray, labels: np.ndarray, epochs: int = 5, batch: int = 4096,
           lr: float = 1e-3, seed: int = 0, log=None) -> list:
-    """Mini-batch Adam over shuffled pairs; returns the mean loss of each epoch."""
+    """Mini-batch Adam over shuffled pairs, the whole run in one library call
+    (cm_screen_train); returns the mean loss of each epoch."""
     import torch
-    rng = np.random.default_rng(seed)
     tp = torch.from_numpy(np.ascontiguousarray(pairs, dtype=np.int32)).cuda()
     ty = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.uint8)).cuda()
-    hist = []
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(len(pairs))).cuda()
-        sp, sy = tp[perm].contiguous(), ty[perm].contiguous()
-        tot, nb = 0.0, 0
-        for k in range(0, len(pairs) - batch + 1, batch):
-            tot += scr.train_step(feat, sp[k:k + batch], sy[k:k + batch], lr)
-            nb += 1
-        hist.append(tot / max(nb, 1))
-        if log:
-            log(f"screen epoch {ep}: loss {hist[-1]:.4f}")
+    steps = scr.train(feat, tp, ty, epochs=epochs, batch=batch, lr=lr, shuffle=True, seed=seed, drop_last=True)
+    per = len(steps) // epochs
+    hist = [float(steps[e * per:(e + 1) * per].mean()) for e in range(epochs)]
+    if log:
+        for ep, v in enumerate(hist):
+            log(f"screen epoch {ep}: loss {v:.4f}")
     return hist
 
 

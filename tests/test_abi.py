@@ -22,9 +22,9 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("cm_sw_score_batch", "cm_sw_span_batch", "cm_sw_traceback_batch", "cm_clustermerge_run",
                      "cm_clustermerge_extend", "cm_allvsall_count", "cm_kmer_features", "cm_screen_infer",
-                     "cm_screen_train_step", "cm_context_create"):
+                     "cm_screen_train_step", "cm_screen_train", "cm_screen_train_steps", "cm_context_create"):
         assert required in names
-    assert len(names) >= 27
+    assert len(names) >= 29
 
 
 def test_header_is_plain_c(tmp_path):
@@ -56,3 +56,18 @@ def test_status_strings_without_device():
     assert lib.cm_status_str(-2) == b"input data out of range"
     lib.cm_screen_num_params.restype = ctypes.c_int64
     assert lib.cm_screen_num_params() == 1312257
+
+
+def test_train_steps_without_device():
+    """The step count of a training run is host arithmetic (no device)."""
+    lib = ctypes.CDLL(LIB)
+
+    class Cfg(ctypes.Structure):
+        _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                    ("shuffle", ctypes.c_int32), ("seed", ctypes.c_uint64), ("drop_last", ctypes.c_int32)]
+
+    lib.cm_screen_train_steps.restype = ctypes.c_int64
+    lib.cm_screen_train_steps.argtypes = [ctypes.c_int64, ctypes.POINTER(Cfg)]
+    assert lib.cm_screen_train_steps(10000, ctypes.byref(Cfg(3, 4096, 1e-3, 1, 0, 1))) == 6
+    assert lib.cm_screen_train_steps(10000, ctypes.byref(Cfg(3, 4096, 1e-3, 1, 0, 0))) == 9
+    assert lib.cm_screen_train_steps(10000, ctypes.byref(Cfg(1, 0, 1e-3, 1, 0, 0))) == -1

@@ -353,3 +353,23 @@ def test_end_records_beyond_prefix(cm, graphs):
     assert g["stats"]["end_pairs"] == n - 1
     assert g["stats"]["n_similar_pairs"] == n * (n - 1) // 2
     ctx.close()
+
+
+def test_allocation_failure_returns_enomem_and_context_recovers(cm, monkeypatch):
+    """An allocation that fails inside cm_clustermerge_run (a host vector of the
+    final stage while a batch is on the device, or the growth of device
+    scratch) returns CM_ENOMEM instead of aborting; the same context then runs
+    the same input to the exact result."""
+    ds = cmgen.clustermerge_families(n_seqs=300, n_families=30, seed=231, median=120, hi=400)
+    res, off = dev_store(ds)
+    clusters, pairs, st = ocm.clustermerge(ds.residues, ds.offsets, ds.matrix)
+    ctx = cm.Context(0)
+    for site in ("device", "host"):   # device first: a fresh context still has scratch to grow
+        monkeypatch.setenv("CM_TEST_FAIL_ALLOC", site)
+        with pytest.raises(cm.CMError) as e:
+            cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+        assert e.value.status == cm.CM_ENOMEM, (site, str(e.value))
+        monkeypatch.delenv("CM_TEST_FAIL_ALLOC")
+        g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+        assert_same(g, clusters, pairs, st)
+    ctx.close()

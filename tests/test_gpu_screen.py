@@ -117,6 +117,51 @@ def test_training_reduces_loss_and_adam_matches(cm, data):
     assert losses[-1] < 0.5 * first, (first, losses[-1])
 
 
+def test_training_run_equals_steps(cm, data):
+    """cm_screen_train over the given order equals cm_screen_train_step over the
+    same batches bit for bit (weights), with a ragged last batch; its loss log
+    holds each step's mean loss before the update."""
+    ds, res, off, feat = data
+    w = S.init_params(21)
+    pairs, y = _batch(ds, 1000, 22)
+    tp, ty = torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda()
+    a = cm.Screen(0)
+    a.set_weights(w)
+    log = a.train(feat, tp, ty, epochs=2, batch=384, lr=2e-3, shuffle=False, drop_last=False)
+    assert len(log) == 2 * 3
+    b = cm.Screen(0)
+    b.set_weights(w)
+    want = []
+    for _ in range(2):
+        for k in range(0, 1000, 384):
+            want.append(b.train_step(feat, tp[k:k + 384], ty[k:k + 384], lr=2e-3))
+    wa, ba = a.get_weights()
+    wb, bb = b.get_weights()
+    assert np.array_equal(wa, wb) and np.array_equal(ba, bb)
+    assert np.allclose(log, want, rtol=1e-5, atol=1e-7), (log, want)
+    # the first step's loss is the reference loss of the initial weights
+    z, _ = S.forward(w, S.pair_input(feat_bits(feat), pairs[:384]))
+    assert abs(log[0] - S.bce(z, y[:384])) < 1e-3
+
+
+def test_training_run_shuffles_and_learns(cm, data):
+    ds, res, off, feat = data
+    pairs, y = _batch(ds, 4000, 23)
+    tp, ty = torch.from_numpy(pairs).cuda(), torch.from_numpy(y).cuda()
+    runs = []
+    for seed in (5, 5, 6):
+        scr = cm.Screen(3)
+        log = scr.train(feat, tp, ty, epochs=4, batch=256, lr=1e-3, seed=seed)
+        runs.append((log, scr.get_weights()[0]))
+    assert len(runs[0][0]) == 4 * (4000 // 256)
+    assert np.array_equal(runs[0][1], runs[1][1])          # same seed, same run
+    assert not np.array_equal(runs[0][1], runs[2][1])      # another order
+    log = runs[0][0]
+    assert log[-15:].mean() < 0.7 * log[:15].mean()
+    with pytest.raises(cm.CMError):
+        cm.Screen(0).train(feat, tp, ty, epochs=1, batch=1 << 21, drop_last=False)
+
+
 def test_save_load_roundtrip(cm, data, tmp_path):
     ds, res, off, feat = data
     scr = cm.Screen(7)
