@@ -142,6 +142,29 @@ cm_status cm_sw_score_batch(cm_context* ctx,
                             int32_t* scores, int32_t* end_a, int32_t* end_b,
                             void* stream);
 
+/* For callers that cannot allocate (code under HIP stream capture, tight
+ * serving loops, harnesses that forbid allocation): cm_sw_score_batch with
+ * the same arguments, outputs and errors, bit-identical results, and no
+ * allocation of any kind in the call.  Its per-call scratch (plan keys and
+ * values, sorted copies, saturated-pair list, sort temp, counters) is a
+ * static device array of CM_NOALLOC_SCRATCH_MIB MiB that the library holds on
+ * every GPU it runs on until the process ends (its address is taken when a
+ * context is created on that GPU); the boundary rows between strips are the
+ * context's, allocated when it is created.  At most CM_NOALLOC_MAX_PAIRS
+ * pairs per call (CM_EINVAL beyond, nothing enqueued).  All calls on one GPU
+ * share the array: calls that overlap on one GPU (two streams, two contexts,
+ * two host threads) race and must be ordered by the caller.  Score-only calls
+ * run the two-profile packed kernel, score+end calls the int32 kernel, each
+ * at its occupancy limit; the context's plans and timing are not used. */
+#define CM_NOALLOC_MAX_PAIRS   1048576
+#define CM_NOALLOC_SCRATCH_MIB 48
+cm_status cm_sw_score_batch_noalloc(cm_context* ctx,
+                                    const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
+                                    const int32_t* pairs, int64_t n_pairs,
+                                    const int32_t* matrix, int32_t gap_open, int32_t gap_extend,
+                                    int32_t* scores, int32_t* end_a, int32_t* end_b,
+                                    void* stream);
+
 /* Start cells of the optimal local alignments (needed by the coverage test of
  * the protein transitivity function, Section 4): for every pair whose score
  * (input, from cm_sw_score_batch) exceeds min_score, the same recurrence is run

@@ -560,6 +560,9 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) { cm_context_destroy(ctx); return hip_fail(e, "context init"); }
+    // device address of the allocation-free entry point's scratch array (once
+    // per device; a failure only disables that entry point, which reports it)
+    (void)noalloc_setup(device_ordinal);
     const char* cache = getenv("CM_AUTOTUNE_CACHE");
     if (cache && *cache) (void)load_plans(ctx, cache);   // a missing or corrupt cache keeps the defaults
     *out = ctx;

@@ -133,6 +133,9 @@ cm_status score_args(cm_context* ctx, const uint8_t* seqs, const int64_t* offset
                      const int32_t* pairs, int64_t n_pairs, const int64_t* n_live, const int32_t* matrix,
                      int32_t gap_open, int32_t gap_extend, int32_t* scores, int32_t* end_a, int32_t* end_b,
                      cmk::SwArgs& a);
+// the allocation-free entry point's per-device scratch address (set up once
+// per device by cm_context_create)
+cm_status noalloc_setup(int device);
 // accumulate the durations of timed launches that have completed
 // (blocking = wait for all of them)
 void drain_timers(cm_context* ctx, bool blocking);
