@@ -186,7 +186,9 @@ def test_trained_screen_quality_and_screened_recall(cm):
     test = cmgen.clustermerge_families(n_seqs=2000, n_families=200, seed=222)
     res, off = torch.from_numpy(test.residues).cuda(), torch.from_numpy(test.offsets).cuda()
     plain = cm.clustermerge_run(res, off, test.matrix)
-    scr_run = cm.clustermerge_run(res, off, test.matrix, screen=scr, screen_tau=tau)
+    # the size guard the benchmark uses: representative pairs of clusters whose
+    # member counts multiply to 64 or more bypass the screen
+    scr_run = cm.clustermerge_run(res, off, test.matrix, screen=scr, screen_tau=tau, screen_min_product=64)
     ps, ss = plain["stats"], scr_run["stats"]
     print({k: (ps[k], ss[k]) for k in ("n_similar_pairs", "aligned_pairs", "aligned_cells", "screened_out",
                                       "t_total_s")})
