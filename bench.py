@@ -56,12 +56,46 @@ def measured_traffic():
     return float(kv["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(ds, n_sample, T=120, mT=166, mU=15):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_POOL = {}
+
+
+def _pool_init(res, off, mat):
+    _POOL["res"], _POOL["off"], _POOL["mat"] = res, off, mat
+
+
+def _pool_score(pairs):
+    from oracle import sw_batch
+    return sw_batch(_POOL["res"], _POOL["off"], pairs, _POOL["mat"], with_end=False)
+
+
+def cpu_baseline(ds, n_sample, tp_pairs=48000, workers=0, T=120, mT=166, mU=15):
     """The CPU oracle (scalar C Smith-Waterman + sequential Algorithms 1-2 in
-    Python) on the first n_sample proteins of the same store."""
+    Python), run before anything touches the GPU:
+      * value: the ClusterMerge oracle on the first n_sample proteins of the
+        same store, one thread;
+      * single_core_allvsall_100: the oracle's Smith-Waterman on the 4,950
+        pairs of the 100-protein all-against-all set, one thread;
+      * all_cores_throughput_sample: the first tp_pairs pairs of the
+        1,000,000-pair throughput batch scored by independent oracle
+        processes (one per host core, up to 16), contiguous chunks."""
+    import multiprocessing as mp
     import numpy as np
-    import cmgen  # noqa: F401
+    import cmgen
     from oracle import clustermerge as ocm
+    from oracle import sw_batch
+    nproc = os.cpu_count() or 1
+    workers = workers or min(16, nproc)
     off = ds.offsets[: n_sample + 1]
     res = ds.residues[: int(off[-1])]
     judge = ocm.ProteinJudge(res, off, ds.matrix, T, mT, mU)
@@ -71,9 +105,30 @@ def cpu_baseline(ds, n_sample, T=120, mT=166, mU=15):
     dt = time.perf_counter() - t0
     L = np.diff(off).astype(np.float64)
     cells = sum(L[x] * L[y] for x, y in judge._score)
-    return dict(value=cells / dt / 1e9, unit="GCUPS", cores=1, kind="oracle",
-                sample=f"ClusterMerge oracle on the first {n_sample} proteins of the same store "
-                       f"({len(judge._score)} alignments, {cells:.3e} cells, {dt:.1f} s, single thread)")
+    out = dict(value=cells / dt / 1e9, unit="GCUPS", cores=1, kind="oracle",
+               sample=f"ClusterMerge oracle on the first {n_sample} proteins of the same store "
+                      f"({len(judge._score)} alignments, {cells:.3e} cells, {dt:.1f} s, single thread)",
+               nproc=nproc, cpu_model=cpu_model(), compiler="gcc -O2 -std=c99 (scalar C Smith-Waterman)")
+    small = cmgen.allvsall_small()
+    Ls = small.lengths().astype(np.float64)
+    c1 = float((Ls[small.pairs[:, 0]] * Ls[small.pairs[:, 1]]).sum())
+    t0 = time.perf_counter()
+    sw_batch(small.residues, small.offsets, small.pairs, small.matrix, with_end=False)
+    d1 = time.perf_counter() - t0
+    out["single_core_allvsall_100"] = dict(pairs=int(len(small.pairs)), cells=c1, seconds=d1, gcups=c1 / d1 / 1e9)
+    tp = cmgen.throughput_pool()
+    pr = tp.pairs[:tp_pairs]
+    Lt = tp.lengths().astype(np.float64)
+    c2 = float((Lt[pr[:, 0]] * Lt[pr[:, 1]]).sum())
+    chunks = np.array_split(pr, workers * 4)
+    with mp.get_context("fork").Pool(workers, initializer=_pool_init,
+                                      initargs=(tp.residues, tp.offsets, tp.matrix)) as pool:
+        t0 = time.perf_counter()
+        pool.map(_pool_score, chunks, chunksize=1)
+        d2 = time.perf_counter() - t0
+    out["all_cores_throughput_sample"] = dict(pairs=int(len(pr)), cells=c2, processes=workers, seconds=d2,
+                                              gcups=c2 / d2 / 1e9)
+    return out
 
 
 def sampled_recall(cm, res, off, M, clusters, n, k_sample, seed=7, T=120, chunk=1 << 23):
@@ -318,6 +373,11 @@ def main():
     ap.add_argument("--screen-pairs", type=int, default=2000000)
     ap.add_argument("--screen-epochs", type=int, default=5)
     ap.add_argument("--screen-keep", type=float, default=0.999)
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="steps timed again with graph-captured waves (0: skip)")
+    ap.add_argument("--autotune-pairs", type=int, default=1000000,
+                    help="pairs of the throughput batch the autotuner times every plan on (0: skip); a small "
+                         "sample favours plans with short tails over plans with high throughput")
     ap.add_argument("--screen-min-product", type=int, default=64,
                     help="representative pairs of clusters whose sizes multiply to at least this bypass the screen")
     args = ap.parse_args()
@@ -327,8 +387,21 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import cmgen
+
+    # the CPU oracle runs first, while no GPU state exists (its process pool
+    # forks this process)
+    cpu = None
+    if not args.no_cpu_baseline and not args.sweep:
+        base_ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families) \
+            if args.workload != "clustermerge-300k" else cmgen.clustermerge_large()
+        cpu = cpu_baseline(base_ds, args.cpu_sample)
+        del base_ds
+        log(f"cpu baseline: {cpu['value']:.3f} GCUPS (one thread), "
+            f"{cpu['all_cores_throughput_sample']['gcups']:.2f} GCUPS on "
+            f"{cpu['all_cores_throughput_sample']['processes']} processes ({cpu['cpu_model']}, nproc {cpu['nproc']})")
+
+    import torch
     import paper_1908_10574_amd as cm
 
     dev = torch.device("cuda:0")
@@ -376,7 +449,11 @@ def main():
     step_s = wall / args.steps
     s = stats[-1]
     cells = s["aligned_cells"]
-    value = cells / step_s / 1e9
+    # headline: the cells the method needs (Algorithm 1's comparisons, its
+    # exchanges' tests, the final stage's pairs not already scored) per second
+    # of the whole step; executed cells (with speculation) are reported beside
+    req_cells = s["required_cells"]
+    value = req_cells / step_s / 1e9
     k_launch = sum(x["sw_launches"] for x in stats)
     k_sec = sum(x["sw_kernel_s"] for x in stats)
     k_cells = sum(x["aligned_cells"] for x in stats)
@@ -395,6 +472,16 @@ def main():
                     cell_rate_gcups=k_cells / k_sec / 1e9,
                     int32_formulation_frac=OPS_PER_CELL * k_cells / k_sec / PEAK_INT32_OPS)
 
+    probes = {}
+    for name, kind in (("i32_add", cm.CM_PROBE_I32_ADD), ("i32_max3", cm.CM_PROBE_I32_MAX3),
+                       ("pk16_add", cm.CM_PROBE_PK16_ADD), ("pk16_maximum3", cm.CM_PROBE_PK16_MAX3)):
+        ops, clk = cm.probe_valu(kind)
+        probes[name] = ops / 1e12
+        probes[name + "_clock_ghz"] = clk / 1e9
+    roofline["measured_peak"] = dict(unit="TOP/s", **probes)
+    mp_peak = probes["pk16_maximum3"] if packed else probes["i32_max3"]
+    roofline["frac_of_measured_peak"] = achieved / (mp_peak * 1e12)
+    log(f"measured VALU peaks (TOP/s): {probes}")
     out = dict(metric=METRIC, value=value, unit="GCUPS", n_gpus=1, steps=args.steps, warmup=args.warmup,
                ms_per_step=1e3 * step_s, higher_is_better=True, scaling="weak", vs_baseline=None,
                # the score pass computes in packed 16-bit integers (int32 for end and start cells and
@@ -406,13 +493,30 @@ def main():
                            n_seqs=ds.n, residues=int(len(ds.residues))),
                roofline=roofline)
     out["clustermerge"] = dict(
-        time_s=step_s, aligned_cells=cells, aligned_pairs=s["aligned_pairs"], rep_comparisons=s["rep_comparisons"],
+        time_s=step_s, required_cells=req_cells, required_gcups=req_cells / step_s / 1e9,
+        executed_gcups=cells / step_s / 1e9, speculative_cell_frac=1.0 - req_cells / max(cells, 1.0),
+        aligned_cells=cells, aligned_pairs=s["aligned_pairs"], rep_comparisons=s["rep_comparisons"],
         exchange_alignments=s["exchange_alignments"], full_merges=s["full_merges"], exchanges=s["exchanges"],
         n_clusters=s["n_clusters"], n_similar_pairs=s["n_similar_pairs"], waves=s["waves"],
         gpu_s=s["t_gpu_s"], host_s=s["t_host_s"], merge_s=s["t_merge_s"], final_s=s["t_final_s"],
         score_kernel_s=s["sw_kernel_s"], end_kernel_s=s["end_kernel_s"], end_pairs=s["end_pairs"],
         speculative_pairs=s["speculative_pairs"], final_candidates=s["final_candidates"],
         cache_hits=s["cache_hits"], rounds=s["rounds"])
+
+    if not large and args.graph_steps > 0:
+        # the same step with every wave replayed as a captured graph
+        ctx.set_graphs(True)
+        cm.clustermerge_run(res, off, M, **cm_kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            gg = cm.clustermerge_run(res, off, M, **cm_kw)
+        torch.cuda.synchronize()
+        g_step = (time.perf_counter() - t0) / args.graph_steps
+        ctx.set_graphs(False)
+        out["clustermerge"]["graphs"] = dict(time_s=g_step, steps=args.graph_steps, vs_eager=step_s / g_step,
+                                             same_pairs=gg["stats"]["pair_set_hash"] == s["pair_set_hash"])
+        log(f"graph-captured waves: {g_step:.3f} s/step against {step_s:.3f} s eager")
 
     plain_clusters = g["clusters"]
     if not args.no_recall and large:
@@ -478,6 +582,21 @@ def main():
         p2 = torch.from_numpy(tp.pairs).to(dev)
         L = tp.lengths().astype(np.float64)
         tcells = float((L[tp.pairs[:, 0]] * L[tp.pairs[:, 1]]).sum())
+        if args.autotune_pairs > 0:
+            # the autotuner picks the score pass's plan on a sample of the batch
+            # (every candidate must agree on every output); the leg runs with it
+            plan0 = ctx.get_plan(0)
+            t = time.perf_counter()
+            table = ctx.autotune(r2, o2, p2[:args.autotune_pairs], M, 0)
+            tune_s = time.perf_counter() - t
+            chosen = ctx.get_plan(0)
+            out["autotune"] = dict(sample_pairs=args.autotune_pairs, seconds=tune_s,
+                                   table=[dict(kernel=k, rmax=r, blocks_per_cu=b, ms=ms) for k, r, b, ms in table],
+                                   chosen=dict(kernel=chosen[0], rmax=chosen[1], blocks_per_cu=chosen[2]),
+                                   default=dict(kernel=plan0[0], rmax=plan0[1], blocks_per_cu=plan0[2]))
+            log(f"autotune on {args.autotune_pairs} pairs: {len(table)} plans in {tune_s:.2f} s, chosen {chosen[:3]}")
+        tp_packed = ctx.get_plan(0)[0] >= 1
+        tp_opc, tp_peak = (PK_OPS_PER_CELL, PEAK_PK16_OPS) if tp_packed else (OPS_PER_CELL, PEAK_INT32_OPS)
         cm.sw_score_batch(r2, o2, p2, M)
         ctx.sync()
         ctx.set_timing(True)
@@ -496,14 +615,16 @@ def main():
         out["sw_throughput"] = dict(
             workload=f"throughput-{args.throughput_pairs}: random pairs of a 200,000-protein pool, 80% "
                      "lognormal(300, 0.6) / 20% U[1000,5000]", cells=tcells, batch_s=bt, gcups=tcells / bt / 1e9,
-            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=opc * tcells / ks / peak,
+            plan=list(ctx.get_plan(0)[:3]),
+            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=tp_opc * tcells / ks / tp_peak,
             int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
         log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
+        if args.autotune_pairs > 0:
+            ctx.set_plan(0, *plan0[:3])     # the ClusterMerge legs keep the default plan
         del r2, o2, p2
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ds, args.cpu_sample)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} GCUPS")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

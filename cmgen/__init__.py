@@ -279,6 +279,34 @@ def clustermerge_large(seed: int = 505) -> Dataset:
     return clustermerge_families(300000, 25000, seed, hi=5000)
 
 
+def max_length_set(L: int = 65535, seed: int = 113) -> Dataset:
+    """Proteins at the longest accepted length L: a query (a mutated copy of a
+    random ancestor, padded with random residues to L) against eight subjects
+    of 0.9 L to L residues sharing it (one item of eight pairs with one query):
+    an identical copy, mutated relatives and unrelated proteins; plus a 4,000-
+    residue stretch of the query, short proteins and one residue.  Pairs: the
+    eight query-subject pairs, some reversed, and the short ones both ways."""
+    rng = np.random.default_rng(seed)
+    anc = rng.integers(0, N_RES, size=L).astype(np.uint8)
+    q = np.concatenate([mutate(rng, anc), rng.integers(0, N_RES, size=L).astype(np.uint8)])[:L]
+    seqs = [q]
+    for k, n in enumerate((L, L - 1, int(0.98 * L), int(0.96 * L), int(0.94 * L), int(0.93 * L), int(0.92 * L),
+                           int(0.9 * L))):
+        if k == 0:
+            t = q.copy()
+        elif k % 2 == 0:
+            t = mutate(rng, anc)
+        else:
+            t = rng.integers(0, N_RES, size=n).astype(np.uint8)
+        seqs.append(np.concatenate([t, rng.integers(0, N_RES, size=L).astype(np.uint8)])[:n])
+    seqs.append(q[20000:24000].copy())                                  # 9: a stretch of the query
+    seqs += [rng.integers(0, N_RES, size=n).astype(np.uint8) for n in (3000, 300, 1)]   # 10, 11, 12
+    ds = _pack(seqs, np.full(len(seqs), -1), make_matrix(), dict(seed=seed, workload=f"max-length-{L}"))
+    ds.pairs = np.array([(0, k) for k in range(1, 9)] + [(3, 0), (4, 0), (9, 0), (0, 9), (0, 10), (10, 0),
+                                                         (11, 0), (0, 12), (12, 3)], np.int32)
+    return ds
+
+
 def random_pairs(rng, n_seqs: int, n_pairs: int) -> np.ndarray:
     a = rng.integers(0, n_seqs, size=n_pairs)
     b = rng.integers(0, n_seqs, size=n_pairs)

@@ -66,7 +66,7 @@ typedef int32_t cm_status;
 #define CM_EDEVICE      -4   /* HIP runtime error (see cm_last_error) */
 #define CM_EUNSUPPORTED -5   /* e.g. |matrix entry| > 127 */
 
-#define CM_MAX_LEN 16384     /* longest sequence the alignment kernels accept */
+#define CM_MAX_LEN 65535     /* longest sequence the alignment kernels accept */
 
 const char* cm_status_str(cm_status s);
 const char* cm_last_error(void);
@@ -94,6 +94,18 @@ cm_status cm_context_set_timing(cm_context* ctx, int on);
  * memory); alignment-kernel timing is then not collected.  Off by default. */
 cm_status cm_context_set_graphs(cm_context* ctx, int on);
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
+
+/* Measured peak rate of one VALU instruction of the cell update (the
+ * denominators of the alignment kernels' roofline): every lane of 8
+ * wavefronts per SIMD runs 32 independent chains of the instruction;
+ * *ops_per_second counts 16-bit halves of packed instructions as two
+ * operations; *clock_hz (nullable) is the shader clock over the run (cycle
+ * counter against the real-time counter).  Synchronous, about 0.1 s. */
+#define CM_PROBE_I32_ADD   0   /* v_add_u32 */
+#define CM_PROBE_I32_MAX3  1   /* v_max3_i32 */
+#define CM_PROBE_PK16_ADD  2   /* v_pk_add_u16 */
+#define CM_PROBE_PK16_MAX3 3   /* v_pk_maximum3_f16 */
+cm_status cm_probe_valu(cm_context* ctx, int kind, double* ops_per_second, double* clock_hz);
 
 /* Launch plan of the alignment kernels, per pass: the kernel (packed = 2: the
  * score pass groups pairs by query and runs items of eight pairs sharing one
@@ -194,7 +206,10 @@ cm_status cm_sw_span_batch(cm_context* ctx,
  * rejected).  op_offsets (device i64 [n_pairs + 1], caller-computed) must give
  * every pair with score > 0 at least (end_a - start_a + 1) + (end_b - start_b
  * + 1) bytes.  The call waits for its work on `stream` (scratch of one byte per
- * box cell, bounded per launch).  Bad indices, cells or capacities make the
+ * box cell, bounded per launch: boxes of up to 2^28 cells, e.g. 16384 x 16384;
+ * pairs are grouped 64 to a wavefront by box shape, and a wavefront whose
+ * largest rows x columns exceed 2^28 makes the call return CM_EUNSUPPORTED
+ * before anything is launched).  Bad indices, cells or capacities make the
  * pair's n_ops -1 and are reported by cm_context_sync as CM_ERANGE. */
 cm_status cm_sw_traceback_batch(cm_context* ctx,
                                 const uint8_t* seqs, const int64_t* offsets, int32_t n_seqs,
@@ -272,6 +287,10 @@ typedef struct {
     int64_t end_pairs;              /* pairs realigned for end and start cells */
     double  t_screen_s;             /* wall time of screen inference calls */
     int64_t screened_pairs;         /* candidate pairs the screen evaluated */
+    double  required_cells;         /* sum of m*n over the comparisons Algorithm 1 makes (representative
+                                       pairs it compares, member-vs-representative tests of its
+                                       exchanges) and the final stage's pairs not already scored: the
+                                       cells the method needs, without speculative or cached work */
 } cm_stats;
 
 typedef struct cm_result cm_result;

@@ -78,7 +78,7 @@ class CMStats(ctypes.Structure):
                 ("t_merge_s", ctypes.c_double), ("t_final_s", ctypes.c_double), ("t_gpu_s", ctypes.c_double),
                 ("t_host_s", ctypes.c_double), ("sw_launches", _i64), ("sw_kernel_s", ctypes.c_double),
                 ("end_kernel_s", ctypes.c_double), ("end_pairs", _i64),
-                ("t_screen_s", ctypes.c_double), ("screened_pairs", _i64)]
+                ("t_screen_s", ctypes.c_double), ("screened_pairs", _i64), ("required_cells", ctypes.c_double)]
 
 
 _lib.cm_clustermerge_run.restype = _i32
@@ -102,10 +102,23 @@ _lib.cm_allvsall_count.restype = _i32
 _lib.cm_allvsall_count.argtypes = [_P, _P, _P, _i32, _P, _i32, _i32, _i32, ctypes.POINTER(_i64),
                                    ctypes.POINTER(ctypes.c_double)]
 
+_lib.cm_probe_valu.restype = _i32
+_lib.cm_probe_valu.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+
 CM_STAGE_REP, CM_STAGE_EXCHANGE, CM_STAGE_FINAL = 1, 2, 4
+CM_PROBE_I32_ADD, CM_PROBE_I32_MAX3, CM_PROBE_PK16_ADD, CM_PROBE_PK16_MAX3 = 0, 1, 2, 3
+
+
+def probe_valu(kind: int, ctx: "Context | None" = None):
+    """(operations per second, shader clock in Hz) of one VALU instruction at
+    full occupancy (cm_probe_valu); packed 16-bit halves count as two."""
+    ctx = ctx or context()
+    ops, clk = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.cm_probe_valu(ctx.handle, int(kind), ctypes.byref(ops), ctypes.byref(clk)))
+    return ops.value, clk.value
 
 CM_OK, CM_EINVAL, CM_ERANGE, CM_ENOMEM, CM_EDEVICE, CM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CM_MAX_LEN = 16384
+CM_MAX_LEN = 65535
 
 
 class CMError(RuntimeError):

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcm.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "cm")
 SOURCES = ["cm_api.hip", "sw_kernels.hip", "cm_driver.hip", "cm_screen.hip", "screen_kernels.hip", "cm_tune.hip",
-           "cm_traceback.hip", "cm_noalloc.hip"]
+           "cm_traceback.hip", "cm_noalloc.hip", "cm_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -12,6 +12,8 @@
 #include "cm_internal.h"
 #include "cm_runtime.h"
 
+static_assert(cmk::kMaxLen == CM_MAX_LEN, "kernel length limit and the ABI's CM_MAX_LEN differ");
+
 namespace {
 thread_local std::string g_last_error;
 }

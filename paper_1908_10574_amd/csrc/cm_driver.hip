@@ -775,6 +775,7 @@ void Driver::simulate(MergeJob& job, const uint8_t* bits) {
         for (size_t j = 0; j < n2; ++j) {
             if (merged2[j]) { ++spec_merged_col_; continue; }
             ++st_.rep_comparisons;
+            st_.required_cells += static_cast<double>(len_[cl_[cs1[i]].rep]) * len_[cl_[cs2[j]].rep];
             const uint8_t b = bits[i * n2 + j];
             if (!(b & kSim)) continue;
             if (b & kT21) {                 // cluster2 absorbs cluster1; leave the inner loop
@@ -904,9 +905,11 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
         add2.clear();
         bool missing = false;
         int64_t tests = 0;
+        double test_cells = 0;
         for (int32_t m : c2.objs) {
             if (c1.has(m)) continue;
             ++tests;
+            test_cells += static_cast<double>(len_[m]) * len_[c1.rep];
             int32_t s;
             if (!score_of(m, c1.rep, &s)) { missing = true; continue; }
             if (s >= p_.T) add1.push_back(m);
@@ -914,6 +917,7 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
         for (int32_t m : c1.objs) {
             if (c2.has(m)) continue;
             ++tests;
+            test_cells += static_cast<double>(len_[m]) * len_[c2.rep];
             int32_t s;
             if (!score_of(m, c2.rep, &s)) { missing = true; continue; }
             if (s >= p_.T) add2.push_back(m);
@@ -925,6 +929,7 @@ bool Driver::replay(MergeJob& job, std::vector<int32_t>& req) {
             return true;
         }
         st_.exchange_alignments += tests;
+        st_.required_cells += test_cells;
         ++st_.exchanges;
         for (int32_t m : add1) c1.add(m);
         for (int32_t m : add2) c2.add(m);
@@ -1157,6 +1162,8 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
                 for (size_t j = c0; j < c1; ++j) {
                     if (st.merged2[j]) { ++spec_merged_col_; continue; }
                     ++st_.rep_comparisons;
+                    st_.required_cells += static_cast<double>(len_[cl_[sets_[jobs[b].set1][i]].rep]) *
+                                          len_[cl_[sets_[jobs[b].set2][j]].rep];
                     const uint8_t bb = bits[q + (j - c0)];
                     if (!(bb & kSim)) continue;
                     if (bb & kT21) {            // cluster2 absorbs cluster1; the row leaves the loop
@@ -1465,6 +1472,7 @@ cm_status Driver::final_stage(cm_result* res) {
                 c.cs.push_back(-1);
                 c.gpu.push_back(x);
                 c.gpu.push_back(y);
+                st_.required_cells += static_cast<double>(len_[x]) * len_[y];
             }
         }
         if (static_cast<int64_t>(c.gpu.size() / 2) >= chunk || static_cast<int64_t>(c.cx.size()) >= 4 * kChunk) {

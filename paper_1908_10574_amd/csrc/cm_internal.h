@@ -7,6 +7,7 @@
 
 namespace cmk {
 
+constexpr int kMaxLen = 65535;      // longest sequence (the plans' sort keys hold a column count in 16 bits)
 constexpr int kGroup = 16;          // lanes that cooperate on one pair (one DPP row)
 constexpr int kPairsPerWave = 4;    // 64-lane wavefront = 4 groups
 constexpr int kRMax = 16;           // most query rows a lane can hold

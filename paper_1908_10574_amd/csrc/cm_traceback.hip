@@ -280,6 +280,21 @@ extern "C" cm_status cm_sw_traceback_batch(cm_context* ctx, const uint8_t* seqs,
         return cols[x] != cols[y] ? cols[x] < cols[y] : (rows_of(x) != rows_of(y) ? rows_of(x) < rows_of(y) : x < y);
     });
     const size_t n_waves = (order.size() + 63) / 64;
+    // every wavefront's predecessor bytes (its largest rows x columns, 64 lanes)
+    // must fit the per-launch bound; checked before anything is launched
+    for (size_t w = 0; w < n_waves; ++w) {
+        int32_t rmax = 0, cmax = 0;
+        for (size_t k = 64 * w; k < std::min(order.size(), 64 * w + 64); ++k) {
+            rmax = std::max(rmax, rows_of(order[k]));
+            cmax = std::max(cmax, cols[order[k]]);
+        }
+        const int64_t wd = static_cast<int64_t>(rmax) * cmax * 64;
+        if (wd > cmtb::kScratchCells)
+            return fail(CM_EUNSUPPORTED,
+                        "traceback: boxes of up to %d x %d cells in one wavefront need %lld bytes of predecessor "
+                        "scratch, above the %lld-byte bound (boxes of up to 2^28 cells, e.g. 16384 x 16384)", rmax,
+                        cmax, static_cast<long long>(wd), static_cast<long long>(cmtb::kScratchCells));
+    }
     std::vector<cmtb::Wave> waves;
     std::vector<int32_t> lane_pair;
     size_t w0 = 0;

@@ -136,7 +136,7 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
     } else {
         const int64_t lx = a.offsets[x + 1] - a.offsets[x];
         const int64_t ly = a.offsets[y + 1] - a.offsets[y];
-        if (lx > 16384 || ly > 16384 || lx < 0 || ly < 0) {
+        if (lx > kMaxLen || ly > kMaxLen || lx < 0 || ly < 0) {
             atomicOr(a.err, kErrLength);
         } else if (P == Pass::Span) {
             const int s = a.scores[p];
@@ -1012,7 +1012,7 @@ __global__ void k_plan_q(SwArgs a, uint64_t* keys, int32_t* vals) {
     } else {
         const int64_t lx = a.offsets[x + 1] - a.offsets[x];
         const int64_t ly = a.offsets[y + 1] - a.offsets[y];
-        if (lx > 16384 || ly > 16384 || lx < 0 || ly < 0) {
+        if (lx > kMaxLen || ly > kMaxLen || lx < 0 || ly < 0) {
             atomicOr(a.err, kErrLength);
         } else if (lx == 0 || ly == 0) {
             a.scores[p] = 0;

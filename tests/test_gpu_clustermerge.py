@@ -373,3 +373,36 @@ def test_allocation_failure_returns_enomem_and_context_recovers(cm, monkeypatch)
         g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
         assert_same(g, clusters, pairs, st)
     ctx.close()
+
+
+def test_required_cells_closed_form(cm):
+    """With T out of reach nothing is ever similar: Algorithm 2 compares every
+    pair of proteins exactly once as representatives, there is no exchange and
+    every final cluster is a singleton, so the cells the method needs are
+    sum over x < y of L_x L_y; executed cells are at least that."""
+    ds = cmgen.clustermerge_families(n_seqs=150, n_families=15, seed=241, median=150, hi=600)
+    res, off = dev_store(ds)
+    g = cm.clustermerge_run(res, off, ds.matrix, T=10 ** 6, mT=10 ** 6)
+    s = g["stats"]
+    L = ds.lengths().astype(np.float64)
+    want = (L.sum() ** 2 - (L ** 2).sum()) / 2
+    assert s["rep_comparisons"] == ds.n * (ds.n - 1) // 2 and s["exchanges"] == 0
+    assert s["required_cells"] == want
+    assert s["aligned_cells"] >= want
+    # the workload's thresholds: required cells sit between the final stage's
+    # share and the executed cells
+    g = cm.clustermerge_run(res, off, ds.matrix)
+    s = g["stats"]
+    assert 0 < s["required_cells"] <= s["aligned_cells"]
+
+
+def test_valu_probe_rates(cm):
+    """The VALU probe's rates are positive and below what 256 compute units of
+    128 lanes could issue at 3 GHz (packed 16-bit halves count twice; some
+    32-bit adds issue above 64 lanes per clock on this chip)."""
+    for kind, per_lane in ((cm.CM_PROBE_I32_ADD, 1), (cm.CM_PROBE_I32_MAX3, 1), (cm.CM_PROBE_PK16_ADD, 2),
+                           (cm.CM_PROBE_PK16_MAX3, 2)):
+        ops, clk = cm.probe_valu(kind)
+        print(kind, ops / 1e12, "TOP/s", clk / 1e9, "GHz")
+        assert 0 < ops < 256 * 128 * 3.0e9 * per_lane
+        assert 0.5e9 < clk < 3.5e9

@@ -143,30 +143,53 @@ def test_long_multistrip_pairs(cm):
 
 
 def test_maximum_length(cm):
-    """Sequences at the longest accepted length (CM_MAX_LEN = 16,384; 32 strips of
-    512 rows in the shared-query kernel, 64 of 256 in the int32 kernels): one
-    query against eight subjects of 14,400-16,384 residues (an item of the
-    shared-query kernel: an identical copy, whose score saturates 16 bits and is
-    re-run in int32, mutated relatives and unrelated proteins), plus short
-    partners.  One residue more is rejected."""
-    rng = np.random.default_rng(113)
+    """Sequences at the longest accepted length (CM_MAX_LEN = 65,535; 128 strips
+    of 512 rows in the shared-query kernel, 512 of 128 in the two-profile packed
+    kernel, 256 of 256 in the int32 kernels): one query against eight subjects
+    of 0.9-1.0 CM_MAX_LEN residues (one item of the shared-query kernel: an
+    identical copy, whose score saturates 16 bits and is re-run in int32,
+    mutated relatives and unrelated proteins), a stretch of the query, short
+    partners both ways.  Expected values: the oracle's (stored by
+    tests/golden/make_full_goldens.py maxlen) and the closed forms of a
+    self-alignment and of an embedded stretch.  Every score plan, and the
+    score+end and start-cell passes.  One residue more is rejected."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "max_length.json")))
+    ds = cmgen.max_length_set()
     L = cm.CM_MAX_LEN
-    anc = rng.integers(0, 20, size=L).astype(np.uint8)
-    q = cmgen.mutate(rng, anc)
-    q = np.concatenate([q, rng.integers(0, 20, size=L).astype(np.uint8)])[:L]
-    subs = []
-    for k, n in enumerate((L, L - 1, 16000, 15500, 15000, 14800, 14600, 14400)):
-        if k == 0:
-            s_ = q.copy()                                  # self-score ~ 1.2e5: saturates 16 bits
-        else:
-            s_ = cmgen.mutate(rng, anc) if k % 2 == 0 else rng.integers(0, 20, size=n).astype(np.uint8)
-        subs.append(np.concatenate([s_, rng.integers(0, 20, size=L).astype(np.uint8)])[:n])
-    seqs = [q] + subs + [rng.integers(0, 20, size=n).astype(np.uint8) for n in (1, 17, 300)]
-    ds = cmgen.from_list(seqs)
-    assert ds.lengths().max() == L
-    pairs = np.array([(0, k) for k in range(1, 9)] + [(9, 0), (0, 10), (11, 0), (1, 2)], np.int32)
-    sc = check_exact(cm, ds, pairs, label="max-length")
-    assert sc.max() > 32767 and (sc[1:8] > 20000).sum() >= 3   # a saturated pair re-run in int32
+    assert ds.lengths().max() == L and ds.lengths().tolist() == gold["lengths"]
+    assert ds.pairs.tolist() == gold["pairs"]
+    want = np.array([gold[k] for k in ("score", "end_a", "end_b", "start_a", "start_b")]).T
+    # closed forms: the query against its copy scores the sum of its diagonal
+    # entries over the whole length; its stretch 20000..23999 scores its own
+    # diagonal sum, ending on the stretch's last cell inside the query
+    q = ds.seq(0)
+    diag = int(ds.matrix[q, q].sum())
+    k_self = gold["pairs"].index([0, 1])
+    assert tuple(want[k_self]) == (diag, L - 1, L - 1, 0, 0)
+    t = ds.seq(9)
+    k_sub = gold["pairs"].index([9, 0])
+    assert tuple(want[k_sub]) == (int(ds.matrix[t, t].sum()), len(t) - 1, 20000 + len(t) - 1, 0, 20000)
+    res, off, pr = to_dev(ds, ds.pairs)
+    for plan in ("default", (1, 8), (0, 16)):
+        ctx = cm.Context(0)
+        if plan != "default":
+            ctx.set_plan(0, plan[0], plan[1], 1)
+            ctx.set_plan(0, plan[0], plan[1], ctx.get_plan(0)[3])     # at its occupancy limit
+        print("max length, score plan", plan, flush=True)
+        sc = cm.sw_score_batch(res, off, pr, ds.matrix, ctx=ctx)
+        ctx.sync()
+        assert np.array_equal(sc.cpu().numpy(), want[:, 0]), plan
+        ctx.close()
+    print("max length, score+end and start cells", flush=True)
+    sc, ea, eb = cm.sw_score_batch(res, off, pr, ds.matrix, return_end=True)
+    sa, sb = cm.sw_span_batch(res, off, pr, ds.matrix, sc, ea, eb, 0)
+    cm.sync()
+    got = np.stack([x.cpu().numpy() for x in (sc, ea, eb, sa, sb)], 1)
+    bad = np.flatnonzero((got != want).any(axis=1))
+    assert len(bad) == 0, (ds.pairs[bad], got[bad], want[bad])
+    assert want[:, 0].max() > 32767              # a saturated pair re-run in int32
     too_long = cmgen.from_list([np.zeros(L + 1, np.uint8), np.zeros(5, np.uint8)])
     res, off, pr = to_dev(too_long, np.array([[0, 1]], np.int32))
     cm.sw_score_batch(res, off, pr, too_long.matrix)
