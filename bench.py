@@ -348,6 +348,65 @@ def parameter_sweep(cm, ds, res, off, n_seqs, n_families):
                 incremental=incremental, traceback=traceback, parameters=rows, composition=comp)
 
 
+def throughput_leg(cm, ctx, args, out, log):
+    """The 1,000,000-pair throughput batch: optional autotuning of the score
+    pass over the batch (its table goes to out["autotune"]), then one warm
+    batch and three timed batches (HIP events around the batches and around
+    every score-kernel launch)."""
+    import numpy as np
+    import torch
+    import cmgen
+    dev = torch.device("cuda:0")
+    tp = cmgen.throughput_pool(n_pairs=args.throughput_pairs)
+    M = tp.matrix
+    r2 = torch.from_numpy(tp.residues).to(dev)
+    o2 = torch.from_numpy(tp.offsets).to(dev)
+    p2 = torch.from_numpy(tp.pairs).to(dev)
+    L = tp.lengths().astype(np.float64)
+    tcells = float((L[tp.pairs[:, 0]] * L[tp.pairs[:, 1]]).sum())
+    plan0 = ctx.get_plan(0)
+    if args.autotune_pairs > 0:
+        # the autotuner picks the score pass's plan on a sample of the batch
+        # (every candidate must agree on every output); the leg runs with it
+        t = time.perf_counter()
+        table = ctx.autotune(r2, o2, p2[:args.autotune_pairs], M, 0)
+        tune_s = time.perf_counter() - t
+        chosen = ctx.get_plan(0)
+        out["autotune"] = dict(sample_pairs=args.autotune_pairs, seconds=tune_s,
+                               table=[dict(kernel=k, rmax=r, blocks_per_cu=b, ms=ms) for k, r, b, ms in table],
+                               chosen=dict(kernel=chosen[0], rmax=chosen[1], blocks_per_cu=chosen[2]),
+                               default=dict(kernel=plan0[0], rmax=plan0[1], blocks_per_cu=plan0[2]))
+        log(f"autotune on {args.autotune_pairs} pairs: {len(table)} plans in {tune_s:.2f} s, chosen {chosen[:3]}")
+    tp_packed = ctx.get_plan(0)[0] >= 1
+    tp_opc, tp_peak = (PK_OPS_PER_CELL, PEAK_PK16_OPS) if tp_packed else (OPS_PER_CELL, PEAK_INT32_OPS)
+    cm.sw_score_batch(r2, o2, p2, M)
+    ctx.sync()
+    ctx.set_timing(True)
+    n0, s0 = ctx.kernel_time(0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 3
+    for _ in range(reps):
+        cm.sw_score_batch(r2, o2, p2, M)
+    e1.record()
+    ctx.sync()
+    n1, s1 = ctx.kernel_time(0)
+    ctx.set_timing(False)
+    bt = e0.elapsed_time(e1) / 1e3 / reps
+    ks = (s1 - s0) / max(n1 - n0, 1)
+    res = dict(
+        workload=f"throughput-{args.throughput_pairs}: random pairs of a 200,000-protein pool, 80% "
+                 "lognormal(300, 0.6) / 20% U[1000,5000]", cells=tcells, batch_s=bt, gcups=tcells / bt / 1e9,
+        plan=list(ctx.get_plan(0)[:3]),
+        kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=tp_opc * tcells / ks / tp_peak,
+        kernel_frac_8ops_packed_peak=8 * tcells / ks / PEAK_PK16_OPS,
+        int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
+    log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
+    if args.autotune_pairs > 0:
+        ctx.set_plan(0, *plan0[:3])     # the ClusterMerge legs keep the default plan
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -358,6 +417,8 @@ def main():
                          "recall from a sample of elements (use --steps 1 --warmup 0)")
     ap.add_argument("--recall-sample", type=int, default=256,
                     help="clustermerge-300k: elements whose pairs with every protein define the recall sample")
+    ap.add_argument("--sub-rate", type=float, default=0.30,
+                    help="member substitution rate of the family generator (dataset composition; 0.30 = the workload)")
     ap.add_argument("--n-seqs", type=int, default=20000)
     ap.add_argument("--n-families", type=int, default=2000)
     ap.add_argument("--throughput-pairs", type=int, default=1000000)
@@ -373,11 +434,16 @@ def main():
     ap.add_argument("--screen-pairs", type=int, default=2000000)
     ap.add_argument("--screen-epochs", type=int, default=5)
     ap.add_argument("--screen-keep", type=float, default=0.999)
+    ap.add_argument("--only-throughput", action="store_true",
+                    help="only the 1,000,000-pair throughput leg (for profiling its kernels); prints its JSON")
     ap.add_argument("--graph-steps", type=int, default=3,
                     help="steps timed again with graph-captured waves (0: skip)")
     ap.add_argument("--autotune-pairs", type=int, default=1000000,
                     help="pairs of the throughput batch the autotuner times every plan on (0: skip); a small "
                          "sample favours plans with short tails over plans with high throughput")
+    ap.add_argument("--screen-calibration-seed", type=int, default=406,
+                    help="family set whose plain-run candidates calibrate the screen threshold (0: the training "
+                         "holdout)")
     ap.add_argument("--screen-min-product", type=int, default=64,
                     help="representative pairs of clusters whose sizes multiply to at least this bypass the screen")
     args = ap.parse_args()
@@ -405,12 +471,17 @@ def main():
     import paper_1908_10574_amd as cm
 
     dev = torch.device("cuda:0")
+    if args.only_throughput:
+        extra = {}
+        res_tp = throughput_leg(cm, cm.context(), args, extra, log)
+        print(json.dumps(dict(sw_throughput=res_tp, **extra)), flush=True)
+        return
     large = args.workload == "clustermerge-300k"
     if large:
         args.n_seqs, args.n_families = 300000, 25000
         ds = cmgen.clustermerge_large()
     else:
-        ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families)
+        ds = cmgen.clustermerge_families(n_seqs=args.n_seqs, n_families=args.n_families, sub_rate=args.sub_rate)
     # the large store reports counts and the set hash only (billions of pairs)
     cm_kw = dict(max_result_pairs=0) if large else {}
     res = torch.from_numpy(ds.residues).to(dev)
@@ -488,8 +559,9 @@ def main():
                # for pairs that saturate); every output is the exact int32 result
                dtype="i16x2" if packed else "i32", data="synthetic",
                config=dict(workload=f"clustermerge-{ds.n}: {args.n_families} Zipf(1.2) families, lognormal "
-                                    f"lengths median 350 sigma 0.6 clipped 30-{5000 if large else 2000}, "
-                                    "T=120 mT=166 mU=15, gap -11/-1, matrix seed 1917, plain method",
+                                    f"lengths median 350 sigma 0.6 clipped 30-{5000 if large else 2000}"
+                                    + (f", substitution rate {args.sub_rate}" if args.sub_rate != 0.30 else "")
+                                    + ", T=120 mT=166 mU=15, gap -11/-1, matrix seed 1917, plain method",
                            n_seqs=ds.n, residues=int(len(ds.residues))),
                roofline=roofline)
     out["clustermerge"] = dict(
@@ -540,6 +612,14 @@ def main():
         scr, tau, info = screen_train.train_on_dataset(tr, epochs=args.screen_epochs, seed=1,
                                                        keep_recall=args.screen_keep, log=log)
         del tr
+        calib = None
+        if args.screen_calibration_seed > 0:
+            # tau from the candidates of a plain run on a third family set
+            cal = cmgen.clustermerge_families(n_seqs=min(args.n_seqs, 20000), n_families=min(args.n_families, 2000),
+                                              seed=args.screen_calibration_seed, sub_rate=args.sub_rate)
+            tau, calib = screen_train.calibrate_on_clustermerge(scr, cal, keep_recall=args.screen_keep)
+            del cal
+            log(f"tau from {calib['n_candidates']} ClusterMerge candidates: {tau:.3f} (holdout tau {info['tau']:.3f})")
         kw = dict(screen=scr, screen_tau=tau, screen_min_product=args.screen_min_product, **cm_kw)
         if not large:
             g = cm.clustermerge_run(res, off, M, **kw)   # warm
@@ -557,6 +637,7 @@ def main():
             n_similar_pairs=ss["n_similar_pairs"], screened_out=ss["screened_out"],
             aligned_cells=ss["aligned_cells"], aligned_pairs=ss["aligned_pairs"],
             similar_pairs_vs_plain=ss["n_similar_pairs"] / max(s["n_similar_pairs"], 1),
+            calibration=calib, tau_holdout=info["tau"],
             training=dict(workload=f"screen-train: separate 20,000-protein family set (seed 404), "
                                    f"{args.screen_pairs} pairs (half within-family), labels from the GPU "
                                    f"Smith-Waterman (score >= 120), {args.screen_epochs} epochs, batch 4096, "
@@ -576,52 +657,7 @@ def main():
         scr.close()
 
     if not args.no_throughput:
-        tp = cmgen.throughput_pool(n_pairs=args.throughput_pairs)
-        r2 = torch.from_numpy(tp.residues).to(dev)
-        o2 = torch.from_numpy(tp.offsets).to(dev)
-        p2 = torch.from_numpy(tp.pairs).to(dev)
-        L = tp.lengths().astype(np.float64)
-        tcells = float((L[tp.pairs[:, 0]] * L[tp.pairs[:, 1]]).sum())
-        if args.autotune_pairs > 0:
-            # the autotuner picks the score pass's plan on a sample of the batch
-            # (every candidate must agree on every output); the leg runs with it
-            plan0 = ctx.get_plan(0)
-            t = time.perf_counter()
-            table = ctx.autotune(r2, o2, p2[:args.autotune_pairs], M, 0)
-            tune_s = time.perf_counter() - t
-            chosen = ctx.get_plan(0)
-            out["autotune"] = dict(sample_pairs=args.autotune_pairs, seconds=tune_s,
-                                   table=[dict(kernel=k, rmax=r, blocks_per_cu=b, ms=ms) for k, r, b, ms in table],
-                                   chosen=dict(kernel=chosen[0], rmax=chosen[1], blocks_per_cu=chosen[2]),
-                                   default=dict(kernel=plan0[0], rmax=plan0[1], blocks_per_cu=plan0[2]))
-            log(f"autotune on {args.autotune_pairs} pairs: {len(table)} plans in {tune_s:.2f} s, chosen {chosen[:3]}")
-        tp_packed = ctx.get_plan(0)[0] >= 1
-        tp_opc, tp_peak = (PK_OPS_PER_CELL, PEAK_PK16_OPS) if tp_packed else (OPS_PER_CELL, PEAK_INT32_OPS)
-        cm.sw_score_batch(r2, o2, p2, M)
-        ctx.sync()
-        ctx.set_timing(True)
-        n0, s0 = ctx.kernel_time(0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        reps = 3
-        for _ in range(reps):
-            cm.sw_score_batch(r2, o2, p2, M)
-        e1.record()
-        ctx.sync()
-        n1, s1 = ctx.kernel_time(0)
-        ctx.set_timing(False)
-        bt = e0.elapsed_time(e1) / 1e3 / reps
-        ks = (s1 - s0) / max(n1 - n0, 1)
-        out["sw_throughput"] = dict(
-            workload=f"throughput-{args.throughput_pairs}: random pairs of a 200,000-protein pool, 80% "
-                     "lognormal(300, 0.6) / 20% U[1000,5000]", cells=tcells, batch_s=bt, gcups=tcells / bt / 1e9,
-            plan=list(ctx.get_plan(0)[:3]),
-            kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=tp_opc * tcells / ks / tp_peak,
-            int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
-        log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
-        if args.autotune_pairs > 0:
-            ctx.set_plan(0, *plan0[:3])     # the ClusterMerge legs keep the default plan
-        del r2, o2, p2
+        out["sw_throughput"] = throughput_leg(cm, ctx, args, out, log)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu

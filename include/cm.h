@@ -258,6 +258,9 @@ typedef struct {
                                        chunks; 0 = about 2^25, < 0 = one batch per level.  Not
                                        used while a screen covers CM_STAGE_REP under graph
                                        capture.  Results do not depend on it. */
+    int64_t record_candidates;      /* 1: the result keeps every pair scored during the merge stage
+                                       (representative and exchange alignments, speculative ones
+                                       included) with its score (cm_result_candidates); 0: not kept */
 } cm_params;
 
 #define CM_STAGE_REP       1u       /* representative vs representative */
@@ -335,6 +338,11 @@ cm_status cm_result_clusters(const cm_result* r, int32_t* n_clusters, const int3
  * NULL-free arrays of *n_pairs rows (possibly truncated to max_result_pairs). */
 cm_status cm_result_pairs(const cm_result* r, int64_t* n_pairs, const int32_t** pairs,
                           const int32_t** scores);
+/* Pairs (x < y) scored during the merge stage, sorted, with their scores,
+ * when the run was made with params.record_candidates = 1 (else none): the
+ * candidates the screen decides on, e.g. for calibrating its threshold. */
+cm_status cm_result_candidates(const cm_result* r, int64_t* n_pairs, const int32_t** pairs,
+                               const int32_t** scores);
 cm_status cm_result_stats(const cm_result* r, cm_stats* out);
 void      cm_result_free(cm_result* r);
 

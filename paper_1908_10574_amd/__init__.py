@@ -66,7 +66,8 @@ _lib.cm_sw_span_batch.argtypes = [_P, _P, _P, _i32, _P, _i64, _P, _i32, _i32, _P
 class CMParams(ctypes.Structure):
     _fields_ = [("matrix", _i32 * 400), ("gap_open", _i32), ("gap_extend", _i32), ("T", _i32),
                 ("mT", _i32), ("mU", _i32), ("screen_stages", ctypes.c_uint32), ("screen_tau", _f32),
-                ("max_result_pairs", _i64), ("screen_min_product", _i64), ("rep_chunk_pairs", _i64)]
+                ("max_result_pairs", _i64), ("screen_min_product", _i64), ("rep_chunk_pairs", _i64),
+                ("record_candidates", _i64)]
 
 
 class CMStats(ctypes.Structure):
@@ -94,6 +95,8 @@ _lib.cm_result_clusters.argtypes = [_P, ctypes.POINTER(_i32), ctypes.POINTER(_P)
                                     ctypes.POINTER(_P)]
 _lib.cm_result_pairs.restype = _i32
 _lib.cm_result_pairs.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_P), ctypes.POINTER(_P)]
+_lib.cm_result_candidates.restype = _i32
+_lib.cm_result_candidates.argtypes = [_P, ctypes.POINTER(_i64), ctypes.POINTER(_P), ctypes.POINTER(_P)]
 _lib.cm_result_stats.restype = _i32
 _lib.cm_result_stats.argtypes = [_P, ctypes.POINTER(CMStats)]
 _lib.cm_result_free.restype = None
@@ -340,7 +343,8 @@ def _np_from(ptr, n, dtype):
 
 
 def make_params(matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, screen_stages=0,
-                screen_tau=0.0, max_result_pairs=1 << 62, screen_min_product=0, rep_chunk_pairs=0) -> CMParams:
+                screen_tau=0.0, max_result_pairs=1 << 62, screen_min_product=0, rep_chunk_pairs=0,
+                record_candidates=False) -> CMParams:
     p = CMParams()
     m = _matrix_host(matrix)
     for k in range(400):
@@ -349,17 +353,19 @@ def make_params(matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1, scree
     p.screen_stages, p.screen_tau, p.max_result_pairs = int(screen_stages), float(screen_tau), int(max_result_pairs)
     p.screen_min_product = int(screen_min_product)
     p.rep_chunk_pairs = int(rep_chunk_pairs)
+    p.record_candidates = 1 if record_candidates else 0
     return p
 
 
 def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-11, gap_extend=-1,
                      screen=None, screen_stages=CM_STAGE_REP | CM_STAGE_EXCHANGE, screen_tau=0.0,
                      max_result_pairs=1 << 62, screen_min_product=0, rep_chunk_pairs=0,
-                     ctx: Context | None = None):
+                     record_candidates=False, ctx: Context | None = None):
     """ClusterMerge on a device-resident store (residues u8, offsets i64: CUDA tensors).
 
     Returns dict(clusters=[(rep, members ndarray)], pairs=ndarray [k,2], scores=ndarray [k],
-    stats=dict).  Synchronous.
+    stats=dict), and with record_candidates also candidates=ndarray [c,2] and
+    candidate_scores=ndarray [c] (the pairs scored during the merge stage).  Synchronous.
     """
     import torch
     ctx = ctx or context()
@@ -367,7 +373,7 @@ def clustermerge_run(residues, offsets, matrix, T=120, mT=166, mU=15, gap_open=-
     offsets = _dev(offsets, torch.int64, "offsets")
     torch.cuda.current_stream().synchronize()
     p = make_params(matrix, T, mT, mU, gap_open, gap_extend, screen_stages if screen else 0, screen_tau,
-                    max_result_pairs, screen_min_product, rep_chunk_pairs)
+                    max_result_pairs, screen_min_product, rep_chunk_pairs, record_candidates)
     res = _P()
     _check(_lib.cm_clustermerge_run(ctx.handle, residues.data_ptr() if residues.numel() else None,
                                     offsets.data_ptr(), offsets.numel() - 1, ctypes.byref(p),
@@ -394,9 +400,16 @@ def _take_result(res):
         st = CMStats()
         _check(_lib.cm_result_stats(res, ctypes.byref(st)))
         stats = {k: getattr(st, k) for k, _ in CMStats._fields_}
+        nc2 = _i64()
+        cp, cs = _P(), _P()
+        _check(_lib.cm_result_candidates(res, ctypes.byref(nc2), ctypes.byref(cp), ctypes.byref(cs)))
+        extra = {}
+        if nc2.value:
+            extra = dict(candidates=_np_from(cp.value, 2 * nc2.value, np.int32).reshape(-1, 2),
+                         candidate_scores=_np_from(cs.value, nc2.value, np.int32))
     finally:
         _lib.cm_result_free(res)
-    return dict(clusters=clusters, pairs=pairs, scores=scores, stats=stats)
+    return dict(clusters=clusters, pairs=pairs, scores=scores, stats=stats, **extra)
 
 
 def clustermerge_extend(residues, offsets, matrix, prev_clusters, n_prev, known_pairs=None, known_scores=None,

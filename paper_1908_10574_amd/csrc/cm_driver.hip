@@ -69,6 +69,10 @@ struct cm_result {
     std::vector<int32_t> members;
     std::vector<int32_t> pairs;
     std::vector<int32_t> pair_scores;
+    // pairs scored during the merge stage (representative and exchange
+    // alignments, speculative ones included), when params.record_candidates
+    std::vector<int32_t> cand_pairs;
+    std::vector<int32_t> cand_scores;
     cm_stats stats{};
 };
 
@@ -732,6 +736,7 @@ private:
     std::vector<Cluster> cl_;
     std::vector<std::vector<int32_t>> sets_;
     PairMap cache_;    // unordered pair -> score
+    std::vector<std::pair<uint64_t, int32_t>> cand_;   // merge-stage scores (params.record_candidates)
     PairMap pending_;  // pairs requested in the current wave
 };
 
@@ -986,6 +991,8 @@ cm_status Driver::align_requests(std::vector<int32_t>& req) {
     cm_status s = al_.run(req.data(), static_cast<int64_t>(req.size() / 2), false, out);
     if (s != CM_OK) return s;
     for (size_t k = 0; k < out.size(); ++k) cache_.put(unordered_key(req[2 * k], req[2 * k + 1]), out[k]);
+    if (p_.record_candidates)
+        for (size_t k = 0; k < out.size(); ++k) cand_.emplace_back(unordered_key(req[2 * k], req[2 * k + 1]), out[k]);
     pending_.clear();
     req.clear();
     return CM_OK;
@@ -1131,6 +1138,7 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
         for (size_t k = 0; k < n; ++k) {
             if (!keep[k]) continue;             // dropped by the screen: not similar
             const int32_t sc = out[q];
+            if (p_.record_candidates) cand_.emplace_back(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
             if (sc >= p_.T) {
                 bits[k] = kSim;
                 cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
@@ -1304,6 +1312,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     for (size_t k = 0; k < total; ++k) {
         if (!keep[k]) continue;                 // dropped by the screen: not similar
         const int32_t sc = out[q++];
+        if (p_.record_candidates) cand_.emplace_back(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
         if (sc >= p_.T) {
             bits[k] = kSim;
             // similar representative scores may be needed again (exchanges, final stage)
@@ -1598,6 +1607,23 @@ cm_status Driver::run(cm_result** out) {
     if (sets_.empty()) sets_.emplace_back();
     const auto t1 = Clock::now();
     std::unique_ptr<cm_result> res(new cm_result());
+    if (p_.record_candidates) {
+        // every pair scored in the merge stage, once
+        std::vector<std::pair<uint64_t, int32_t>>& ent = cand_;
+        std::sort(ent.begin(), ent.end());
+        ent.erase(std::unique(ent.begin(), ent.end(),
+                              [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) {
+                                  return x.first == y.first;
+                              }),
+                  ent.end());
+        res->cand_pairs.reserve(2 * ent.size());
+        res->cand_scores.reserve(ent.size());
+        for (const auto& e : ent) {
+            res->cand_pairs.push_back(static_cast<int32_t>(e.first >> 32));
+            res->cand_pairs.push_back(static_cast<int32_t>(e.first & 0xffffffffu));
+            res->cand_scores.push_back(e.second);
+        }
+    }
     s = final_stage(res.get());
     if (s != CM_OK) return s;
     const auto t2 = Clock::now();
@@ -1669,6 +1695,8 @@ static cm_status check_run_params(const cm_params* params) {
                                   x, y, y, x);
     if (params->T < 1 || params->mT < 0 || params->mU < 0 || params->max_result_pairs < 0)
         return cmrt::fail(CM_EINVAL, "T must be >= 1; mT, mU and max_result_pairs >= 0");
+    if (params->record_candidates != 0 && params->record_candidates != 1)
+        return cmrt::fail(CM_EINVAL, "record_candidates must be 0 or 1");
     return CM_OK;
 }
 
@@ -1763,6 +1791,16 @@ cm_status cm_result_pairs(const cm_result* r, int64_t* n_pairs, const int32_t** 
     if (n_pairs) *n_pairs = static_cast<int64_t>(r->pair_scores.size());
     if (pairs) *pairs = r->pairs.data();
     if (scores) *scores = r->pair_scores.data();
+    return CM_OK;
+    CM_CATCH
+}
+
+cm_status cm_result_candidates(const cm_result* r, int64_t* n_pairs, const int32_t** pairs, const int32_t** scores) {
+    CM_TRY
+    if (!r) return cmrt::fail(CM_EINVAL, "result is NULL");
+    if (n_pairs) *n_pairs = static_cast<int64_t>(r->cand_scores.size());
+    if (pairs) *pairs = r->cand_pairs.data();
+    if (scores) *scores = r->cand_scores.data();
     return CM_OK;
     CM_CATCH
 }

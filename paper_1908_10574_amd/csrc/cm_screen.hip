@@ -19,7 +19,9 @@ struct cm_screen {
     DeviceBuf master, mom, vel, grad;      // fp32 [kParams]
     DeviceBuf w1, w2, w2t, w3;             // bf16 copies
     // per-batch workspace, sized for cap rows
-    DeviceBuf h1, h1t, h2, z, dz, loss, dh2, dh2t, dh1t, xt;
+    DeviceBuf h1, h1t, h2, z, dz, loss, dh2, dh2t, dh1t, xt, x;
+    DeviceBuf zpart;                       // fp32 [cap][kHidden / 128]: layer-2 logit partials
+    DeviceBuf part;                        // fp32 split-K partials of the weight gradients
     DeviceBuf gpart;                       // fp32 [cap / 64][kHidden]: layer-3 gradient partials
     // training runs: epoch orders, the current batch's rows and labels, loss log
     DeviceBuf perm, bpairs, blabels, losslog;
@@ -42,15 +44,29 @@ cm_status alloc_params(cm_screen* s) {
     return CM_OK;
 }
 
+// rows of a padded batch: the training products tile the batch by 128
+int64_t pad_rows(int64_t n) { return round_up(n, 128); }
+
+// largest split count <= s_max (a power of two) whose K share is a multiple
+// of the products' K step (128)
+int splits_for(int mb, int s_max) {
+    int sp = s_max;
+    while (sp > 1 && mb % (128 * sp) != 0) sp /= 2;
+    return sp;
+}
+constexpr int kSplitW1 = 4, kSplitW2 = 8;
+
 // training workspace for mb rows (every buffer sized for s->cap rows)
 cm_status ensure_workspace(cm_screen* s, int mb) {
     if (mb <= s->cap) return CM_OK;
     const int c = mb;
     const size_t hb = static_cast<size_t>(c) * cms::kHidden * 2;
+    const size_t parts = std::max<size_t>(static_cast<size_t>(kSplitW1) * cms::kW1, static_cast<size_t>(kSplitW2) * cms::kW2);
     bool ok = s->z.ensure(static_cast<size_t>(c) * 4);
     ok = ok && s->h1.ensure(hb) && s->h1t.ensure(hb) && s->h2.ensure(hb) && s->dz.ensure(c * 4) &&
          s->loss.ensure(c * 4) && s->dh2.ensure(hb) && s->dh2t.ensure(hb) && s->dh1t.ensure(hb) &&
-         s->xt.ensure(static_cast<size_t>(c) * cms::kIn * 2) &&
+         s->xt.ensure(static_cast<size_t>(c) * cms::kIn * 2) && s->x.ensure(static_cast<size_t>(c) * cms::kIn * 2) &&
+         s->zpart.ensure(static_cast<size_t>(c) * (cms::kHidden / 128) * 4) && s->part.ensure(parts * 4) &&
          s->gpart.ensure(static_cast<size_t>(c / 64) * cms::kHidden * 4);
     if (!ok) return fail(CM_ENOMEM, "screen workspace for %d rows", c);
     s->cap = c;
@@ -73,51 +89,71 @@ cms::FwdArgs fwd_args(const cm_screen* s, const uint16_t* feat, const int32_t* p
     return a;
 }
 
-// forward + backward of the mean BCE on one batch; gradients in s->grad
+// forward + backward of the mean BCE on one batch; gradients in s->grad.
+// The batch is padded to mb rows (a multiple of 128); padding rows have zero
+// inputs and contribute nothing (their dz is 0).
 cm_status forward_backward(cm_screen* s, const uint16_t* feat, const int32_t* pairs, const uint8_t* labels, int n,
                            float* loss_out) {
-    const int mb = static_cast<int>(round_up(n, 64));
+    const int mb = static_cast<int>(pad_rows(n));
     cm_status r = ensure_workspace(s, mb);
     if (r != CM_OK) return r;
     hipStream_t st = s->st;
+    uint16_t* x = static_cast<uint16_t*>(s->x.ptr);
+    uint16_t* xt = static_cast<uint16_t*>(s->xt.ptr);
     uint16_t* h1 = static_cast<uint16_t*>(s->h1.ptr);
     uint16_t* h1t = static_cast<uint16_t*>(s->h1t.ptr);
     uint16_t* h2 = static_cast<uint16_t*>(s->h2.ptr);
     uint16_t* dh2 = static_cast<uint16_t*>(s->dh2.ptr);
     uint16_t* dh2t = static_cast<uint16_t*>(s->dh2t.ptr);
     uint16_t* dh1t = static_cast<uint16_t*>(s->dh1t.ptr);
-    uint16_t* xt = static_cast<uint16_t*>(s->xt.ptr);
+    float* part = static_cast<float*>(s->part.ptr);
+    float* zpart = static_cast<float*>(s->zpart.ptr);
     float* g = static_cast<float*>(s->grad.ptr);
-    cms::FwdArgs a = fwd_args(s, feat, pairs, n, static_cast<float*>(s->z.ptr));
-    a.h1 = h1;
-    a.h1t = h1t;
-    a.h2 = h2;
-    a.ld_t = mb;
-    if ((r = chk(cms::launch_fwd(a, mb, st), "screen forward")) != CM_OK) return r;
-    if ((r = chk(cms::launch_pair_xt(feat, pairs, n, mb, xt, st), "pair inputs")) != CM_OK) return r;
-    if ((r = chk(cms::launch_backward_tail(static_cast<float*>(s->z.ptr), labels, n, mb, h2,
-                                           static_cast<uint16_t*>(s->w3.ptr), static_cast<float*>(s->dz.ptr),
-                                           static_cast<float*>(s->loss.ptr), dh2, dh2t,
-                                           static_cast<float*>(s->gpart.ptr), g + cms::kOffW3,
-                                           g + cms::kOffB3, st),
+    const float* master = static_cast<const float*>(s->master.ptr);
+    const uint16_t* w1 = static_cast<const uint16_t*>(s->w1.ptr);
+    const uint16_t* w2 = static_cast<const uint16_t*>(s->w2.ptr);
+    const uint16_t* w2t = static_cast<const uint16_t*>(s->w2t.ptr);
+    const uint16_t* w3 = static_cast<const uint16_t*>(s->w3.ptr);
+    if ((r = chk(cms::launch_build_x(feat, pairs, n, mb, x, xt, st), "pair inputs")) != CM_OK) return r;
+    cms::Gemm2Args q{};
+    // h1 = relu(X W1^T + b1), row-major and transposed
+    q.A = x; q.B = w1; q.M = mb; q.N = cms::kHidden; q.lda = cms::kIn; q.ldb = cms::kIn; q.kper = cms::kIn;
+    q.Cb = h1; q.ldcb = cms::kHidden; q.Ct = h1t; q.ldct = mb; q.bias = master + cms::kOffB1;
+    if ((r = chk(cms::launch_gemm2(q, 64, cms::kEpi2BiasRelu, 1, st), "layer 1")) != CM_OK) return r;
+    // h2 = relu(h1 W2^T + b2) and the logit partials of every 128 units
+    q = {};
+    q.A = h1; q.B = w2; q.M = mb; q.N = cms::kHidden; q.lda = cms::kHidden; q.ldb = cms::kHidden;
+    q.kper = cms::kHidden; q.Cb = h2; q.ldcb = cms::kHidden; q.bias = master + cms::kOffB2; q.w3 = w3;
+    q.zpart = zpart;
+    if ((r = chk(cms::launch_gemm2(q, 64, cms::kEpi2Logit, 1, st), "layer 2")) != CM_OK) return r;
+    if ((r = chk(cms::launch_logit_bce(zpart, cms::kHidden / 128, master + cms::kOffB3, labels, n, mb,
+                                       static_cast<float*>(s->z.ptr), static_cast<float*>(s->dz.ptr),
+                                       static_cast<float*>(s->loss.ptr), st),
+                 "loss")) != CM_OK)
+        return r;
+    // dH2 (both layouts), layer-3 gradients
+    if ((r = chk(cms::launch_backward_tail(static_cast<float*>(s->dz.ptr), n, mb, h2, w3, dh2, dh2t,
+                                           static_cast<float*>(s->gpart.ptr), g + cms::kOffW3, g + cms::kOffB3, st),
                  "layer-3 backward")) != CM_OK)
         return r;
-    cms::GemmArgs q{};
-    // dW2[i][j] = sum_m dH2[m][i] H1[m][j]
+    // dW2[i][j] = sum_m dH2[m][i] H1[m][j]: split over the batch, partials added in order
+    const int s2 = splits_for(mb, kSplitW2);
     q = {};
-    q.A = dh2t; q.B = h1t; q.M = cms::kHidden; q.N = cms::kHidden; q.K = mb; q.lda = mb; q.ldb = mb;
-    q.Cf = g + cms::kOffW2; q.ldc = cms::kHidden;
-    if ((r = chk(cms::launch_gemm(q, cms::kEpiF32, st), "dW2")) != CM_OK) return r;
+    q.A = dh2t; q.B = h1t; q.M = cms::kHidden; q.N = cms::kHidden; q.lda = mb; q.ldb = mb; q.kper = mb / s2;
+    q.Cp = part;
+    if ((r = chk(cms::launch_gemm2(q, 128, cms::kEpi2Partial, s2, st), "dW2")) != CM_OK) return r;
+    if ((r = chk(cms::launch_reduce(part, s2, cms::kW2, g + cms::kOffW2, st), "dW2 sum")) != CM_OK) return r;
     // dH1^T[j][m] = (sum_i dH2[m][i] W2[i][j]) * [h1[m][j] > 0]
     q = {};
-    q.A = dh2; q.B = static_cast<const uint16_t*>(s->w2t.ptr); q.M = mb; q.N = cms::kHidden; q.K = cms::kHidden;
-    q.lda = cms::kHidden; q.ldb = cms::kHidden; q.Cb = dh1t; q.ldc = mb; q.mask = h1; q.ldm = cms::kHidden;
-    if ((r = chk(cms::launch_gemm(q, cms::kEpiMaskT, st), "dH1")) != CM_OK) return r;
+    q.A = dh2; q.B = w2t; q.M = mb; q.N = cms::kHidden; q.lda = cms::kHidden; q.ldb = cms::kHidden;
+    q.kper = cms::kHidden; q.Ct = dh1t; q.ldct = mb; q.mask = h1; q.ldm = cms::kHidden;
+    if ((r = chk(cms::launch_gemm2(q, 64, cms::kEpi2MaskT, 1, st), "dH1")) != CM_OK) return r;
     // dW1[i][k] = sum_m dH1[m][i] X[m][k]
+    const int s1 = splits_for(mb, kSplitW1);
     q = {};
-    q.A = dh1t; q.B = xt; q.M = cms::kHidden; q.N = cms::kIn; q.K = mb; q.lda = mb; q.ldb = mb;
-    q.Cf = g + cms::kOffW1; q.ldc = cms::kIn;
-    if ((r = chk(cms::launch_gemm(q, cms::kEpiF32, st), "dW1")) != CM_OK) return r;
+    q.A = dh1t; q.B = xt; q.M = cms::kHidden; q.N = cms::kIn; q.lda = mb; q.ldb = mb; q.kper = mb / s1; q.Cp = part;
+    if ((r = chk(cms::launch_gemm2(q, 128, cms::kEpi2Partial, s1, st), "dW1")) != CM_OK) return r;
+    if ((r = chk(cms::launch_reduce(part, s1, cms::kW1, g + cms::kOffW1, st), "dW1 sum")) != CM_OK) return r;
     if ((r = chk(cms::launch_rowsum(dh2t, cms::kHidden, mb, g + cms::kOffB2, st), "db2")) != CM_OK) return r;
     if ((r = chk(cms::launch_rowsum(dh1t, cms::kHidden, mb, g + cms::kOffB1, st), "db1")) != CM_OK) return r;
     if (loss_out) {
@@ -169,18 +205,16 @@ cm_status upload_master(cm_screen* s, const float* host) {
     return chk(hipStreamSynchronize(s->st), "upload");
 }
 
-// one Adam update of the master weights from s->grad, then the bf16 copies
+// one Adam update of the master weights from s->grad and, in the same pass,
+// the bf16 copies the network reads
 cm_status adam_step(cm_screen* s, float lr) {
     s->step += 1;
-    cm_status r = chk(cms::launch_adam(static_cast<float*>(s->master.ptr), static_cast<const float*>(s->grad.ptr),
-                                       static_cast<float*>(s->mom.ptr), static_cast<float*>(s->vel.ptr), cms::kParams,
-                                       lr, 0.9f, 0.999f, 1e-8f, s->step, s->st),
-                      "adam");
-    if (r != CM_OK) return r;
-    return chk(cms::launch_pack(static_cast<const float*>(s->master.ptr), static_cast<uint16_t*>(s->w1.ptr),
-                                static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
-                                static_cast<uint16_t*>(s->w3.ptr), s->st),
-               "pack");
+    return chk(cms::launch_adam_pack(static_cast<float*>(s->master.ptr), static_cast<const float*>(s->grad.ptr),
+                                     static_cast<float*>(s->mom.ptr), static_cast<float*>(s->vel.ptr), cms::kParams,
+                                     lr, 0.9f, 0.999f, 1e-8f, s->step, static_cast<uint16_t*>(s->w1.ptr),
+                                     static_cast<uint16_t*>(s->w2.ptr), static_cast<uint16_t*>(s->w2t.ptr),
+                                     static_cast<uint16_t*>(s->w3.ptr), s->st),
+               "adam");
 }
 
 int64_t train_steps(int64_t n, const cm_train_cfg* c) {
@@ -247,7 +281,8 @@ void cm_screen_destroy(cm_screen* s) {
     if (!s) return;
     if (s->st) { (void)hipStreamSynchronize(s->st); (void)hipStreamDestroy(s->st); }
     for (DeviceBuf* b : {&s->master, &s->mom, &s->vel, &s->grad, &s->w1, &s->w2, &s->w2t, &s->w3, &s->h1, &s->h1t,
-                         &s->h2, &s->z, &s->dz, &s->loss, &s->dh2, &s->dh2t, &s->dh1t, &s->xt, &s->gpart,
+                         &s->h2, &s->z, &s->dz, &s->loss, &s->dh2, &s->dh2t, &s->dh1t, &s->xt, &s->x,
+                         &s->zpart, &s->part, &s->gpart,
                          &s->perm, &s->bpairs, &s->blabels, &s->losslog})
         b->release();
     delete s;
@@ -344,7 +379,7 @@ cm_status cm_screen_train(cm_screen* s, const uint16_t* feat, const int32_t* pai
     if (per_epoch < 1) return fail(CM_EINVAL, "no full batch of %d pairs in %lld", cfg->batch,
                                    static_cast<long long>(n_pairs));
     const int64_t steps = per_epoch * cfg->epochs;
-    const int mb_max = static_cast<int>(round_up(std::min<int64_t>(cfg->batch, n_pairs), 64));
+    const int mb_max = static_cast<int>(pad_rows(std::min<int64_t>(cfg->batch, n_pairs)));
     cm_status r = ensure_workspace(s, mb_max);
     if (r != CM_OK) return r;
     if (!s->perm.ensure(static_cast<size_t>(n_pairs) * 4 * cfg->epochs) ||
@@ -367,7 +402,7 @@ cm_status cm_screen_train(cm_screen* s, const uint16_t* feat, const int32_t* pai
         for (int64_t b = 0; b < per_epoch; ++b, ++k) {
             const int64_t first = b * cfg->batch;
             const int n = static_cast<int>(std::min<int64_t>(cfg->batch, n_pairs - first));
-            const int mb = static_cast<int>(round_up(n, 64));
+            const int mb = static_cast<int>(pad_rows(n));
             r = chk(cms::launch_gather_batch(perm + first, pairs, labels, n, mb, bp, by, st), "batch gather");
             if (r == CM_OK) r = forward_backward(s, feat, bp, by, n, nullptr);
             if (r == CM_OK) r = chk(cms::launch_mean(static_cast<const float*>(s->loss.ptr), n, log + k, st), "loss");

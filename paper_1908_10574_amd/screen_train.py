@@ -10,7 +10,7 @@ import time
 
 import numpy as np
 
-from . import Screen, context, kmer_features, sw_score_batch, sync
+from . import Screen, clustermerge_run, context, kmer_features, sw_score_batch, sync
 
 
 def label_pairs(residues, offsets, pairs: np.ndarray, matrix, T: int = 120, gap_open: int = -11,
@@ -100,3 +100,27 @@ def train_on_dataset(ds, n_holdout_frac: float = 0.05, epochs: int = 5, batch: i
                 holdout_neg_dropped=float((z[ho_y == 0] < tau).mean()) if (ho_y == 0).sum() else float("nan"),
                 label_s=t1 - t0, train_s=t2 - t1)
     return scr, tau, info
+
+
+def calibrate_on_clustermerge(scr: Screen, ds, keep_recall: float = 0.999, T: int = 120) -> tuple:
+    """Threshold from the candidates the screen will judge: a plain
+    ClusterMerge run on a separate family set records every pair it scores in
+    the merge stage (representative and exchange alignments); tau keeps
+    keep_recall of those scoring >= T.  Returns (tau, info)."""
+    import torch
+    t0 = time.perf_counter()
+    res = torch.from_numpy(ds.residues).cuda()
+    off = torch.from_numpy(ds.offsets).cuda()
+    feat = kmer_features(res, off)
+    g = clustermerge_run(res, off, ds.matrix, T=T, record_candidates=True, max_result_pairs=0)
+    pairs, scores = g["candidates"], g["candidate_scores"]
+    z = screen_logits(scr, feat, pairs)
+    y = (scores >= T).astype(np.uint8)
+    tau = calibrate_tau(z, y, keep_recall)
+    info = dict(workload=f"plain ClusterMerge candidates of a separate {ds.n}-protein family set "
+                         f"(seed {ds.meta.get('seed')})", n_candidates=int(len(pairs)),
+                positive_frac=float(y.mean()), tau=tau,
+                candidate_pos_kept=float((z[y == 1] >= tau).mean()) if y.sum() else float("nan"),
+                candidate_neg_dropped=float((z[y == 0] < tau).mean()) if (y == 0).sum() else float("nan"),
+                auc=auc(z, y), seconds=time.perf_counter() - t0)
+    return tau, info
