@@ -838,36 +838,56 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 Fout = F;
             };
 
+            // step t (even: never the last step of a 16-column chunk)
+            auto step_even = [&](int t, bool store) {
+                const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
+                const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+                pb0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
+                pb1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
+                __builtin_amdgcn_sched_barrier(0);
+                cells(t, HA, HB, pa0, pa1, false, store);
+                feedR = feedR2;
+                c = cn;
+            };
+            // step t (odd)
+            auto step_odd = [&](int t, bool chunk_last) {
+                uint32_t feedR2;
+                if (chunk_last) {
+                    feedR2 = col_in(nfeedR, t + 1 + gl);
+                    nfeedR = col_raw(t + 1 + kGroup + gl);
+                } else {
+                    feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
+                }
+                const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+                pa0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
+                pa1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
+                __builtin_amdgcn_sched_barrier(0);
+                cells(t, HB, HA, pb0, pb1, chunk_last, false);
+                feedR = feedR2;
+                c = cn;
+            };
             const int steps = (n_max + kGroup - 1 + 1) & ~1;
+            // Two-profile kernel: whole 16-column chunks fully unrolled, so that
+            // which step ends a chunk (feed reload) or starts one (boundary
+            // store) is known at compile time; the two-step loop takes the
+            // remaining steps.  The shared-query kernel runs every step in the
+            // two-step loop (its rows per lane leave no registers for the
+            // unrolled code).
+            const int full = kShared ? 0 : steps & ~(kGroup - 1);
+            int t = 0;
 #pragma unroll 1
-            for (int t = 0; t < steps; t += 2) {
-                {   // step t (even: never the last step of a 16-column chunk)
-                    const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
-                    const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
-                    pb0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
-                    pb1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
-                    __builtin_amdgcn_sched_barrier(0);
-                    cells(t, HA, HB, pa0, pa1, false, (t & (kGroup - 1)) == 0 && t > 0);
-                    feedR = feedR2;
-                    c = cn;
+            for (; t < full; t += kGroup) {
+                const bool st = t > 0;
+#pragma unroll
+                for (int u = 0; u < kGroup; u += 2) {
+                    step_even(t + u, u == 0 && st);
+                    step_odd(t + u + 1, u + 2 == kGroup);
                 }
-                {   // step t+1
-                    const bool chunk_last = ((t + 2) & (kGroup - 1)) == 0;
-                    uint32_t feedR2;
-                    if (chunk_last) {
-                        feedR2 = col_in(nfeedR, t + 2 + gl);
-                        nfeedR = col_raw(t + 2 + kGroup + gl);
-                    } else {
-                        feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
-                    }
-                    const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
-                    pa0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
-                    pa1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
-                    __builtin_amdgcn_sched_barrier(0);
-                    cells(t + 1, HB, HA, pb0, pb1, chunk_last, false);
-                    feedR = feedR2;
-                    c = cn;
-                }
+            }
+#pragma unroll 1
+            for (; t < steps; t += 2) {
+                step_even(t, (t & (kGroup - 1)) == 0 && t > 0);
+                step_odd(t + 1, ((t + 2) & (kGroup - 1)) == 0);
             }
             if constexpr (kMulti) {
                 // collect the last step's bottom row and write the final columns
