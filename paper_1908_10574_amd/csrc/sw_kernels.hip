@@ -590,7 +590,7 @@ __device__ __forceinline__ ProfWords<W> load_prof_any(const uint8_t* p) {
 template <int R, int RMAXT, bool kShared>
 __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __restrict__ order, int item,
                                             int n_work, const int8_t* __restrict__ s_mat,
-                                            uint8_t* __restrict__ s_prof) {
+                                            uint8_t* __restrict__ s_prof, uint2* __restrict__ s_stage) {
     constexpr bool k16 = kShared && R <= kR16Max;   // 16-bit shared profile
     constexpr int RP = k16 ? prof16_row_bytes(R) : prof_row_bytes(R);   // bytes per lane and residue
     constexpr int W = RP / 4;
@@ -640,6 +640,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
     const uint8_t* lp0 = prof0 + gl * RP;
     const uint8_t* lp1 = prof1 + gl * RP;
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
+    uint2* stg = s_stage + g * kGroup;   // this group's staged boundary chunk
 
     bool bad = false;
     int badcode = 0;
@@ -746,14 +747,18 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
             uint32_t hdiag = KB, Hout = KB, Fout = KB;
             uint32_t feedR = col_in(col_raw(gl), gl);
             int2 nfeedR = col_raw(kGroup + gl);
-            uint32_t feedH = 0, feedF = 0, collH = 0, collF = 0;
+            uint32_t collH = 0, collF = 0;
+            uint32_t sH = 0, sF = 0;     // staged top row (H, F) of the next step's column
             int2 nfeed = make_int2(0, 0);
             if constexpr (kMulti) {
                 const int2 v0 = bnd_raw(gl);
                 const uint32_t mk = rd_mask(gl);
-                feedH = (static_cast<uint32_t>(v0.x) & mk) | (KB & ~mk);
-                feedF = (static_cast<uint32_t>(v0.y) & mk) | (KB & ~mk);
+                stg[gl] = make_uint2((static_cast<uint32_t>(v0.x) & mk) | (KB & ~mk),
+                                     (static_cast<uint32_t>(v0.y) & mk) | (KB & ~mk));
                 nfeed = bnd_raw(kGroup + gl);
+                const uint2 v = stg[0];
+                sH = v.x;
+                sF = v.y;
             }
             uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR), static_cast<int>(kSentPk)));
             ProfWords<W> pa0 = load_prof_any<W, k16>(lp0 + (c & 0xffffu));
@@ -761,30 +766,29 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
             ProfWords<W> pb0, pb1;
 
             // One column step t.  Multi-strip: lane 0 takes the top row from
-            // the boundary feed (a 16-column chunk rotated one lane per step,
-            // reloaded when a chunk ends), and lane 15's bottom row of the
+            // the group's 16-column chunk of the boundary row staged in LDS
+            // (all lanes read the next step's column one step ahead; when a
+            // chunk ends its lanes stage the next chunk, loaded from global
+            // memory 16 steps earlier), and lane 15's bottom row of the
             // previous step is collected into a 16-column register that is
-            // written to the boundary row every 16 steps.  Each feed register
-            // is rotated before the DPP that overwrites it, so that DPP can
-            // write in place.
+            // written to the boundary row every 16 steps.
             auto cells = [&](int t, const uint32_t (&Hi)[R], uint32_t (&Ho)[R], const ProfWords<W>& w0,
                              const ProfWords<W>& w1, bool chunk_last, bool store) {
                 uint32_t Htop, F;
                 if constexpr (kMulti) {
-                    uint32_t nH, nF;
-                    if (chunk_last) {
+                    Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(sH), static_cast<int>(Hout)));
+                    F = static_cast<uint32_t>(dpp_shr1(static_cast<int>(sF), static_cast<int>(Fout)));
+                    if (chunk_last) {   // stage columns t+1 .. t+16
                         const uint32_t mk = rd_mask(t + 1 + gl);
-                        nH = (static_cast<uint32_t>(nfeed.x) & mk) | (KB & ~mk);
-                        nF = (static_cast<uint32_t>(nfeed.y) & mk) | (KB & ~mk);
+                        stg[gl] = make_uint2((static_cast<uint32_t>(nfeed.x) & mk) | (KB & ~mk),
+                                             (static_cast<uint32_t>(nfeed.y) & mk) | (KB & ~mk));
                         nfeed = bnd_raw(t + 1 + kGroup + gl);
-                    } else {
-                        nH = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedH)));
-                        nF = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedF)));
                     }
-                    Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedH), static_cast<int>(Hout)));
-                    F = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedF), static_cast<int>(Fout)));
-                    feedH = nH;
-                    feedF = nF;
+                    {
+                        const uint2 v = stg[(t + 1) & (kGroup - 1)];
+                        sH = v.x;
+                        sF = v.y;
+                    }
                     collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
                     collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
                     if (store) {   // lane j holds the bottom row of column t - 31 + j
@@ -941,6 +945,7 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
     __shared__ __attribute__((aligned(16))) uint8_t
         s_prof[kPairsPerWave * 2 * kNRes * kGroup * prof_row_bytes(RMAXT)];
+    __shared__ uint2 s_stage[kPairsPerWave * kGroup];
     const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
     if (n_work == 0) return;
     int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
@@ -955,15 +960,15 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
         int R;
         if (a.keys) R = kRMax - static_cast<int>(a.keys[static_cast<int64_t>(item) * kPairsPerWavePk] >> 24);
         else R = item_rows(a, a.order, item, kPairsPerWavePk, RMAXT, false);
-        if (R <= 1) run_item_pk<1, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-        else if (R == 2) run_item_pk<2, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-        else if (R == 3) run_item_pk<3, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+        if (R <= 1) run_item_pk<1, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+        else if (R == 2) run_item_pk<2, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+        else if (R == 3) run_item_pk<3, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
         else if constexpr (RMAXT >= 8) {
-            if (R == 5) run_item_pk<5, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-            else if (R == 6) run_item_pk<6, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-            else if (R == 7) run_item_pk<7, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
-            else run_item_pk<8, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof);
+            if (R == 5) run_item_pk<5, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+            else if (R == 6) run_item_pk<6, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+            else if (R == 7) run_item_pk<7, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+            else run_item_pk<8, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
         }
     }
 }
@@ -972,15 +977,16 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
 // per lane up to 32 (strips of up to 512 rows), one LDS profile per wavefront.
 template <int R>
 __device__ __forceinline__ void run_pkq_range(const SwArgs& a, int Rw, int item, int n_work, const int8_t* s_mat,
-                                              uint8_t* s_prof) {
-    if (Rw == R) run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof);
-    else if constexpr (R < kRMaxQ) run_pkq_range<R + 1>(a, Rw, item, n_work, s_mat, s_prof);
+                                              uint8_t* s_prof, uint2* s_stage) {
+    if (Rw == R) run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+    else if constexpr (R < kRMaxQ) run_pkq_range<R + 1>(a, Rw, item, n_work, s_mat, s_prof, s_stage);
 }
 
 __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
     __shared__ __attribute__((aligned(16))) uint8_t
         s_prof[kNRes * kGroup * cmax(prof_row_bytes(kRMaxQ), prof16_row_bytes(kR16Max))];
+    __shared__ uint2 s_stage[kPairsPerWave * kGroup];
     const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
     if (n_work == 0) return;
     int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
@@ -993,7 +999,7 @@ __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
         const int R = item_rows(a, a.order, item, kPairsPerWavePk, kRMaxQ, false);
-        run_pkq_range<1>(a, R, item, n_work, s_mat, s_prof);
+        run_pkq_range<1>(a, R, item, n_work, s_mat, s_prof, s_stage);
     }
 }
 
