@@ -414,8 +414,24 @@ __global__ __launch_bounds__(256) void k_gemm2(Gemm2Args g) {
     __shared__ float zl[2][BM];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int64_t kbeg = static_cast<int64_t>(blockIdx.z) * g.kper;
+    // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs in
+    // launch order, so block b runs on XCD b % 8.  Each XCD takes a contiguous
+    // range of tiles (N fastest), so the column tiles that share an A row
+    // block run on one XCD and read it through that XCD's L2 once.
+    int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    {
+        const int gx = gridDim.x, gy = gridDim.y;
+        const int total = gx * gy * gridDim.z;
+        if ((total & 7) == 0) {
+            const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+            const int q = (lin & 7) * (total >> 3) + (lin >> 3);
+            bx = q % gx;
+            by = (q / gx) % gy;
+            bz = q / (gx * gy);
+        }
+    }
+    const int m0 = by * BM, n0 = bx * BN;
+    const int64_t kbeg = static_cast<int64_t>(bz) * g.kper;
     const int r = lane & 15, kq = (lane >> 4) * 8;
     // loaders: B row tid / 2, 64 columns at (tid & 1) * 64 (8 x 16 B); A likewise
     // when BM = 128, and row tid / 4, 32 columns at (tid & 3) * 32 (4 x 16 B) when BM = 64
@@ -463,7 +479,7 @@ __global__ __launch_bounds__(256) void k_gemm2(Gemm2Args g) {
     // epilogue: acc[i][j][q] is C[m0 + wm*BM/2 + 16i + 4(lane/16) + q][n0 + wn*64 + 16j + r]
     const int mrow = m0 + wm * (BM / 2) + 4 * (lane >> 4);
     if constexpr (EPI == kEpi2Partial) {
-        float* out = g.Cp + static_cast<int64_t>(blockIdx.z) * g.M * g.N;
+        float* out = g.Cp + static_cast<int64_t>(bz) * g.M * g.N;
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
@@ -527,7 +543,7 @@ __global__ __launch_bounds__(256) void k_gemm2(Gemm2Args g) {
                 }
             __syncthreads();
             if (tid < BM)
-                g.zpart[static_cast<int64_t>(m0 + tid) * (g.N / BN) + blockIdx.x] = zl[0][tid] + zl[1][tid];
+                g.zpart[static_cast<int64_t>(m0 + tid) * (g.N / BN) + bx] = zl[0][tid] + zl[1][tid];
         }
     }
 }
