@@ -63,14 +63,36 @@ __device__ __forceinline__ int dpp_shl1_any(int src) {
     // lane k <- lane k+1 of the same 16-lane row; lane 15 of the row reads 0
     return __builtin_amdgcn_mov_dpp(src, 0x101, 0xf, 0xf, true);
 }
+// The same moves over a lane group of G: one 16-lane row (row_shr / row_shl)
+// or the whole 64-lane wavefront (wave_shr / wave_shl).
+template <int G>
+__device__ __forceinline__ int dpp_shr1g(int old_v, int src) {
+    if constexpr (G == 16) return dpp_shr1(old_v, src);
+    else return __builtin_amdgcn_update_dpp(old_v, src, 0x138, 0xf, 0xf, false);
+}
+template <int G>
+__device__ __forceinline__ int dpp_shl1g(int old_v, int src) {
+    if constexpr (G == 16) return dpp_shl1(old_v, src);
+    else return __builtin_amdgcn_update_dpp(old_v, src, 0x130, 0xf, 0xf, false);
+}
+template <int G>
+__device__ __forceinline__ int dpp_shr1_zerog(int src) {
+    if constexpr (G == 16) return dpp_shr1_zero(src);
+    else return __builtin_amdgcn_mov_dpp(src, 0x138, 0xf, 0xf, true);
+}
+template <int G>
+__device__ __forceinline__ int dpp_shl1_anyg(int src) {
+    if constexpr (G == 16) return dpp_shl1_any(src);
+    else return __builtin_amdgcn_mov_dpp(src, 0x130, 0xf, 0xf, true);
+}
 __device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
 
 template <int W>
 struct ProfWords { uint32_t w[W]; };
 
-template <int W>
+template <int W, int G = kGroup>
 __device__ __forceinline__ ProfWords<W> load_prof(const uint8_t* prof, int c, int gl) {
-    const uint8_t* p = prof + (c * kGroup + gl) * (4 * W);
+    const uint8_t* p = prof + (c * G + gl) * (4 * W);
     ProfWords<W> r;
     if constexpr (W == 4) {
         uint4 v = *reinterpret_cast<const uint4*>(p);
@@ -175,25 +197,29 @@ __global__ void k_plan(SwArgs a, int pass, uint32_t* keys, int32_t* vals) {
 }
 
 // ---------------------------------------------------------------------------
-// one wavefront item: four pairs of the same rows-per-lane class
+// one wavefront item: 64 / G pairs of the same rows-per-lane class, each on a
+// group of G lanes (16: four pairs, one DPP row each; 64: one pair on the
+// whole wavefront, for launches with few pairs, whose time is the serial
+// latency of their longest pair: G lanes hold G * R rows of a strip, so a pair
+// of m rows takes m / (G * R) strips of n + G - 1 steps)
 // ---------------------------------------------------------------------------
-template <int R, Pass P, int RMAXT>
+template <int R, Pass P, int RMAXT, int G = kGroup>
 __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restrict__ order, int item,
                                          int n_work, const int8_t* __restrict__ s_mat,
                                          uint8_t* __restrict__ s_prof) {
     constexpr int RP = R <= 4 ? 4 : (R <= 8 ? 8 : 16);
     constexpr int W = RP / 4;
-    constexpr int kRows = kGroup * R;
+    constexpr int kRows = G * R;
     constexpr bool kEnd = (P != Pass::Score);
     const int lane = threadIdx.x;
-    const int g = lane >> 4;
-    const int gl = lane & 15;
+    const int g = lane / G;
+    const int gl = lane % G;
     const int go = a.go, ge = a.ge;
     // the clamp value is a kernel argument (always 0) so the compiler keeps the
     // signed three-input max instead of splitting it on a known sign
     const int z = a.zero;
 
-    const int64_t pos = static_cast<int64_t>(item) * kPairsPerWave + g;
+    const int64_t pos = static_cast<int64_t>(item) * (64 / G) + g;
     const bool has = pos < n_work;
     int p = 0, m = 0, n = 0, ea = 0, eb = 0;
     const uint8_t* A = a.seqs;
@@ -213,7 +239,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
     }
     const int S = (m + kRows - 1) / kRows;
     const int s_max = wave_max4(S);
-    uint8_t* prof = s_prof + g * (kNRes * kGroup * prof_row_bytes(RMAXT));
+    uint8_t* prof = s_prof + g * (kNRes * G * prof_row_bytes(RMAXT));
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
 
     bool bad = false;
@@ -257,7 +283,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
                     }
                     w[q] = word;
                 }
-                uint8_t* dst = prof + (c * kGroup + gl) * RP;
+                uint8_t* dst = prof + (c * G + gl) * RP;
                 if constexpr (W == 4) {
                     *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
                 } else if constexpr (W == 2) {
@@ -293,29 +319,29 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
             for (int r = 0; r < R; ++r) { HA[r] = 0; E[r] = 0; }
             int hdiag = 0, Hout = 0, Fout = 0;
             int feedR = col_in(col_raw(gl), gl);
-            int nfeedR = col_raw(kGroup + gl);
+            int nfeedR = col_raw(G + gl);
             int feedH = 0, feedF = 0;
             int2 nfeed = make_int2(0, 0);
             if constexpr (kMulti) {
                 const int2 v0 = bnd_raw(gl);
                 feedH = (rd && gl < n) ? v0.x : 0;
                 feedF = (rd && gl < n) ? v0.y : 0;
-                nfeed = bnd_raw(kGroup + gl);
+                nfeed = bnd_raw(G + gl);
             }
             int collH = 0, collF = 0;
-            int c = dpp_shr1(feedR, kSent);
-            ProfWords<W> pwA = load_prof<W>(prof, c, gl);
+            int c = dpp_shr1g<G>(feedR, kSent);
+            ProfWords<W> pwA = load_prof<W, G>(prof, c, gl);
             ProfWords<W> pwB;
 
             // one column step: previous column Hi -> this column Ho
             auto cells = [&](int t, const int (&Hi)[R], int (&Ho)[R], const ProfWords<W>& pw) {
                 int Htop, F;
                 if constexpr (kMulti) {
-                    Htop = dpp_shr1(feedH, Hout);
-                    F = dpp_shr1(feedF, Fout);
+                    Htop = dpp_shr1g<G>(feedH, Hout);
+                    F = dpp_shr1g<G>(feedF, Fout);
                 } else {
-                    Htop = dpp_shr1_zero(Hout);
-                    F = dpp_shr1_zero(Fout);
+                    Htop = dpp_shr1_zerog<G>(Hout);
+                    F = dpp_shr1_zerog<G>(Fout);
                 }
                 int colmax = z;
 #pragma unroll
@@ -354,15 +380,15 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
                         const int col = t + 1 + gl;
                         feedH = (rd && col < n) ? nfeed.x : 0;
                         feedF = (rd && col < n) ? nfeed.y : 0;
-                        nfeed = bnd_raw(t + 1 + kGroup + gl);
+                        nfeed = bnd_raw(t + 1 + G + gl);
                     } else {
-                        feedH = dpp_shl1_any(feedH);
-                        feedF = dpp_shl1_any(feedF);
+                        feedH = dpp_shl1_anyg<G>(feedH);
+                        feedF = dpp_shl1_anyg<G>(feedF);
                     }
-                    collH = dpp_shl1(Hout, collH);
-                    collF = dpp_shl1(Fout, collF);
-                    if ((t & (kGroup - 1)) == kGroup - 1) {
-                        const int col = t - 2 * (kGroup - 1) + gl;
+                    collH = dpp_shl1g<G>(Hout, collH);
+                    collF = dpp_shl1g<G>(Fout, collF);
+                    if ((t & (G - 1)) == G - 1) {
+                        const int col = t - 2 * (G - 1) + gl;
                         if (wr && col >= 0 && col < n) bnd[col] = make_int2(collH, collF);
                     }
                 }
@@ -370,13 +396,13 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
 
             // steps rounded up to even: an extra step only touches columns past
             // every subject's end
-            const int steps = (n_max + kGroup - 1 + 1) & ~1;
+            const int steps = (n_max + G - 1 + 1) & ~1;
 #pragma unroll 1
             for (int t = 0; t < steps; t += 2) {
                 {   // step t (even, never the last step of a 16-column chunk)
-                    const int feedR2 = dpp_shl1_any(feedR);
-                    const int cn = dpp_shr1(feedR2, c);
-                    pwB = load_prof<W>(prof, cn, gl);
+                    const int feedR2 = dpp_shl1_anyg<G>(feedR);
+                    const int cn = dpp_shr1g<G>(feedR2, c);
+                    pwB = load_prof<W, G>(prof, cn, gl);
                     // keep the read ahead of this step's cells: the scheduler
                     // would otherwise sink it next to its use a step later
                     __builtin_amdgcn_sched_barrier(0);
@@ -386,16 +412,16 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
                     c = cn;
                 }
                 {   // step t+1
-                    const bool chunk_end = ((t + 2) & (kGroup - 1)) == 0;
+                    const bool chunk_end = ((t + 2) & (G - 1)) == 0;
                     int feedR2;
                     if (chunk_end) {
                         feedR2 = col_in(nfeedR, t + 2 + gl);
-                        nfeedR = col_raw(t + 2 + kGroup + gl);
+                        nfeedR = col_raw(t + 2 + G + gl);
                     } else {
-                        feedR2 = dpp_shl1_any(feedR);
+                        feedR2 = dpp_shl1_anyg<G>(feedR);
                     }
-                    const int cn = dpp_shr1(feedR2, c);
-                    pwA = load_prof<W>(prof, cn, gl);
+                    const int cn = dpp_shr1g<G>(feedR2, c);
+                    pwA = load_prof<W, G>(prof, cn, gl);
                     __builtin_amdgcn_sched_barrier(0);
                     cells(t + 1, HB, HA, pwB);
                     boundary(t + 1, chunk_end);
@@ -404,7 +430,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
                 }
             }
             if constexpr (kMulti) {
-                const int col = (steps - 1) - 2 * (kGroup - 1) + gl;
+                const int col = (steps - 1) - 2 * (G - 1) + gl;
                 if (wr && col >= 0 && col < n) bnd[col] = make_int2(collH, collF);
                 __threadfence();
             }
@@ -416,14 +442,14 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
     // ---- group reductions and output
     int Sbest = best;
 #pragma unroll
-    for (int k = 1; k < kGroup; k <<= 1) Sbest = max(Sbest, __shfl_xor(Sbest, k, kGroup));
+    for (int k = 1; k < G; k <<= 1) Sbest = max(Sbest, __shfl_xor(Sbest, k, G));
     if constexpr (kEnd) {
         uint32_t key = (best == Sbest && Sbest > 0)
                            ? ((static_cast<uint32_t>(bi) << 16) | static_cast<uint32_t>(bj))
                            : 0xffffffffu;
 #pragma unroll
-        for (int k = 1; k < kGroup; k <<= 1) {
-            const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(key), k, kGroup));
+        for (int k = 1; k < G; k <<= 1) {
+            const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(key), k, G));
             key = min(key, o);
         }
         bi = Sbest > 0 ? static_cast<int>(key >> 16) : -1;
@@ -457,6 +483,39 @@ __global__ __launch_bounds__(64) void k_sw(SwArgs a) {
     for (int i = threadIdx.x; i < kNRes * kMatStride; i += 64) s_mat[i] = a.mat[i];
     __syncthreads();
     const int n_work = a.ctr->n_work;
+    if constexpr (P != Pass::Score && RMAXT == 16) {
+        // End and start cells of a few pairs (ClusterMerge's representative
+        // pairs above mT: a few thousand per level): at most four pairs per
+        // persistent wavefront, so every pair gets a whole wavefront of 64
+        // lanes, a quarter of the strips of the 16-lane layout.  The plan's
+        // order (rows-per-lane class, strips, columns, descending) takes the
+        // longest pairs first.
+        if (n_work <= 4 * static_cast<int>(gridDim.x)) {
+            while (true) {
+                int item = 0;
+                if (threadIdx.x == 0) item = atomicAdd(&a.ctr->ticket, 1);
+                item = __builtin_amdgcn_readfirstlane(item);
+                if (item >= n_work) break;
+                const int p = a.order[item];
+                const int x = a.pairs[2 * p];
+                const int m = (P == Pass::Span) ? a.end_a[p] + 1 : static_cast<int>(a.offsets[x + 1] - a.offsets[x]);
+                int strips = (m + 64 * RMAXT - 1) / (64 * RMAXT);
+                strips = max(strips, 1);
+                int R = (m + 64 * strips - 1) / (64 * strips);
+                R += R & 1;
+                R = __builtin_amdgcn_readfirstlane(min(max(R, 2), RMAXT));
+                if (R <= 2) run_item<2, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 4) run_item<4, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 6) run_item<6, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 8) run_item<8, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 10) run_item<10, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 12) run_item<12, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else if (R <= 14) run_item<14, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+                else run_item<16, P, RMAXT, 64>(a, a.order, item, n_work, s_mat, s_prof);
+            }
+            return;
+        }
+    }
     const int n_items = (n_work + kPairsPerWave - 1) / kPairsPerWave;
     while (true) {
         int item = 0;
