@@ -147,47 +147,64 @@ def exchange_similar(c1, c2, judge, stats):
     stats.exchanges += 1
 
 
+# How two live clusters relate, from their representatives (Section 3.1: the
+# similarity f >= T; Section 4: the transitivity test that lets one cluster
+# absorb the other; approximate transitivity is not symmetric, Section 3.3).
+APART, INTO_SECOND, INTO_FIRST, EXCHANGE = range(4)
+
+
+def relation(c1, c2, judge, stats):
+    """Relation of cluster c1 (first set) to cluster c2 (second set)."""
+    stats.rep_comparisons += 1
+    similar, second_absorbs_first, first_absorbs_second = judge.rep_test(c1.rep, c2.rep)
+    if not similar:
+        return APART
+    if second_absorbs_first:
+        return INTO_SECOND
+    return INTO_FIRST if first_absorbs_second else EXCHANGE
+
+
+def absorb(keeper, gone, stats):
+    """Full merge: the absorbed cluster's members join the keeper (in order,
+    skipping members already present) and the absorbed cluster is retired."""
+    _append_missing(keeper.objs, gone.objs)
+    gone.merged = True
+    stats.full_merges += 1
+
+
+def sweep_row(c1, cs2, judge, stats):
+    """Compare c1 with the second set's clusters that are still live, in set
+    order.  Returns True when c1 was absorbed, which ends its comparisons."""
+    for c2 in (c for c in cs2 if not c.merged):     # liveness read as the row advances
+        rel = relation(c1, c2, judge, stats)
+        if rel == INTO_SECOND:
+            absorb(c2, c1, stats)
+            return True
+        if rel == INTO_FIRST:
+            absorb(c1, c2, stats)
+        elif rel == EXCHANGE:
+            exchange_similar(c1, c2, judge, stats)
+    return False
+
+
 def merge(cs1, cs2, judge, stats):
-    """Algorithm 1 on two ordered cluster lists; returns the new ordered list."""
+    """Algorithm 1 (Section 3.1) on two ordered cluster lists: every cluster of
+    the first set, in order, is swept against the second set; the new list is
+    the first set's surviving clusters followed by the second set's."""
     if hasattr(judge, "begin_merge"):
         judge.begin_merge(cs1, cs2)
-    out = []
-    for c1 in cs1:
-        for c2 in cs2:
-            if c2.merged:
-                continue
-            stats.rep_comparisons += 1
-            similar, c2_takes_c1, c1_takes_c2 = judge.rep_test(c1.rep, c2.rep)
-            if not similar:
-                continue
-            if c2_takes_c1:
-                _append_missing(c2.objs, c1.objs)
-                c1.merged = True
-                stats.full_merges += 1
-                break
-            elif c1_takes_c2:
-                _append_missing(c1.objs, c2.objs)
-                c2.merged = True
-                stats.full_merges += 1
-            else:
-                exchange_similar(c1, c2, judge, stats)
-        if not c1.merged:
-            out.append(c1)
-    for c2 in cs2:
-        if not c2.merged:
-            out.append(c2)
-    return out
+    survivors = [c1 for c1 in cs1 if not sweep_row(c1, cs2, judge, stats)]
+    return survivors + [c2 for c2 in cs2 if not c2.merged]
 
 
 def bottom_up_merge(n, judge, stats=None):
-    """Algorithm 2 over elements 0..n-1 in index order; returns (clusters, stats)."""
+    """Algorithm 2 (Section 3.2) over elements 0..n-1 in index order: the sets
+    are merged in the FIFO order of merge_schedule; returns (clusters, stats)."""
     stats = stats or Stats()
-    q = deque([[Cluster(e, [e])] for e in range(n)])
-    while len(q) > 1:
-        cs1 = q.popleft()
-        cs2 = q.popleft()
-        q.append(merge(cs1, cs2, judge, stats))
-    final = q.popleft() if q else []
+    sets = {e: [Cluster(e, [e])] for e in range(n)}
+    for first, second, result in merge_schedule(n):
+        sets[result] = merge(sets.pop(first), sets.pop(second), judge, stats)
+    final = next(iter(sets.values())) if sets else []
     return final, stats
 
 
@@ -234,12 +251,12 @@ def clustermerge_extend(residues, offsets, M, prev, n_prev, T=120, mT=166, mU=15
     n = len(offsets) - 1
     judge = ProteinJudge(residues, offsets, M, T, mT, mU, go, ge)
     stats = Stats()
-    q = deque([[Cluster(e, [e])] for e in range(n_prev, n)])
-    while len(q) > 1:
-        cs1 = q.popleft()
-        cs2 = q.popleft()
-        q.append(merge(cs1, cs2, judge, stats))
-    new_set = q.popleft() if q else []
+    # Algorithm 2 over the new elements alone: the FIFO schedule of n - n_prev
+    # singletons, its set ids offset to the new elements
+    sets = {k: [Cluster(n_prev + k, [n_prev + k])] for k in range(n - n_prev)}
+    for first, second, result in merge_schedule(n - n_prev):
+        sets[result] = merge(sets.pop(first), sets.pop(second), judge, stats)
+    new_set = next(iter(sets.values())) if sets else []
     prev_set = [Cluster(int(r), [int(x) for x in m]) for r, m in prev]
     final = merge(prev_set, new_set, judge, stats) if new_set else prev_set
     pairs = similar_pairs(final, judge.score, T)

@@ -1439,8 +1439,10 @@ cm_status Driver::final_stage(cm_result* res) {
     // cached scores as per-element runs sorted by partner: candidates of x
     // come sorted by y, so one forward walk finds the cached ones (a probe of
     // the hash map per candidate costs a cache miss each)
+    const auto t_members = Clock::now();
     std::vector<std::pair<uint64_t, int32_t>> known;
     cache_.sorted_entries(&known);
+    const auto t_known = Clock::now();
     size_t kp = 0;
     std::vector<int32_t> tmp;
     for (int32_t x = 0; x < n_; ++x) {
@@ -1508,9 +1510,11 @@ cm_status Driver::final_stage(cm_result* res) {
     }
     st_.n_clusters = static_cast<int64_t>(fin.size());
     if (log_)
-        fprintf(stderr, "[cm] final candidates=%lld cache_hits=%lld similar=%lld %.3fs (submit %.3f wait %.3f consume %.3f)\n",
+        fprintf(stderr, "[cm] final candidates=%lld cache_hits=%lld similar=%lld %.3fs (members %.3f, sorted cache of "
+                "%zu scores %.3f, submit %.3f wait %.3f consume %.3f)\n",
                 static_cast<long long>(st_.final_candidates), static_cast<long long>(st_.cache_hits),
-                static_cast<long long>(st_.n_similar_pairs), secs(t0, Clock::now()), t_submit, t_wait, t_consume);
+                static_cast<long long>(st_.n_similar_pairs), secs(t0, Clock::now()), secs(t0, t_members), known.size(),
+                secs(t_members, t_known), t_submit, t_wait, t_consume);
     return CM_OK;
 }
 
