@@ -383,6 +383,7 @@ def throughput_leg(cm, ctx, args, out, log):
     ctx.sync()
     ctx.set_timing(True)
     n0, s0 = ctx.kernel_time(0)
+    cc0 = ctx.cells_computed(0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     reps = 3
@@ -391,6 +392,7 @@ def throughput_leg(cm, ctx, args, out, log):
     e1.record()
     ctx.sync()
     n1, s1 = ctx.kernel_time(0)
+    computed = (ctx.cells_computed(0) - cc0) / reps
     ctx.set_timing(False)
     bt = e0.elapsed_time(e1) / 1e3 / reps
     ks = (s1 - s0) / max(n1 - n0, 1)
@@ -400,8 +402,13 @@ def throughput_leg(cm, ctx, args, out, log):
         plan=list(ctx.get_plan(0)[:3]),
         kernel_s=ks, kernel_gcups=tcells / ks / 1e9, kernel_roofline_frac=tp_opc * tcells / ks / tp_peak,
         kernel_frac_8ops_packed_peak=8 * tcells / ks / PEAK_PK16_OPS,
-        int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS)
-    log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS")
+        int32_formulation_frac=OPS_PER_CELL * tcells / ks / PEAK_INT32_OPS,
+        # cells the kernels computed (strip ramps, padded rows, columns past a
+        # shorter pair's end) per cell the pairs have
+        computed_cells=computed, computed_per_counted_cell=computed / tcells,
+        kernel_frac_8ops_on_computed_cells=8 * computed / ks / PEAK_PK16_OPS)
+    log(f"throughput: {tcells / bt / 1e9:.1f} GCUPS batch, kernel {tcells / ks / 1e9:.1f} GCUPS, "
+        f"{computed / tcells:.3f} computed cells per counted cell")
     if args.autotune_pairs > 0:
         ctx.set_plan(0, *plan0[:3])     # the ClusterMerge legs keep the default plan
     return res
@@ -508,6 +515,7 @@ def main():
         log(f"warmup {w}: {g['stats']['t_total_s']:.2f} s")
     torch.cuda.synchronize()
     stats = []
+    cc0 = ctx.cells_computed(0)
     t0 = time.perf_counter()
     if large:
         os.environ["CM_LOG"] = "1"          # per-level progress lines
@@ -517,6 +525,7 @@ def main():
         log(f"step {k}: {g['stats']['t_total_s']:.2f} s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    computed = ctx.cells_computed(0) - cc0      # cells the score kernels computed (padding and ramps included)
     step_s = wall / args.steps
     s = stats[-1]
     cells = s["aligned_cells"]
@@ -539,6 +548,8 @@ def main():
                                 "sharing a query, then the rest; saturated pairs re-run in int32)"}
                             .get(ctx.get_plan(0)[0], "k_sw (int32 Smith-Waterman score kernel)")),
                     ops_per_cell=opc, launches=k_launch, avg_launch_ms=1e3 * k_sec / max(k_launch, 1),
+                    computed_per_counted_cell=computed / k_cells if k_cells else None,
+                    frac_on_computed_cells=opc * computed / k_sec / peak,
                     ops_per_launch=opc * k_cells / max(k_launch, 1),
                     cell_rate_gcups=k_cells / k_sec / 1e9,
                     int32_formulation_frac=OPS_PER_CELL * k_cells / k_sec / PEAK_INT32_OPS)

@@ -94,6 +94,12 @@ cm_status cm_context_set_timing(cm_context* ctx, int on);
  * memory); alignment-kernel timing is then not collected.  Off by default. */
 cm_status cm_context_set_graphs(cm_context* ctx, int on);
 cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, double* seconds);
+/* DP cells the alignment kernels of `pass` computed in the context's timed
+ * launches so far (running total; waits for the device): every lane-row of
+ * every column step of every strip, so ramps, padded rows and columns beyond
+ * a shorter pair's end are included.  Divided by the pairs' m * n it is the
+ * kernels' padding overhead. */
+cm_status cm_context_cells_computed(cm_context* ctx, int pass, double* cells);
 
 /* Measured peak rate of one VALU instruction of the cell update (the
  * denominators of the alignment kernels' roofline): every lane of 8

@@ -45,6 +45,8 @@ _lib.cm_context_set_graphs.restype = _i32
 _lib.cm_context_set_graphs.argtypes = [_P, ctypes.c_int]
 _lib.cm_context_kernel_time.restype = _i32
 _lib.cm_context_kernel_time.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)]
+_lib.cm_context_cells_computed.restype = _i32
+_lib.cm_context_cells_computed.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 _lib.cm_plan_get.restype = _i32
 _lib.cm_plan_get.argtypes = [_P, ctypes.c_int, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                              ctypes.POINTER(_i32)]
@@ -211,6 +213,13 @@ class Context:
         n, sec = _i64(), ctypes.c_double()
         _check(_lib.cm_context_kernel_time(self.handle, int(pass_), ctypes.byref(n), ctypes.byref(sec)))
         return n.value, sec.value
+
+    def cells_computed(self, pass_: int) -> float:
+        """DP cells the alignment kernels of a pass computed in timed launches so far
+        (ramps and padding included)."""
+        c = ctypes.c_double()
+        _check(_lib.cm_context_cells_computed(self.handle, int(pass_), ctypes.byref(c)))
+        return c.value
 
 
 _default_ctx: Context | None = None

@@ -211,6 +211,7 @@ cm_status run_pass_scratch(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, cons
     a.bnd = static_cast<int2*>(ctx->bnd.ptr);
     a.bnd_stride = ctx->bnd_stride;
     a.zero = 0;
+    a.cells_acc = ps.timed ? ctx->cells_acc + static_cast<int>(pass) : nullptr;
     hipError_t e = cmk::launch_plan(a, pass, ps.keys, ps.vals, st);
     if (e != hipSuccess) return hip_fail(e, "plan launch");
     size_t tmp = ps.sort_bytes;
@@ -257,6 +258,7 @@ cm_status run_pass(cm_context* ctx, cmk::SwArgs& a, cmk::Pass pass, hipStream_t 
         a.bnd = static_cast<int2*>(ctx->bnd.ptr);
         a.bnd_stride = ctx->bnd_stride;
         a.zero = 0;
+        a.cells_acc = ctx->cells_acc + CM_PASS_SCORE;
         a.packed = 1;
         const uint32_t go = static_cast<uint32_t>(-static_cast<int64_t>(a.go) < 65535 ? -a.go : 65535);
         const uint32_t ge = static_cast<uint32_t>(-static_cast<int64_t>(a.ge) < 65535 ? -a.ge : 65535);
@@ -549,6 +551,7 @@ cm_status cm_context_create(int device_ordinal, cm_context** out) {
     ctx->counters = reinterpret_cast<cmk::Counters*>(static_cast<char*>(small));
     ctx->err_flag = reinterpret_cast<uint32_t*>(static_cast<char*>(small) + 1024);
     ctx->dummy = reinterpret_cast<const uint8_t*>(static_cast<char*>(small) + 2048);
+    ctx->cells_acc = reinterpret_cast<unsigned long long*>(static_cast<char*>(small) + 3072);
     // boundary rows: one slot per group of the largest persistent grid
     ctx->bnd_stride = CM_MAX_LEN + 64;
     const size_t bnd_bytes = static_cast<size_t>(gmax) * cmk::kPairsPerWave * ctx->bnd_stride * sizeof(int2);
@@ -648,6 +651,19 @@ cm_status cm_context_kernel_time(cm_context* ctx, int pass, int64_t* launches, d
     drain_timers(ctx, true);
     if (launches) *launches = ctx->timer.launches[pass];
     if (seconds) *seconds = ctx->timer.secs[pass];
+    return CM_OK;
+    CM_CATCH
+}
+
+cm_status cm_context_cells_computed(cm_context* ctx, int pass, double* cells) {
+    CM_TRY
+    if (!ctx || !cells || pass < 0 || pass > 2) return fail(CM_EINVAL, "bad argument");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    unsigned long long v = 0;
+    if (e == hipSuccess) e = hipMemcpy(&v, ctx->cells_acc + pass, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "cells computed");
+    *cells = static_cast<double>(v);
     return CM_OK;
     CM_CATCH
 }

@@ -89,6 +89,7 @@ struct SwArgs {
     int32_t bnd_stride;
     uint32_t* err;
     const uint8_t* dummy;       // >= 64 readable bytes (target of clamped prefetches)
+    unsigned long long* cells_acc;   // nullable: running count of DP cells computed (padding and ramps included)
     int8_t mat[kNRes * kMatStride];   // M[row residue][column residue], sentinel -> -128
 };
 

@@ -86,6 +86,7 @@ struct cm_context {
     cmk::Counters* counters = nullptr;
     uint32_t* err_flag = nullptr;
     const uint8_t* dummy = nullptr;
+    unsigned long long* cells_acc = nullptr;   // per pass: DP cells the alignment kernels computed
     cmrt::DeviceBuf keys, keys_alt, vals, vals_alt, sort_tmp;
     cmrt::DeviceBuf bnd;                // boundary rows between strips
     cmrt::DeviceBuf over;               // saturated pairs of the packed kernel

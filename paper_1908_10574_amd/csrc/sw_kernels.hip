@@ -244,6 +244,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
 
     bool bad = false;
     int best = 0, bi = -1, bj = -1;
+    unsigned long long computed = 0;   // lane-rows x steps of the item (wave-uniform)
 
     for (int s = 0; s < s_max; ++s) {
         const bool act = s < S;
@@ -252,6 +253,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
         const int row0 = s * kRows;
         const int n_act = act ? n : 0;
         const int n_max = wave_max4(n_act);
+        computed += static_cast<unsigned long long>((n_max + G - 1 + 1) & ~1) * 64 * R;
         const bool rd_any = wave_max4(rd ? 1 : 0) != 0;
         const bool wr_any = wave_max4(wr ? 1 : 0) != 0;
 
@@ -473,6 +475,7 @@ __device__ __forceinline__ void run_item(const SwArgs& a, const int32_t* __restr
         }
     }
     if (bad) atomicOr(a.err, kErrResidue);
+    if (a.cells_acc && lane == 0) atomicAdd(a.cells_acc, computed);
 }
 
 template <Pass P, int RMAXT>
@@ -706,6 +709,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
     // every H, E, F and best value carries the bias kPkBias (in both halves)
     constexpr uint32_t KB = static_cast<uint32_t>(kPkBias) * 0x10001u;
     uint32_t best = KB;
+    unsigned long long computed = 0;   // lane-rows x halves x steps of the item (wave-uniform)
 
     for (int s = 0; s < s_max; ++s) {
         const bool act0 = s < S0, act1 = s < S1;
@@ -714,6 +718,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
         const int row0 = s * kRows;
         const int n_act = max(act0 ? n[0] : 0, act1 ? n[1] : 0);
         const int n_max = wave_max4(n_act);
+        computed += static_cast<unsigned long long>((n_max + kGroup - 1 + 1) & ~1) * 128 * R;
         const bool rd_any = wave_max4((rd0 || rd1) ? 1 : 0) != 0;
         const bool wr_any = wave_max4((wr0 || wr1) ? 1 : 0) != 0;
 
@@ -986,6 +991,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
     }
     if (bad || badcode > 19) atomicOr(a.err, kErrResidue);
     if (bad_plan) atomicOr(a.err, kErrPlan);
+    if (a.cells_acc && lane == 0) atomicAdd(a.cells_acc, computed);
 }
 
 // rows per lane of an item from its first pair's query (lists without keys)

@@ -315,3 +315,33 @@ def test_packed_saturation_boundary(cm):
             assert np.array_equal(sc.cpu().numpy(), ref), (kind, rmax)
     finally:
         ctx.set_plan(0, saved[0], saved[1], saved[2])
+
+
+def test_cells_computed_accounting(cm):
+    """The kernels' count of computed cells follows the strip and skew layout.
+    Eight copies of one 100 x 100 pair: on the two-profile packed kernel (at
+    most 8 rows per lane) they are one item of one strip of 7 rows per lane
+    and 116 column steps (100 + 15, rounded up to even) over 64 lanes and two
+    halves; their score+end pass has 8 pairs, at most four per wavefront, so
+    each pair takes a whole 64-lane wavefront with 2 rows per lane and 164
+    steps (100 + 63, rounded up to even).  Both are above the 80,000 cells the
+    pairs have, and the scores stay the oracle's."""
+    rng = np.random.default_rng(7)
+    ds = cmgen.from_list([rng.integers(0, 20, size=100).astype(np.uint8),
+                          rng.integers(0, 20, size=100).astype(np.uint8)])
+    pairs = np.array([(0, 1)] * 8, np.int32)
+    res, off, pr = to_dev(ds, pairs)
+    ctx = cm.Context(0)
+    ctx.set_plan(0, 1, 8, 1)
+    c0 = ctx.cells_computed(0)
+    sc = cm.sw_score_batch(res, off, pr, ds.matrix, ctx=ctx)
+    ctx.sync()
+    assert ctx.cells_computed(0) - c0 == 116 * 128 * 7
+    c1 = ctx.cells_computed(1)
+    s2, ea, eb = cm.sw_score_batch(res, off, pr, ds.matrix, return_end=True, ctx=ctx)
+    ctx.sync()
+    assert ctx.cells_computed(1) - c1 == 8 * 164 * 64 * 2
+    osc, oea, oeb = sw_batch(ds.residues, ds.offsets, pairs, ds.matrix, -11, -1)
+    assert np.array_equal(sc.cpu().numpy(), osc) and np.array_equal(s2.cpu().numpy(), osc)
+    assert np.array_equal(ea.cpu().numpy(), oea) and np.array_equal(eb.cpu().numpy(), oeb)
+    ctx.close()
