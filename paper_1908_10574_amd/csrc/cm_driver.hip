@@ -769,37 +769,47 @@ void Driver::request_exchange(const Cluster& c1, const Cluster& c2, std::vector<
         if (!c2.has(m)) want(m, c2.rep);
 }
 
-// Algorithm 1's control flow on representative outcomes only.
+// Algorithm 1's events from the outcome matrix of a merge (rows: clusters of
+// the first set, columns: clusters of the second; bits[i * n2 + j] holds
+// similarity and the two transitivity directions).  Row i meets the columns
+// still live when it starts, up to its first absorber: the first live column
+// that is similar and whose cluster absorbs row i's (Section 4's test); there
+// its cluster is absorbed and its comparisons end.  Before that, a similar
+// column either is absorbed by row i (it leaves the live mask) or exchanges
+// members with it.  A row only retires columns behind its own scan, so the
+// first-absorber scan over the mask at the row's start is exact.
 void Driver::simulate(MergeJob& job, const uint8_t* bits) {
     const std::vector<int32_t>& cs1 = sets_[job.set1];
     const std::vector<int32_t>& cs2 = sets_[job.set2];
     const size_t n2 = cs2.size();
-    std::vector<uint8_t> merged2(n2, 0);
+    std::vector<uint8_t> retired(n2, 0);     // second-set clusters absorbed so far
     for (size_t i = 0; i < cs1.size(); ++i) {
-        bool merged1 = false;
-        for (size_t j = 0; j < n2; ++j) {
-            if (merged2[j]) { ++spec_merged_col_; continue; }
+        const uint8_t* row = bits + i * n2;
+        size_t stop = n2;                    // first absorber of row i (n2: none)
+        for (size_t j = 0; j < n2; ++j)
+            if (!retired[j] && (row[j] & kSim) && (row[j] & kT21)) { stop = j; break; }
+        const size_t end = stop < n2 ? stop + 1 : n2;
+        const int32_t rep1 = cl_[cs1[i]].rep;
+        for (size_t j = 0; j < end; ++j) {
+            if (retired[j]) { ++spec_merged_col_; continue; }
             ++st_.rep_comparisons;
-            st_.required_cells += static_cast<double>(len_[cl_[cs1[i]].rep]) * len_[cl_[cs2[j]].rep];
-            const uint8_t b = bits[i * n2 + j];
-            if (!(b & kSim)) continue;
-            if (b & kT21) {                 // cluster2 absorbs cluster1; leave the inner loop
-                job.events.push_back({kAbsorb21, static_cast<int32_t>(i), static_cast<int32_t>(j)});
-                merged1 = true;
-                spec_after_break_ += static_cast<int64_t>(n2 - j - 1);
-                break;
+            st_.required_cells += static_cast<double>(len_[rep1]) * len_[cl_[cs2[j]].rep];
+            if (!(row[j] & kSim)) continue;
+            const int32_t ii = static_cast<int32_t>(i), jj = static_cast<int32_t>(j);
+            if (j == stop) {
+                job.events.push_back({kAbsorb21, ii, jj});
+            } else if (row[j] & kT12) {
+                job.events.push_back({kAbsorb12, ii, jj});
+                retired[j] = 1;
+            } else {
+                job.events.push_back({kExchange, ii, jj});
             }
-            if (b & kT12) {                 // cluster1 absorbs cluster2
-                job.events.push_back({kAbsorb12, static_cast<int32_t>(i), static_cast<int32_t>(j)});
-                merged2[j] = 1;
-                continue;
-            }
-            job.events.push_back({kExchange, static_cast<int32_t>(i), static_cast<int32_t>(j)});
         }
-        if (!merged1) job.result.push_back(cs1[i]);
+        if (stop < n2) spec_after_break_ += static_cast<int64_t>(n2 - stop - 1);   // aligned, never compared
+        else job.result.push_back(cs1[i]);
     }
     for (size_t j = 0; j < n2; ++j)
-        if (!merged2[j]) job.result.push_back(cs2[j]);
+        if (!retired[j]) job.result.push_back(cs2[j]);
 }
 
 // The replay is blocked at event job.next (its own pairs are requested).
