@@ -210,6 +210,9 @@ struct Aligner {
     };
     std::vector<Graph> graphs;
     Pinned sh_pairs, sh_out;   // screen staging (separate from the in-flight slots)
+    // end and start cells for the first span_pairs pairs of the next submit
+    // only (-1: all); the rest of the batch is scored only
+    int64_t span_pairs = -1;
     hipEvent_t scr0 = nullptr, scr1 = nullptr;   // around the device-side screen of a batch
 
     cm_status init() {
@@ -251,7 +254,7 @@ struct Aligner {
     // scores of every pair; end and start cells only where the coverage test
     // can use them (score above mT), compacted on the device
     cm_status enqueue(int32_t* d_pairs, int64_t n, int64_t cap, const int64_t* d_live, int32_t* dsc, bool spans,
-                      void* h_out, hipEvent_t scored) {
+                      void* h_out, hipEvent_t scored, int64_t n_span) {
         cm_status s = cmrt::score_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open,
                                         p->gap_extend, dsc, nullptr, nullptr, st);
         if (s != CM_OK) return s;
@@ -261,17 +264,17 @@ struct Aligner {
         if (!spans) return CM_OK;
         // the host can process the scores while the end and start passes run
         if (scored) (void)hipEventRecord(scored, st);
-        s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open, p->gap_extend, dsc,
-                            dsc + cap, dsc + 2 * cap, p->mT, st);
+        s = cmrt::end_batch(ctx, seqs, offsets, n_seqs, d_pairs, n_span, d_live, p->matrix, p->gap_open, p->gap_extend,
+                            dsc, dsc + cap, dsc + 2 * cap, p->mT, st);
         if (s != CM_OK) return s;
-        s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, d_pairs, n, d_live, p->matrix, p->gap_open, p->gap_extend,
+        s = cmrt::span_batch(ctx, seqs, offsets, n_seqs, d_pairs, n_span, d_live, p->matrix, p->gap_open, p->gap_extend,
                              dsc, dsc + cap, dsc + 2 * cap, p->mT, dsc + 3 * cap, dsc + 4 * cap, st);
         if (s != CM_OK) return s;
         uint32_t* d_count = reinterpret_cast<uint32_t*>(dsc + 5 * cap + 4);
         int32_t* d_ent = dsc + 5 * cap + 8;
         hipLaunchKernelGGL(cmdrv::k_zero_u32, dim3(1), dim3(64), 0, st, d_count);
         hipLaunchKernelGGL(cmdrv::k_end_compact, dim3(static_cast<unsigned>((cap + 255) / 256)), dim3(256), 0, st,
-                           dsc, cap, d_live, n, p->mT, d_count, d_ent);
+                           dsc, cap, d_live, n_span, p->mT, d_count, d_ent);
         e = hipMemcpyAsync(h + cap, d_count, 16, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(h + cap + 4, d_ent, static_cast<size_t>(prefix_of(cap)) * 20, hipMemcpyDeviceToHost, st);
@@ -294,6 +297,8 @@ struct Aligner {
     // the pairs scoring above mT also get end and start cells (EndRec).
     cm_status submit(int k, const int32_t* pairs, int64_t np, bool spans) {
         Slot& sl = slot[k];
+        const int64_t n_span = span_pairs >= 0 ? std::min(span_pairs, np) : np;
+        span_pairs = -1;
         sl.screened = false;
         sl.np = np;
         sl.stride = np;
@@ -319,7 +324,7 @@ struct Aligner {
         (void)hipEventRecord(sl.e0, st);
         sl.have_scores = false;
         cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr,
-                              spans ? sl.scored : nullptr);
+                              spans ? sl.scored : nullptr, n_span);
         if (s != CM_OK) return s;
         (void)hipEventRecord(sl.e1, st);
         e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
@@ -367,7 +372,7 @@ struct Aligner {
             if (e != hipSuccess) { ctx->timer.on = timed; return hip_fail(e, "begin capture"); }
             (void)hipMemcpyAsync(d_live, h_live, 8, hipMemcpyHostToDevice, st);
             (void)hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
-            s = enqueue(static_cast<int32_t*>(d_pairs.ptr), cap, cap, d_live, dsc, spans, sl.h_out.ptr, nullptr);
+            s = enqueue(static_cast<int32_t*>(d_pairs.ptr), cap, cap, d_live, dsc, spans, sl.h_out.ptr, nullptr, cap);
             (void)hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
@@ -454,7 +459,7 @@ struct Aligner {
                            hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "keep flags download");
         s = enqueue(static_cast<int32_t*>(d_kept.ptr), np, np, d_count, static_cast<int32_t*>(d_out.ptr), true,
-                    sl.h_out.ptr, sl.scored);
+                    sl.h_out.ptr, sl.scored, np);
         if (s != CM_OK) return s;
         (void)hipEventRecord(sl.e1, st);
         e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
@@ -674,7 +679,20 @@ public:
 
 private:
     cm_status load_lengths();
-    cm_status merge_level(std::vector<MergeJob>& jobs);
+    // A level is its representative stage (one wave, events simulated) and
+    // its exchange stage (replay passes, each blocked pass followed by the
+    // alignment of the pairs it requested).  Exchanges move members between
+    // clusters and never change which clusters survive or their
+    // representatives, so the next level's representative pairs are fixed
+    // before a level's exchanges end: a level's first requests can ride in
+    // the next level's representative batch (carry_), and its exchange stage
+    // then finishes after that wave, before the next level's replay.
+    int rep_chunks(std::vector<MergeJob>& jobs, size_t* total);   // sets rep_off
+    bool can_carry(std::vector<MergeJob>& next);
+    cm_status rep_stage(std::vector<MergeJob>& jobs, int level);
+    bool replay_pass(std::vector<MergeJob>& jobs, std::vector<int32_t>& req);
+    // requests in req (may be empty) aligned, then replay until no merge is blocked
+    cm_status exchange_stage(std::vector<MergeJob>& jobs, std::vector<int32_t>& req, int level);
     // the representative wave of a level: every pair in one batch (with the
     // screen when it covers this stage), or the columns in chunks
     cm_status wave_a(std::vector<MergeJob>& jobs, size_t total);
@@ -738,6 +756,7 @@ private:
     PairMap cache_;    // unordered pair -> score
     std::vector<std::pair<uint64_t, int32_t>> cand_;   // merge-stage scores (params.record_candidates)
     PairMap pending_;  // pairs requested in the current wave
+    std::vector<int32_t> carry_;   // a level's first exchange requests, aligned with the next representative wave
 };
 
 cm_status Driver::load_lengths() {
@@ -1008,13 +1027,13 @@ cm_status Driver::align_requests(std::vector<int32_t>& req) {
     return CM_OK;
 }
 
-cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
-    const auto t0 = Clock::now();
+int Driver::rep_chunks(std::vector<MergeJob>& jobs, size_t* total_out) {
     size_t total = 0;
     for (MergeJob& job : jobs) {
         job.rep_off = total;
         total += sets_[job.set1].size() * sets_[job.set2].size();
     }
+    if (total_out) *total_out = total;
     // a large representative product goes in column chunks (not under a
     // screen of this stage): default about 2^25 pairs per chunk, at most 8
     // (each chunk pays the latency of its end-cell and start-cell launches,
@@ -1025,40 +1044,62 @@ cm_status Driver::merge_level(std::vector<MergeJob>& jobs) {
         chunks = static_cast<int>(std::min<int64_t>(8, (static_cast<int64_t>(total) + per - 1) / per));
         if (chunks < 1) chunks = 1;
     }
+    return chunks;
+}
+
+bool Driver::can_carry(std::vector<MergeJob>& next) {
+    return !screened(CM_STAGE_REP) && !screened(CM_STAGE_EXCHANGE) && !ctx_->graphs && rep_chunks(next, nullptr) == 1;
+}
+
+cm_status Driver::rep_stage(std::vector<MergeJob>& jobs, int level) {
+    const auto t0 = Clock::now();
+    size_t total = 0;
+    const int chunks = rep_chunks(jobs, &total);
     t_prep_ = t_submit_ = t_wait_ = t_bits_ = 0;
-    cm_status s = chunks > 1 ? wave_a_chunked(jobs, chunks) : wave_a(jobs, total);
+    cm_status s = CM_OK;
+    if (chunks > 1 && !carry_.empty()) s = align_requests(carry_);   // chunked waves carry nothing
+    if (s == CM_OK) s = chunks > 1 ? wave_a_chunked(jobs, chunks) : wave_a(jobs, total);
     if (s != CM_OK) return s;
-    const auto t2 = Clock::now();
-    // exchange waves
-    std::vector<int32_t> req;
+    if (log_)
+        fprintf(stderr, "[cm] level %d merges=%zu rep_pairs=%zu waveA=%.3fs in %d chunk(s) (prep %.3f submit %.3f "
+                "wait %.3f bits+simulate %.3f) not compared: %lld past a break, %lld absorbed columns\n",
+                level, jobs.size(), total, secs(t0, Clock::now()), chunks, t_prep_, t_submit_, t_wait_, t_bits_,
+                static_cast<long long>(spec_after_break_), static_cast<long long>(spec_merged_col_));
+    spec_after_break_ = 0;
+    spec_merged_col_ = 0;
+    return CM_OK;
+}
+
+bool Driver::replay_pass(std::vector<MergeJob>& jobs, std::vector<int32_t>& req) {
+    bool blocked = false;
+    for (MergeJob& job : jobs)
+        if (!job.done && replay(job, req)) blocked = true;
+    return blocked;
+}
+
+cm_status Driver::exchange_stage(std::vector<MergeJob>& jobs, std::vector<int32_t>& req, int level) {
+    const auto t0 = Clock::now();
     int waves = 0;
     double t_rep = 0, t_al = 0;
     size_t n_req = 0;
     while (true) {
-        bool any_blocked = false;
-        auto q0 = Clock::now();
-        for (MergeJob& job : jobs)
-            if (!job.done && replay(job, req)) any_blocked = true;
-        auto q1 = Clock::now();
-        t_rep += secs(q0, q1);
-        if (!any_blocked) break;
-        n_req += req.size() / 2;
-        s = align_requests(req);
-        if (s != CM_OK) return s;
-        t_al += secs(q1, Clock::now());
-        ++waves;
+        if (!req.empty()) {
+            const auto a0 = Clock::now();
+            n_req += req.size() / 2;
+            cm_status s = align_requests(req);
+            if (s != CM_OK) return s;
+            t_al += secs(a0, Clock::now());
+            ++waves;
+        }
+        const auto q0 = Clock::now();
+        const bool blocked = replay_pass(jobs, req);
+        t_rep += secs(q0, Clock::now());
+        if (!blocked) break;
     }
-    const auto t3 = Clock::now();
     if (log_)
-        fprintf(stderr, "[cm] level merges=%zu rep_pairs=%zu waveA=%.3fs in %d chunk(s) (prep %.3f submit %.3f wait %.3f "
-                "bits+simulate %.3f) exchange=%.3fs (%d waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f) "
-                "not compared: %lld past a break, %lld absorbed columns\n",
-                jobs.size(), total, secs(t0, t2), chunks, t_prep_, t_submit_, t_wait_, t_bits_, secs(t2, t3), waves,
-                n_req, t_rep, t_spec_, t_al, static_cast<long long>(spec_after_break_),
-                static_cast<long long>(spec_merged_col_));
+        fprintf(stderr, "[cm] level %d exchange=%.3fs (%d more waves, %zu pairs, replay %.3f [speculate %.3f] align %.3f)\n",
+                level, secs(t0, Clock::now()), waves, n_req, t_rep, t_spec_, t_al);
     t_spec_ = 0;
-    spec_after_break_ = 0;
-    spec_merged_col_ = 0;
     return CM_OK;
 }
 
@@ -1284,21 +1325,52 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
             if (keep[k]) { kept.push_back(pairs[2 * k]); kept.push_back(pairs[2 * k + 1]); }
         src = &kept;
     }
+    // The previous level's first exchange requests (carry_, only on the plain
+    // path) ride in this batch after the representative pairs: scores only,
+    // the end and start passes cover the representative prefix.
+    size_t n_carry = 0;
+    const bool carried = !carry_.empty();
+    if (carried) {
+        if (src != &pairs || dev_screen) return fail(CM_EDEVICE, "deferred exchange requests on a screened wave");
+        size_t w = 0;
+        int32_t known;
+        for (size_t k = 0; k < carry_.size() / 2; ++k)
+            if (!cache_.find(unordered_key(carry_[2 * k], carry_[2 * k + 1]), &known)) {
+                carry_[2 * w] = carry_[2 * k];
+                carry_[2 * w + 1] = carry_[2 * k + 1];
+                ++w;
+            }
+        carry_.resize(2 * w);
+        n_carry = w;
+        pairs.insert(pairs.end(), carry_.begin(), carry_.end());
+    }
     std::vector<int32_t> out;
     std::vector<EndRec> ends;
     const size_t nk = src->size() / 2;
     const auto ta = Clock::now();
-    if (dev_screen)
+    if (dev_screen) {
         s = al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(total), scr_,
                                 static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau);
-    else
+    } else {
+        al_.span_pairs = static_cast<int64_t>(nk - n_carry);
         s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
+    }
     if (s != CM_OK) return s;
     const auto tb = Clock::now();
     // scores first (the end and start passes are still running), then the
     // coverage bits of the pairs scoring above mT
     s = al_.wait_scores(0, out);
     if (s != CM_OK) return s;
+    if (carried) {
+        const size_t base = nk - n_carry;
+        for (size_t k = 0; k < n_carry; ++k) {
+            const uint64_t key = unordered_key(carry_[2 * k], carry_[2 * k + 1]);
+            cache_.put(key, out[base + k]);
+            if (p_.record_candidates) cand_.emplace_back(key, out[base + k]);
+        }
+        carry_.clear();
+        pending_.clear();
+    }
     if (dev_screen) {
         const uint8_t* kf = al_.keep_flags();
         int64_t n_kept = 0;
@@ -1609,15 +1681,39 @@ cm_status Driver::run(cm_result** out) {
         }
     }
     st_.rounds = static_cast<int64_t>(by_level.size());
-    for (auto& jobs : by_level) {
-        s = merge_level(jobs);
-        if (s != CM_OK) return s;
+    auto release_inputs = [&](std::vector<MergeJob>& jobs) {
         for (MergeJob& job : jobs) {
-            sets_[job.out] = std::move(job.result);
             std::vector<int32_t>().swap(sets_[job.set1]);
             std::vector<int32_t>().swap(sets_[job.set2]);
         }
+    };
+    std::vector<MergeJob>* held = nullptr;   // level whose exchange stage waits for the carried requests
+    std::vector<int32_t> req;
+    for (size_t lv = 0; lv < by_level.size(); ++lv) {
+        std::vector<MergeJob>& jobs = by_level[lv];
+        const int lvi = static_cast<int>(lv);
+        s = rep_stage(jobs, lvi);
+        if (s != CM_OK) return s;
+        for (MergeJob& job : jobs) sets_[job.out] = std::move(job.result);
+        if (held) {
+            req.clear();
+            s = exchange_stage(*held, req, lvi - 1);
+            if (s != CM_OK) return s;
+            release_inputs(*held);
+            held = nullptr;
+        }
+        req.clear();
+        const bool blocked = replay_pass(jobs, req);
+        if (blocked && lv + 1 < by_level.size() && can_carry(by_level[lv + 1])) {
+            carry_.swap(req);
+            held = &jobs;
+            continue;
+        }
+        s = exchange_stage(jobs, req, lvi);
+        if (s != CM_OK) return s;
+        release_inputs(jobs);
     }
+    if (held || !carry_.empty()) return fail(CM_EDEVICE, "exchange requests left after the last level");
     if (sets_.empty()) sets_.emplace_back();
     const auto t1 = Clock::now();
     std::unique_ptr<cm_result> res(new cm_result());
