@@ -652,7 +652,8 @@ __device__ __forceinline__ ProfWords<W> load_prof_any(const uint8_t* p) {
 template <int R, int RMAXT, bool kShared>
 __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __restrict__ order, int item,
                                             int n_work, const int8_t* __restrict__ s_mat,
-                                            uint8_t* __restrict__ s_prof, uint2* __restrict__ s_stage) {
+                                            uint8_t* __restrict__ s_prof, uint2* __restrict__ s_stage,
+                                            uint32_t* __restrict__ s_code) {
     constexpr bool k16 = kShared && R <= kR16Max;   // 16-bit shared profile
     constexpr int RP = k16 ? prof16_row_bytes(R) : prof_row_bytes(R);   // bytes per lane and residue
     constexpr int W = RP / 4;
@@ -702,7 +703,12 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
     const uint8_t* lp0 = prof0 + gl * RP;
     const uint8_t* lp1 = prof1 + gl * RP;
     int2* bnd = a.bnd + (static_cast<int64_t>(blockIdx.x) * kPairsPerWave + g) * a.bnd_stride;
-    uint2* stg = s_stage + g * kGroup;   // this group's staged boundary chunk
+    uint2* stg = s_stage + g * (kGroup + 1);   // this group's staged boundary chunk (padded: distinct banks)
+    // this group's column codes (both pairs' profile offsets) of kGroup
+    // columns, column j at j mod kGroup: every lane reads the code of column
+    // t + 2 at step t (a broadcast); two steps before a 16-column chunk ends
+    // the lanes write the next chunk's codes, just before that step's read
+    uint32_t* ring = s_code + g * (kGroup + 1);   // padded: the groups' broadcasts hit different banks
 
     bool bad = false;
     int badcode = 0;
@@ -809,10 +815,13 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
 #pragma unroll
             for (int r = 0; r < R; ++r) { HA[r] = KB; E[r] = KB; }
             uint32_t hdiag = KB, Hout = KB, Fout = KB;
-            uint32_t feedR = col_in(col_raw(gl), gl);
+            const uint32_t code0 = col_in(col_raw(gl), gl);
+            ring[gl] = code0;
             int2 nfeedR = col_raw(kGroup + gl);
+            // lane 0's code of the next step's column (column 1 here)
+            uint32_t nc = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(code0)));
             uint32_t collH = 0, collF = 0;
-            uint32_t sH = 0, sF = 0;     // staged top row (H, F) of the next step's column
+            uint32_t sH = 0, sF = 0;     // staged top row (H, F) of this step's column
             int2 nfeed = make_int2(0, 0);
             if constexpr (kMulti) {
                 const int2 v0 = bnd_raw(gl);
@@ -824,14 +833,31 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 sH = v.x;
                 sF = v.y;
             }
-            uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR), static_cast<int>(kSentPk)));
+            uint32_t c = static_cast<uint32_t>(dpp_shr1(static_cast<int>(code0), static_cast<int>(kSentPk)));
             ProfWords<W> pa0 = load_prof_any<W, k16>(lp0 + (c & 0xffffu));
             ProfWords<W> pa1 = load_prof_any<W, k16>(lp1 + (c >> 16));
             ProfWords<W> pb0, pb1;
 
+            // staged top row of column t + 1 (multi-strip); a chunk's last
+            // step first stages the next chunk
+            auto stage_next = [&](int t, bool chunk_last, uint32_t& nsH, uint32_t& nsF) {
+                if constexpr (kMulti) {
+                    if (chunk_last) {   // stage columns t+1 .. t+16
+                        const uint32_t mk = rd_mask(t + 1 + gl);
+                        stg[gl] = make_uint2((static_cast<uint32_t>(nfeed.x) & mk) | (KB & ~mk),
+                                             (static_cast<uint32_t>(nfeed.y) & mk) | (KB & ~mk));
+                        nfeed = bnd_raw(t + 1 + kGroup + gl);
+                    }
+                    const uint2 v = stg[(t + 1) & (kGroup - 1)];
+                    nsH = v.x;
+                    nsF = v.y;
+                }
+            };
             // One column step t.  Multi-strip: lane 0 takes the top row from
             // the group's 16-column chunk of the boundary row staged in LDS
-            // (all lanes read the next step's column one step ahead; when a
+            // (all lanes read the next step's column one step ahead: in the
+            // two-profile kernel before the step's cells, in the shared-query
+            // kernel, which has no registers to spare, within them; when a
             // chunk ends its lanes stage the next chunk, loaded from global
             // memory 16 steps earlier), and lane 15's bottom row of the
             // previous step is collected into a 16-column register that is
@@ -842,17 +868,7 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 if constexpr (kMulti) {
                     Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(sH), static_cast<int>(Hout)));
                     F = static_cast<uint32_t>(dpp_shr1(static_cast<int>(sF), static_cast<int>(Fout)));
-                    if (chunk_last) {   // stage columns t+1 .. t+16
-                        const uint32_t mk = rd_mask(t + 1 + gl);
-                        stg[gl] = make_uint2((static_cast<uint32_t>(nfeed.x) & mk) | (KB & ~mk),
-                                             (static_cast<uint32_t>(nfeed.y) & mk) | (KB & ~mk));
-                        nfeed = bnd_raw(t + 1 + kGroup + gl);
-                    }
-                    {
-                        const uint2 v = stg[(t + 1) & (kGroup - 1)];
-                        sH = v.x;
-                        sF = v.y;
-                    }
+                    if constexpr (kShared) stage_next(t, chunk_last, sH, sF);
                     collH = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Hout), static_cast<int>(collH)));
                     collF = static_cast<uint32_t>(dpp_shl1(static_cast<int>(Fout), static_cast<int>(collF)));
                     if (store) {   // lane j holds the bottom row of column t - 31 + j
@@ -863,9 +879,10 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                             bnd[col] = make_int2(static_cast<int>(collH), static_cast<int>(collF));
                     }
                 } else {
-                    // lane 0's top row is the border (biased zero); a zero F
-                    // there is equivalent, since every E is at least the bias
-                    Htop = static_cast<uint32_t>(dpp_shr1(static_cast<int>(KB), static_cast<int>(Hout)));
+                    // lane 0's top row is the border (biased zero), taken
+                    // after the rows below; a zero F there is equivalent,
+                    // since every E is at least the bias
+                    Htop = 0;
                     F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
                 }
                 constexpr int kPer = k16 ? 2 : 4;            // rows per profile word
@@ -901,38 +918,54 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                         else if (r == R - 1) best = pk_maxs(best, h);
                     }
                 }
-                hdiag = Htop;
+                if constexpr (kMulti) {
+                    hdiag = Htop;
+                } else {
+                    // lane 0 of hdiag holds the border from the start and
+                    // keeps it (its row_shr source is invalid); hdiag is dead
+                    // after row 0, so the move needs no copy
+                    (void)Htop;
+                    hdiag = static_cast<uint32_t>(dpp_shr1(static_cast<int>(hdiag), static_cast<int>(Hout)));
+                }
                 Hout = Ho[R - 1];
                 Fout = F;
             };
 
+            // column code of step t + 1 from the ring (lane 0) and the lane
+            // above (the rest); the code of column t + 2 is read for the next
+            // step, after the next chunk's codes when t + 2 starts a chunk
+            auto next_code = [&](int t, bool code_chunk) -> uint32_t {
+                if (code_chunk) {   // codes of columns t+2 .. t+17
+                    ring[(t + 2 + gl) & (kGroup - 1)] = col_in(nfeedR, t + 2 + gl);
+                    nfeedR = col_raw(t + 2 + kGroup + gl);
+                }
+                const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(nc), static_cast<int>(c)));
+                nc = ring[(t + 2) & (kGroup - 1)];
+                return cn;
+            };
             // step t (even: never the last step of a 16-column chunk)
-            auto step_even = [&](int t, bool store) {
-                const uint32_t feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
-                const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+            auto step_even = [&](int t, bool store, bool code_chunk) {
+                uint32_t nsH = sH, nsF = sF;
+                if constexpr (!kShared) stage_next(t, false, nsH, nsF);
+                const uint32_t cn = next_code(t, code_chunk);
                 pb0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
                 pb1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
                 __builtin_amdgcn_sched_barrier(0);
                 cells(t, HA, HB, pa0, pa1, false, store);
-                feedR = feedR2;
                 c = cn;
+                if constexpr (!kShared) { sH = nsH; sF = nsF; }
             };
-            // step t (odd)
+            // step t (odd: never two steps before a chunk's end)
             auto step_odd = [&](int t, bool chunk_last) {
-                uint32_t feedR2;
-                if (chunk_last) {
-                    feedR2 = col_in(nfeedR, t + 1 + gl);
-                    nfeedR = col_raw(t + 1 + kGroup + gl);
-                } else {
-                    feedR2 = static_cast<uint32_t>(dpp_shl1_any(static_cast<int>(feedR)));
-                }
-                const uint32_t cn = static_cast<uint32_t>(dpp_shr1(static_cast<int>(feedR2), static_cast<int>(c)));
+                uint32_t nsH = sH, nsF = sF;
+                if constexpr (!kShared) stage_next(t, chunk_last, nsH, nsF);
+                const uint32_t cn = next_code(t, false);
                 pa0 = load_prof_any<W, k16>(lp0 + (cn & 0xffffu));
                 pa1 = load_prof_any<W, k16>(lp1 + (cn >> 16));
                 __builtin_amdgcn_sched_barrier(0);
                 cells(t, HB, HA, pb0, pb1, chunk_last, false);
-                feedR = feedR2;
                 c = cn;
+                if constexpr (!kShared) { sH = nsH; sF = nsF; }
             };
             const int steps = (n_max + kGroup - 1 + 1) & ~1;
             // Two-profile kernel: whole 16-column chunks fully unrolled, so that
@@ -948,13 +981,13 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                 const bool st = t > 0;
 #pragma unroll
                 for (int u = 0; u < kGroup; u += 2) {
-                    step_even(t + u, u == 0 && st);
+                    step_even(t + u, u == 0 && st, u + 2 == kGroup);
                     step_odd(t + u + 1, u + 2 == kGroup);
                 }
             }
 #pragma unroll 1
             for (; t < steps; t += 2) {
-                step_even(t, (t & (kGroup - 1)) == 0 && t > 0);
+                step_even(t, (t & (kGroup - 1)) == 0 && t > 0, ((t + 2) & (kGroup - 1)) == 0);
                 step_odd(t + 1, ((t + 2) & (kGroup - 1)) == 0);
             }
             if constexpr (kMulti) {
@@ -1010,7 +1043,8 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
     __shared__ __attribute__((aligned(16))) uint8_t
         s_prof[kPairsPerWave * 2 * kNRes * kGroup * prof_row_bytes(RMAXT)];
-    __shared__ uint2 s_stage[kPairsPerWave * kGroup];
+    __shared__ uint2 s_stage[kPairsPerWave * (kGroup + 1)];
+    __shared__ uint32_t s_code[kPairsPerWave * (kGroup + 1)];
     const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
     if (n_work == 0) return;
     int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
@@ -1025,15 +1059,15 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
         int R;
         if (a.keys) R = kRMax - static_cast<int>(a.keys[static_cast<int64_t>(item) * kPairsPerWavePk] >> 24);
         else R = item_rows(a, a.order, item, kPairsPerWavePk, RMAXT, false);
-        if (R <= 1) run_item_pk<1, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-        else if (R == 2) run_item_pk<2, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-        else if (R == 3) run_item_pk<3, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+        if (R <= 1) run_item_pk<1, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+        else if (R == 2) run_item_pk<2, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+        else if (R == 3) run_item_pk<3, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+        else if (R == 4 || RMAXT == 4) run_item_pk<4, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
         else if constexpr (RMAXT >= 8) {
-            if (R == 5) run_item_pk<5, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-            else if (R == 6) run_item_pk<6, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-            else if (R == 7) run_item_pk<7, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-            else run_item_pk<8, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
+            if (R == 5) run_item_pk<5, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+            else if (R == 6) run_item_pk<6, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+            else if (R == 7) run_item_pk<7, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+            else run_item_pk<8, RMAXT, false>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
         }
     }
 }
@@ -1042,16 +1076,17 @@ __global__ __launch_bounds__(64) void k_sw_pk(SwArgs a) {
 // per lane up to 32 (strips of up to 512 rows), one LDS profile per wavefront.
 template <int R>
 __device__ __forceinline__ void run_pkq_range(const SwArgs& a, int Rw, int item, int n_work, const int8_t* s_mat,
-                                              uint8_t* s_prof, uint2* s_stage) {
-    if (Rw == R) run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof, s_stage);
-    else if constexpr (R < kRMaxQ) run_pkq_range<R + 1>(a, Rw, item, n_work, s_mat, s_prof, s_stage);
+                                              uint8_t* s_prof, uint2* s_stage, uint32_t* s_code) {
+    if (Rw == R) run_item_pk<R, kRMaxQ, true>(a, a.order, item, n_work, s_mat, s_prof, s_stage, s_code);
+    else if constexpr (R < kRMaxQ) run_pkq_range<R + 1>(a, Rw, item, n_work, s_mat, s_prof, s_stage, s_code);
 }
 
 __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
     __shared__ int8_t s_mat[kNRes * kMatStride];
     __shared__ __attribute__((aligned(16))) uint8_t
         s_prof[kNRes * kGroup * cmax(prof_row_bytes(kRMaxQ), prof16_row_bytes(kR16Max))];
-    __shared__ uint2 s_stage[kPairsPerWave * kGroup];
+    __shared__ uint2 s_stage[kPairsPerWave * (kGroup + 1)];
+    __shared__ uint32_t s_code[kPairsPerWave * (kGroup + 1)];
     const int n_work = a.n_work_ptr ? *a.n_work_ptr : a.ctr->n_work;
     if (n_work == 0) return;
     int* ticket = a.ticket ? a.ticket : &a.ctr->ticket;
@@ -1064,7 +1099,7 @@ __global__ __launch_bounds__(64) void k_sw_pkq(SwArgs a) {
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= n_items) break;
         const int R = item_rows(a, a.order, item, kPairsPerWavePk, kRMaxQ, false);
-        run_pkq_range<1>(a, R, item, n_work, s_mat, s_prof, s_stage);
+        run_pkq_range<1>(a, R, item, n_work, s_mat, s_prof, s_stage, s_code);
     }
 }
 
