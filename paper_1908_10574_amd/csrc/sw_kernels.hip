@@ -715,6 +715,8 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
     // every H, E, F and best value carries the bias kPkBias (in both halves)
     constexpr uint32_t KB = static_cast<uint32_t>(kPkBias) * 0x10001u;
     uint32_t best = KB;
+    int sh8 = 8;
+    asm("" : "+s"(sh8));   // the profile words' byte shift, as an unknown wave-uniform amount
     unsigned long long computed = 0;   // lane-rows x halves x steps of the item (wave-uniform)
 
     for (int s = 0; s < s_max; ++s) {
@@ -886,10 +888,33 @@ __device__ __forceinline__ void run_item_pk(const SwArgs& a, const int32_t* __re
                     F = static_cast<uint32_t>(dpp_shr1_zero(static_cast<int>(Fout)));
                 }
                 constexpr int kPer = k16 ? 2 : 4;            // rows per profile word
+                // int8 rows in even bytes are sign-extended from the words
+                // shifted left by 8; a pair's two words of one load form a
+                // 64-bit register pair, shifted at once (the byte carried in
+                // lands in byte 0, which no selector reads; the amount is
+                // opaque to the compiler, which would split a shift by a
+                // constant into 32-bit parts)
+                uint32_t sw0[W], sw1[W];
+                if constexpr (!k16) {
+#pragma unroll
+                    for (int q = 0; q < W; q += 2) {
+                        if (q + 1 < W) {
+                            const uint64_t x0 = __builtin_bit_cast(uint64_t, make_uint2(w0.w[q], w0.w[q + 1])) << sh8;
+                            const uint64_t x1 = __builtin_bit_cast(uint64_t, make_uint2(w1.w[q], w1.w[q + 1])) << sh8;
+                            sw0[q] = static_cast<uint32_t>(x0);
+                            sw0[q + 1] = static_cast<uint32_t>(x0 >> 32);
+                            sw1[q] = static_cast<uint32_t>(x1);
+                            sw1[q + 1] = static_cast<uint32_t>(x1 >> 32);
+                        } else {
+                            sw0[q] = w0.w[q] << 8;
+                            sw1[q] = w1.w[q] << 8;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < W; ++q) {
                     const uint32_t wa = w0.w[q], wb = w1.w[q];
-                    const uint32_t sa = k16 ? 0u : wa << 8, sb = k16 ? 0u : wb << 8;
+                    const uint32_t sa = k16 ? 0u : sw0[q], sb = k16 ? 0u : sw1[q];
 #pragma unroll
                     for (int k = 0; k < kPer; ++k) {
                         const int r = kPer * q + k;
