@@ -53,6 +53,26 @@ __global__ void k_end_compact(const int32_t* planes, int64_t stride, const int64
         e[4] = planes[4 * stride + i];
     }
 }
+// The representative pairs of a level, merge by merge: merge m's block of
+// pairs starts at desc[5m] and holds its n1 x n2 product, row-major
+// (desc[5m + 1], desc[5m + 2]: offset and count of the first set's
+// representatives in reps; desc[5m + 3], desc[5m + 4]: the second set's).
+// Offsets ascend; every merge has n2 >= 1.
+__global__ void k_rep_product(const int64_t* desc, int n_merges, const int32_t* reps, int64_t n, int32_t* pairs) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (t >= n) return;
+    int lo = 0, hi = n_merges - 1;   // the last merge whose block starts at or before t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[5 * mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t* d = desc + 5 * static_cast<int64_t>(lo);
+    const int64_t local = t - d[0];
+    const int64_t i = local / d[4], j = local - i * d[4];
+    pairs[2 * t] = reps[d[1] + i];
+    pairs[2 * t + 1] = reps[d[3] + j];
+}
 // keep[i] = guard[i] (bypasses the screen) or logit >= tau
 __global__ void k_keep(const float* z, const uint8_t* guard, float tau, int64_t n, uint8_t* keep) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -324,6 +344,57 @@ struct Aligner {
         (void)hipEventRecord(sl.e0, st);
         sl.have_scores = false;
         cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr,
+                              spans ? sl.scored : nullptr, n_span);
+        if (s != CM_OK) return s;
+        (void)hipEventRecord(sl.e1, st);
+        e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "flag download");
+        (void)hipEventRecord(sl.done, st);
+        return CM_OK;
+    }
+
+    // Enqueue, in slot k, the representative pairs of a level's merges,
+    // generated on the device from one descriptor per merge (see
+    // k_rep_product; n_prod pairs in all), followed by n_extra host pairs.
+    // cells: the batch's cells (for the statistics).  Not under graphs.
+    cm_status submit_product(int k, const std::vector<int64_t>& desc, const std::vector<int32_t>& reps,
+                             int64_t n_prod, const int32_t* extra, int64_t n_extra, bool spans, double cells) {
+        Slot& sl = slot[k];
+        const int64_t np = n_prod + n_extra;
+        const int64_t n_span = span_pairs >= 0 ? std::min(span_pairs, np) : np;
+        span_pairs = -1;
+        sl.screened = false;
+        sl.np = np;
+        sl.stride = np;
+        sl.spans = spans;
+        sl.cells = cells;
+        if (np == 0) return CM_OK;
+        const int n_merges = static_cast<int>(desc.size() / 5);
+        if (ctx->graphs || (n_prod > 0 && n_merges < 1)) return fail(CM_EINVAL, "product batch");
+        // device: [pairs of the product | extra pairs | descriptors | reps]
+        const size_t pb = static_cast<size_t>(np) * 8;
+        const size_t xb = static_cast<size_t>(n_extra) * 8, db = desc.size() * 8, rb = reps.size() * 4;
+        cmrt::DeviceBuf& d_pairs = ctx->drv[2 * k];
+        cmrt::DeviceBuf& d_out = ctx->drv[2 * k + 1];
+        if (!d_pairs.ensure(pb + db + rb) || !d_out.ensure(dev_ints(np) * 4) || !sl.h_pairs.ensure(xb + db + rb) ||
+            !sl.h_out.ensure(host_ints(np, spans) * 4) || !sl.h_err.ensure(16))
+            return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(np));
+        sl.prefix = prefix_of(np);
+        char* h = static_cast<char*>(sl.h_pairs.ptr);
+        if (xb) std::memcpy(h, extra, xb);
+        if (db) std::memcpy(h + xb, desc.data(), db);
+        if (rb) std::memcpy(h + xb + db, reps.data(), rb);
+        char* dp = static_cast<char*>(d_pairs.ptr);
+        hipError_t e = hipMemcpyAsync(dp + static_cast<size_t>(n_prod) * 8, h, xb + db + rb, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "pairs upload");
+        (void)hipEventRecord(sl.e0, st);
+        if (n_prod > 0)
+            hipLaunchKernelGGL(cmdrv::k_rep_product, dim3(static_cast<unsigned>((n_prod + 255) / 256)), dim3(256), 0,
+                               st, reinterpret_cast<const int64_t*>(dp + pb), n_merges,
+                               reinterpret_cast<const int32_t*>(dp + pb + db), n_prod, reinterpret_cast<int32_t*>(dp));
+        sl.have_scores = false;
+        int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
+        cm_status s = enqueue(reinterpret_cast<int32_t*>(dp), np, np, nullptr, dsc, spans, sl.h_out.ptr,
                               spans ? sl.scored : nullptr, n_span);
         if (s != CM_OK) return s;
         (void)hipEventRecord(sl.e1, st);
@@ -1265,16 +1336,24 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
 // rep), with end and start cells for those above mT.
 cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     const auto t0 = Clock::now();
+    // the device screens, compacts and aligns in one stream (host-side
+    // screening under graph capture)
+    const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
+    // plain eager waves: the device generates the pairs from each merge's
+    // representative lists
+    const bool dev_pairs = !screened(CM_STAGE_REP) && !ctx_->graphs;
     std::vector<int32_t> pairs;
-    pairs.resize(2 * total);
-    for (const MergeJob& job : jobs) {
-        size_t k = job.rep_off;
-        for (int32_t a : sets_[job.set1]) {
-            const int32_t ra = cl_[a].rep;
-            for (int32_t b : sets_[job.set2]) {
-                pairs[2 * k] = ra;
-                pairs[2 * k + 1] = cl_[b].rep;
-                ++k;
+    if (!dev_pairs) {
+        pairs.resize(2 * total);
+        for (const MergeJob& job : jobs) {
+            size_t k = job.rep_off;
+            for (int32_t a : sets_[job.set1]) {
+                const int32_t ra = cl_[a].rep;
+                for (int32_t b : sets_[job.set2]) {
+                    pairs[2 * k] = ra;
+                    pairs[2 * k + 1] = cl_[b].rep;
+                    ++k;
+                }
             }
         }
     }
@@ -1285,9 +1364,6 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     std::vector<int32_t> kept;
     const std::vector<int32_t>* src = &pairs;
     cm_status s = CM_OK;
-    // the device screens, compacts and aligns in one stream (host-side
-    // screening under graph capture)
-    const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
     auto guarded = [&](int32_t a, int32_t b) { return rep_guarded(a, b); };
     std::vector<uint8_t> guard;
     int64_t n_guard = 0;
@@ -1331,7 +1407,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     size_t n_carry = 0;
     const bool carried = !carry_.empty();
     if (carried) {
-        if (src != &pairs || dev_screen) return fail(CM_EDEVICE, "deferred exchange requests on a screened wave");
+        if (!dev_pairs) return fail(CM_EDEVICE, "deferred exchange requests on a screened or captured wave");
         size_t w = 0;
         int32_t known;
         for (size_t k = 0; k < carry_.size() / 2; ++k)
@@ -1342,18 +1418,42 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
             }
         carry_.resize(2 * w);
         n_carry = w;
-        pairs.insert(pairs.end(), carry_.begin(), carry_.end());
     }
     std::vector<int32_t> out;
     std::vector<EndRec> ends;
-    const size_t nk = src->size() / 2;
     const auto ta = Clock::now();
     if (dev_screen) {
         s = al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(total), scr_,
                                 static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau);
+    } else if (dev_pairs) {
+        // one descriptor per merge (block offset, first set's representatives,
+        // second set's) and the batch's cells, (sum of lengths) x (sum of
+        // lengths) per merge
+        std::vector<int64_t> desc;
+        std::vector<int32_t> reps;
+        desc.reserve(5 * jobs.size());
+        double cells = 0;
+        for (const MergeJob& job : jobs) {
+            const std::vector<int32_t>& cs1 = sets_[job.set1];
+            const std::vector<int32_t>& cs2 = sets_[job.set2];
+            if (cs1.empty() || cs2.empty()) continue;
+            desc.push_back(static_cast<int64_t>(job.rep_off));
+            desc.push_back(static_cast<int64_t>(reps.size()));
+            desc.push_back(static_cast<int64_t>(cs1.size()));
+            double l1 = 0, l2 = 0;
+            for (int32_t a : cs1) { reps.push_back(cl_[a].rep); l1 += len_[cl_[a].rep]; }
+            desc.push_back(static_cast<int64_t>(reps.size()));
+            desc.push_back(static_cast<int64_t>(cs2.size()));
+            for (int32_t b : cs2) { reps.push_back(cl_[b].rep); l2 += len_[cl_[b].rep]; }
+            cells += l1 * l2;
+        }
+        for (size_t k = 0; k < n_carry; ++k)
+            cells += static_cast<double>(len_[carry_[2 * k]]) * len_[carry_[2 * k + 1]];
+        al_.span_pairs = static_cast<int64_t>(total);
+        s = al_.submit_product(0, desc, reps, static_cast<int64_t>(total), carry_.data(), static_cast<int64_t>(n_carry),
+                               true, cells);
     } else {
-        al_.span_pairs = static_cast<int64_t>(nk - n_carry);
-        s = al_.submit(0, src->data(), static_cast<int64_t>(nk), true);
+        s = al_.submit(0, src->data(), static_cast<int64_t>(src->size() / 2), true);
     }
     if (s != CM_OK) return s;
     const auto tb = Clock::now();
@@ -1362,11 +1462,10 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     s = al_.wait_scores(0, out);
     if (s != CM_OK) return s;
     if (carried) {
-        const size_t base = nk - n_carry;
         for (size_t k = 0; k < n_carry; ++k) {
             const uint64_t key = unordered_key(carry_[2 * k], carry_[2 * k + 1]);
-            cache_.put(key, out[base + k]);
-            if (p_.record_candidates) cand_.emplace_back(key, out[base + k]);
+            cache_.put(key, out[total + k]);
+            if (p_.record_candidates) cand_.emplace_back(key, out[total + k]);
         }
         carry_.clear();
         pending_.clear();
@@ -1388,19 +1487,34 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
         st_.t_screen_s += al_.screen_seconds();
         al_.set_kept(n_kept, cells);
     }
+    // outcome bits per pair in merge order (batch index k = rep_off + i n2 + j);
+    // the pairs above mT keep their representatives for the end records
     std::vector<uint8_t> bits(total, 0);
-    std::vector<size_t> deferred;            // batch index k of the pairs above mT
+    std::vector<size_t> deferred;                  // batch index k of the pairs above mT
+    std::vector<std::pair<int32_t, int32_t>> deferred_reps;
     size_t q = 0;
-    for (size_t k = 0; k < total; ++k) {
-        if (!keep[k]) continue;                 // dropped by the screen: not similar
-        const int32_t sc = out[q++];
-        if (p_.record_candidates) cand_.emplace_back(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
-        if (sc >= p_.T) {
-            bits[k] = kSim;
-            // similar representative scores may be needed again (exchanges, final stage)
-            cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
+    for (const MergeJob& job : jobs) {
+        size_t k = job.rep_off;
+        for (int32_t a : sets_[job.set1]) {
+            const int32_t ra = cl_[a].rep;
+            for (int32_t b : sets_[job.set2]) {
+                if (keep[k]) {                     // dropped by the screen: not similar
+                    const int32_t rb = cl_[b].rep;
+                    const int32_t sc = out[q++];
+                    if (p_.record_candidates) cand_.emplace_back(unordered_key(ra, rb), sc);
+                    if (sc >= p_.T) {
+                        bits[k] = kSim;
+                        // similar representative scores may be needed again (exchanges, final stage)
+                        cache_.put(unordered_key(ra, rb), sc);
+                    }
+                    if (sc > p_.mT) {
+                        deferred.push_back(k);
+                        deferred_reps.emplace_back(ra, rb);
+                    }
+                }
+                ++k;
+            }
         }
-        if (sc > p_.mT) deferred.push_back(k);
     }
     s = al_.wait(0, out, &ends);
     if (s != CM_OK) return s;
@@ -1412,7 +1526,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
         if (!keep[k]) continue;
         if (k == deferred[qe]) {
             if (ends[qe].idx != static_cast<int32_t>(q)) return fail(CM_EDEVICE, "missing end record for pair %zu", q);
-            const int32_t r1 = pairs[2 * k], r2 = pairs[2 * k + 1];
+            const int32_t r1 = deferred_reps[qe].first, r2 = deferred_reps[qe].second;
             const int32_t u1 = len_[r1] - (ends[qe].ea - ends[qe].sa + 1);
             const int32_t u2 = len_[r2] - (ends[qe].eb - ends[qe].sb + 1);
             if (u1 < p_.mU) bits[k] |= kT21;   // cluster2's rep covers nearly all of rep1
