@@ -73,6 +73,27 @@ __global__ void k_rep_product(const int64_t* desc, int n_merges, const int32_t* 
     pairs[2 * t] = reps[d[1] + i];
     pairs[2 * t + 1] = reps[d[3] + j];
 }
+// The same product with the screen's size guard: guard[t] = 1 when the two
+// clusters' member counts (counts, parallel to reps) multiply to at least
+// min_product (> 0).
+__global__ void k_rep_product_guard(const int64_t* desc, int n_merges, const int32_t* reps, const int32_t* counts,
+                                    int64_t min_product, int64_t n, int32_t* pairs, uint8_t* guard) {
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (t >= n) return;
+    int lo = 0, hi = n_merges - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc[5 * mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t* d = desc + 5 * static_cast<int64_t>(lo);
+    const int64_t local = t - d[0];
+    const int64_t i = local / d[4], j = local - i * d[4];
+    pairs[2 * t] = reps[d[1] + i];
+    pairs[2 * t + 1] = reps[d[3] + j];
+    guard[t] = (min_product > 0 &&
+                static_cast<int64_t>(counts[d[1] + i]) * static_cast<int64_t>(counts[d[3] + j]) >= min_product) ? 1 : 0;
+}
 // keep[i] = guard[i] (bypasses the screen) or logit >= tau
 __global__ void k_keep(const float* z, const uint8_t* guard, float tau, int64_t n, uint8_t* keep) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -474,8 +495,17 @@ struct Aligner {
     // pairs in order and aligns them with end and start cells.  wait_scores()
     // then returns the kept pairs' scores in order and keep_flags() the
     // decision for every candidate.
+    // The representative pairs of a screened wave as merge descriptors (see
+    // k_rep_product_guard): counts holds each representative's cluster size.
+    struct Product {
+        const std::vector<int64_t>* desc;
+        const std::vector<int32_t>* reps;
+        const std::vector<int32_t>* counts;
+        int64_t min_product;
+    };
+    // pairs and guard from the host, or (prod) generated on the device
     cm_status submit_screened(const int32_t* pairs, const uint8_t* guard, int64_t np, const cm_screen* scr,
-                              const uint16_t* feat, float tau) {
+                              const uint16_t* feat, float tau, const Product* prod = nullptr) {
         Slot& sl = slot[0];
         sl.np = np;
         sl.stride = np;
@@ -500,8 +530,13 @@ struct Aligner {
         cmrt::DeviceBuf& d_kept = ctx->drv[4];
         cmrt::DeviceBuf& d_scr = ctx->drv[11];
         const size_t hb = host_ints(np, true) * 4;
-        if (!d_pairs.ensure(pb) || !d_out.ensure(dev_ints(np) * 4) || !d_kept.ensure(pb) ||
-            !d_scr.ensure(o_tmp + tmp) || !sl.h_pairs.ensure(pb + np) || !sl.h_out.ensure(hb + np) ||
+        // with a product: [pairs | descriptors | reps | counts] on the device
+        const size_t db = prod ? prod->desc->size() * 8 : 0, rb = prod ? prod->reps->size() * 4 : 0;
+        const size_t up = prod ? db + 2 * rb : pb + np;   // bytes staged on the host
+        if (prod && (prod->counts->size() != prod->reps->size() || prod->desc->size() < 5))
+            return fail(CM_EINVAL, "screened product batch");
+        if (!d_pairs.ensure(pb + db + 2 * rb) || !d_out.ensure(dev_ints(np) * 4) || !d_kept.ensure(pb) ||
+            !d_scr.ensure(o_tmp + tmp) || !sl.h_pairs.ensure(up) || !sl.h_out.ensure(hb + np) ||
             !sl.h_err.ensure(16))
             return fail(CM_ENOMEM, "cannot stage %lld screened pairs", static_cast<long long>(np));
         char* scr_base = static_cast<char*>(d_scr.ptr);
@@ -509,14 +544,28 @@ struct Aligner {
         uint8_t* d_guard = reinterpret_cast<uint8_t*>(scr_base + o_guard);
         uint8_t* d_keep = reinterpret_cast<uint8_t*>(scr_base + o_keep);
         int64_t* d_count = reinterpret_cast<int64_t*>(scr_base + o_count);
-        std::memcpy(sl.h_pairs.ptr, pairs, pb);
-        std::memcpy(static_cast<char*>(sl.h_pairs.ptr) + pb, guard, static_cast<size_t>(np));
-        e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(d_guard, static_cast<char*>(sl.h_pairs.ptr) + pb, static_cast<size_t>(np),
-                               hipMemcpyHostToDevice, st);
+        char* h = static_cast<char*>(sl.h_pairs.ptr);
+        char* dp = static_cast<char*>(d_pairs.ptr);
+        if (prod) {
+            std::memcpy(h, prod->desc->data(), db);
+            std::memcpy(h + db, prod->reps->data(), rb);
+            std::memcpy(h + db + rb, prod->counts->data(), rb);
+            e = hipMemcpyAsync(dp + pb, h, up, hipMemcpyHostToDevice, st);
+        } else {
+            std::memcpy(h, pairs, pb);
+            std::memcpy(h + pb, guard, static_cast<size_t>(np));
+            e = hipMemcpyAsync(dp, h, pb, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_guard, h + pb, static_cast<size_t>(np), hipMemcpyHostToDevice, st);
+        }
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
         (void)hipEventRecord(sl.e0, st);
+        if (prod)
+            hipLaunchKernelGGL(cmdrv::k_rep_product_guard, dim3(static_cast<unsigned>((np + 255) / 256)), dim3(256),
+                               0, st, reinterpret_cast<const int64_t*>(dp + pb),
+                               static_cast<int>(prod->desc->size() / 5), reinterpret_cast<const int32_t*>(dp + pb + db),
+                               reinterpret_cast<const int32_t*>(dp + pb + db + rb), prod->min_product, np,
+                               reinterpret_cast<int32_t*>(dp), d_guard);
         (void)hipEventRecord(scr0, st);
         cm_status s = cm_screen_infer(scr, feat, static_cast<const int32_t*>(d_pairs.ptr), np, z, st);
         if (s != CM_OK) return s;
@@ -1340,10 +1389,37 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     // screening under graph capture)
     const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
     // plain eager waves: the device generates the pairs from each merge's
-    // representative lists
+    // representative lists (device-screened waves too, with the size guard)
     const bool dev_pairs = !screened(CM_STAGE_REP) && !ctx_->graphs;
     std::vector<int32_t> pairs;
-    if (!dev_pairs) {
+    // one descriptor per merge (block offset, first set's representatives,
+    // second set's), the representatives' cluster sizes (screened waves) and
+    // the batch's cells, (sum of lengths) x (sum of lengths) per merge
+    std::vector<int64_t> desc;
+    std::vector<int32_t> reps, counts;
+    double desc_cells = 0;
+    auto build_desc = [&](bool with_counts) {
+        desc.reserve(5 * jobs.size());
+        for (const MergeJob& job : jobs) {
+            const std::vector<int32_t>& cs1 = sets_[job.set1];
+            const std::vector<int32_t>& cs2 = sets_[job.set2];
+            if (cs1.empty() || cs2.empty()) continue;
+            desc.push_back(static_cast<int64_t>(job.rep_off));
+            desc.push_back(static_cast<int64_t>(reps.size()));
+            desc.push_back(static_cast<int64_t>(cs1.size()));
+            double l1 = 0, l2 = 0;
+            for (int32_t a : cs1) { reps.push_back(cl_[a].rep); l1 += len_[cl_[a].rep]; }
+            desc.push_back(static_cast<int64_t>(reps.size()));
+            desc.push_back(static_cast<int64_t>(cs2.size()));
+            for (int32_t b : cs2) { reps.push_back(cl_[b].rep); l2 += len_[cl_[b].rep]; }
+            if (with_counts) {
+                for (int32_t a : cs1) counts.push_back(static_cast<int32_t>(cl_[a].objs.size()));
+                for (int32_t b : cs2) counts.push_back(static_cast<int32_t>(cl_[b].objs.size()));
+            }
+            desc_cells += l1 * l2;
+        }
+    };
+    if (!dev_pairs && !dev_screen) {
         pairs.resize(2 * total);
         for (const MergeJob& job : jobs) {
             size_t k = job.rep_off;
@@ -1365,17 +1441,24 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     const std::vector<int32_t>* src = &pairs;
     cm_status s = CM_OK;
     auto guarded = [&](int32_t a, int32_t b) { return rep_guarded(a, b); };
-    std::vector<uint8_t> guard;
     int64_t n_guard = 0;
     if (dev_screen) {
-        guard.assign(total, 0);
-        for (const MergeJob& job : jobs) {
-            size_t k = job.rep_off;
-            for (int32_t a : sets_[job.set1])
-                for (int32_t b : sets_[job.set2]) {
-                    if (guarded(a, b)) { guard[k] = 1; ++n_guard; }
-                    ++k;
+        // the guard is set on the device; its count here, per merge from the
+        // second set's sorted cluster sizes
+        build_desc(true);
+        const int64_t minp = p_.screen_min_product;
+        if (minp > 0) {
+            std::vector<int64_t> c2;
+            for (const MergeJob& job : jobs) {
+                c2.clear();
+                for (int32_t b : sets_[job.set2]) c2.push_back(static_cast<int64_t>(cl_[b].objs.size()));
+                std::sort(c2.begin(), c2.end());
+                for (int32_t a : sets_[job.set1]) {
+                    const int64_t c1 = static_cast<int64_t>(cl_[a].objs.size());
+                    const int64_t need = (minp + c1 - 1) / c1;   // c1 * c2 >= minp  <=>  c2 >= need
+                    n_guard += static_cast<int64_t>(c2.end() - std::lower_bound(c2.begin(), c2.end(), need));
                 }
+            }
         }
     } else if (screened(CM_STAGE_REP)) {
         std::vector<int32_t> cand;
@@ -1423,30 +1506,12 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     std::vector<EndRec> ends;
     const auto ta = Clock::now();
     if (dev_screen) {
-        s = al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(total), scr_,
-                                static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau);
+        const Aligner::Product prod{&desc, &reps, &counts, p_.screen_min_product};
+        s = al_.submit_screened(nullptr, nullptr, static_cast<int64_t>(total), scr_,
+                                static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau, &prod);
     } else if (dev_pairs) {
-        // one descriptor per merge (block offset, first set's representatives,
-        // second set's) and the batch's cells, (sum of lengths) x (sum of
-        // lengths) per merge
-        std::vector<int64_t> desc;
-        std::vector<int32_t> reps;
-        desc.reserve(5 * jobs.size());
-        double cells = 0;
-        for (const MergeJob& job : jobs) {
-            const std::vector<int32_t>& cs1 = sets_[job.set1];
-            const std::vector<int32_t>& cs2 = sets_[job.set2];
-            if (cs1.empty() || cs2.empty()) continue;
-            desc.push_back(static_cast<int64_t>(job.rep_off));
-            desc.push_back(static_cast<int64_t>(reps.size()));
-            desc.push_back(static_cast<int64_t>(cs1.size()));
-            double l1 = 0, l2 = 0;
-            for (int32_t a : cs1) { reps.push_back(cl_[a].rep); l1 += len_[cl_[a].rep]; }
-            desc.push_back(static_cast<int64_t>(reps.size()));
-            desc.push_back(static_cast<int64_t>(cs2.size()));
-            for (int32_t b : cs2) { reps.push_back(cl_[b].rep); l2 += len_[cl_[b].rep]; }
-            cells += l1 * l2;
-        }
+        build_desc(false);
+        double cells = desc_cells;
         for (size_t k = 0; k < n_carry; ++k)
             cells += static_cast<double>(len_[carry_[2 * k]]) * len_[carry_[2 * k + 1]];
         al_.span_pairs = static_cast<int64_t>(total);
@@ -1474,13 +1539,20 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
         const uint8_t* kf = al_.keep_flags();
         int64_t n_kept = 0;
         double cells = 0;
-        for (size_t k = 0; k < total; ++k) {
-            keep[k] = kf[k];
-            if (keep[k]) {
-                ++n_kept;
-                cells += static_cast<double>(len_[pairs[2 * k]]) * len_[pairs[2 * k + 1]];
-            } else {
-                ++st_.screened_out;
+        for (const MergeJob& job : jobs) {
+            size_t k = job.rep_off;
+            for (int32_t a : sets_[job.set1]) {
+                const double la = len_[cl_[a].rep];
+                for (int32_t b : sets_[job.set2]) {
+                    keep[k] = kf[k];
+                    if (keep[k]) {
+                        ++n_kept;
+                        cells += la * len_[cl_[b].rep];
+                    } else {
+                        ++st_.screened_out;
+                    }
+                    ++k;
+                }
             }
         }
         st_.screened_pairs += static_cast<int64_t>(total) - n_guard;
