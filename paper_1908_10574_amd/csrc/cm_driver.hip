@@ -1389,7 +1389,8 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
     // screening under graph capture)
     const bool dev_screen = screened(CM_STAGE_REP) && !ctx_->graphs && total > 0;
     // plain eager waves: the device generates the pairs from each merge's
-    // representative lists (device-screened waves too, with the size guard)
+    // representative lists (device-screened waves generate them with the
+    // size guard; only host-screened waves build them here)
     const bool dev_pairs = !screened(CM_STAGE_REP) && !ctx_->graphs;
     std::vector<int32_t> pairs;
     // one descriptor per merge (block offset, first set's representatives,
@@ -1455,6 +1456,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
                 std::sort(c2.begin(), c2.end());
                 for (int32_t a : sets_[job.set1]) {
                     const int64_t c1 = static_cast<int64_t>(cl_[a].objs.size());
+                    if (c1 <= 0) continue;
                     const int64_t need = (minp + c1 - 1) / c1;   // c1 * c2 >= minp  <=>  c2 >= need
                     n_guard += static_cast<int64_t>(c2.end() - std::lower_bound(c2.begin(), c2.end(), need));
                 }
@@ -1570,7 +1572,7 @@ cm_status Driver::wave_a(std::vector<MergeJob>& jobs, size_t total) {
         for (int32_t a : sets_[job.set1]) {
             const int32_t ra = cl_[a].rep;
             for (int32_t b : sets_[job.set2]) {
-                if (keep[k]) {                     // dropped by the screen: not similar
+                if (keep[k]) {                     // (a pair the screen dropped is not similar)
                     const int32_t rb = cl_[b].rep;
                     const int32_t sc = out[q++];
                     if (p_.record_candidates) cand_.emplace_back(unordered_key(ra, rb), sc);
