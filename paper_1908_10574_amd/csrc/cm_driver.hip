@@ -359,16 +359,23 @@ struct Aligner {
             return fail(CM_ENOMEM, "cannot stage %lld pairs", static_cast<long long>(np));
         sl.prefix = prefix_of(np);
         std::memcpy(sl.h_pairs.ptr, pairs, pb);
-        int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
         hipError_t e = hipMemcpyAsync(d_pairs.ptr, sl.h_pairs.ptr, pb, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return hip_fail(e, "pairs upload");
         (void)hipEventRecord(sl.e0, st);
+        return align_staged(k, n_span);
+    }
+
+    // The device pair list of slot k is in place (or will be, in stream
+    // order): align it and queue the copies back and the slot's events.
+    cm_status align_staged(int k, int64_t n_span) {
+        Slot& sl = slot[k];
         sl.have_scores = false;
-        cm_status s = enqueue(static_cast<int32_t*>(d_pairs.ptr), np, np, nullptr, dsc, spans, sl.h_out.ptr,
-                              spans ? sl.scored : nullptr, n_span);
+        cm_status s = enqueue(static_cast<int32_t*>(ctx->drv[2 * k].ptr), sl.np, sl.np, nullptr,
+                              static_cast<int32_t*>(ctx->drv[2 * k + 1].ptr), sl.spans, sl.h_out.ptr,
+                              sl.spans ? sl.scored : nullptr, n_span);
         if (s != CM_OK) return s;
         (void)hipEventRecord(sl.e1, st);
-        e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
+        hipError_t e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_fail(e, "flag download");
         (void)hipEventRecord(sl.done, st);
         return CM_OK;
@@ -413,16 +420,7 @@ struct Aligner {
             hipLaunchKernelGGL(cmdrv::k_rep_product, dim3(static_cast<unsigned>((n_prod + 255) / 256)), dim3(256), 0,
                                st, reinterpret_cast<const int64_t*>(dp + pb), n_merges,
                                reinterpret_cast<const int32_t*>(dp + pb + db), n_prod, reinterpret_cast<int32_t*>(dp));
-        sl.have_scores = false;
-        int32_t* dsc = static_cast<int32_t*>(d_out.ptr);
-        cm_status s = enqueue(reinterpret_cast<int32_t*>(dp), np, np, nullptr, dsc, spans, sl.h_out.ptr,
-                              spans ? sl.scored : nullptr, n_span);
-        if (s != CM_OK) return s;
-        (void)hipEventRecord(sl.e1, st);
-        e = hipMemcpyAsync(sl.h_err.ptr, ctx->err_flag, 4, hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(e, "flag download");
-        (void)hipEventRecord(sl.done, st);
-        return CM_OK;
+        return align_staged(k, n_span);
     }
 
     // Same sequence as a replayed hipGraph: fixed capacity (a power of two),
