@@ -1244,23 +1244,47 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
     // under the screen (graphs off), the device screens each chunk's pairs
     // (the size guard as for one batch) and aligns the kept ones
     const bool dev_screen = screened(CM_STAGE_REP);
-    std::vector<int32_t> pairs, out;
+    // plain eager chunks: the device generates each chunk's pairs from one
+    // descriptor per merge (its live rows' and the chunk's columns'
+    // representatives), in the order the host walks them below
+    const bool dev_pairs = !dev_screen && !ctx_->graphs;
+    std::vector<int32_t> pairs, out, reps;
+    std::vector<int64_t> desc;
     std::vector<EndRec> ends;
     std::vector<uint8_t> bits, guard, keep;
     std::vector<size_t> deferred;
+    std::vector<std::pair<int32_t, int32_t>> deferred_reps;
     for (int c = 0; c < chunks; ++c) {
         const auto q0 = Clock::now();
         pairs.clear();
         guard.clear();
+        desc.clear();
+        reps.clear();
+        size_t n = 0;
+        double cells = 0;
         for (size_t b = 0; b < jobs.size(); ++b) {
             const std::vector<int32_t>& cs1 = sets_[jobs[b].set1];
             const std::vector<int32_t>& cs2 = sets_[jobs[b].set2];
             const size_t n2 = cs2.size();
             const size_t c0 = n2 * c / chunks, c1 = n2 * (c + 1) / chunks;
             js[b].rows.clear();
-            for (size_t i = 0; i < cs1.size(); ++i) {
-                if (js[b].broken[i]) continue;
-                js[b].rows.push_back(static_cast<int32_t>(i));
+            for (size_t i = 0; i < cs1.size(); ++i)
+                if (!js[b].broken[i]) js[b].rows.push_back(static_cast<int32_t>(i));
+            if (dev_pairs) {
+                if (js[b].rows.empty() || c1 == c0) continue;
+                desc.push_back(static_cast<int64_t>(n));
+                desc.push_back(static_cast<int64_t>(reps.size()));
+                desc.push_back(static_cast<int64_t>(js[b].rows.size()));
+                double l1 = 0, l2 = 0;
+                for (int32_t i : js[b].rows) { reps.push_back(cl_[cs1[i]].rep); l1 += len_[cl_[cs1[i]].rep]; }
+                desc.push_back(static_cast<int64_t>(reps.size()));
+                desc.push_back(static_cast<int64_t>(c1 - c0));
+                for (size_t j = c0; j < c1; ++j) { reps.push_back(cl_[cs2[j]].rep); l2 += len_[cl_[cs2[j]].rep]; }
+                cells += l1 * l2;
+                n += js[b].rows.size() * (c1 - c0);
+                continue;
+            }
+            for (int32_t i : js[b].rows) {
                 const int32_t ra = cl_[cs1[i]].rep;
                 for (size_t j = c0; j < c1; ++j) {
                     pairs.push_back(ra);
@@ -1269,12 +1293,13 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
                 }
             }
         }
-        const size_t n = pairs.size() / 2;
+        if (!dev_pairs) n = pairs.size() / 2;
         if (n == 0) continue;
         const auto q1 = Clock::now();
         cm_status s = dev_screen ? al_.submit_screened(pairs.data(), guard.data(), static_cast<int64_t>(n), scr_,
                                                        static_cast<const uint16_t*>(feat_->ptr), p_.screen_tau)
-                                 : al_.submit(0, pairs.data(), static_cast<int64_t>(n), true);
+                      : dev_pairs ? al_.submit_product(0, desc, reps, static_cast<int64_t>(n), nullptr, 0, true, cells)
+                                  : al_.submit(0, pairs.data(), static_cast<int64_t>(n), true);
         if (s != CM_OK) return s;
         const auto q2 = Clock::now();
         s = al_.wait_scores(0, out);
@@ -1299,22 +1324,39 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
             al_.set_kept(n_kept, cells);
         }
         // scores of the kept pairs come in order; end records are indexed by
-        // the kept pair's rank
+        // the kept pair's rank (pairs walked in generation order: merge,
+        // live row, column of the chunk)
         bits.assign(n, 0);
         deferred.clear();
+        deferred_reps.clear();
         std::vector<int32_t> rank;
-        size_t q = 0;
-        for (size_t k = 0; k < n; ++k) {
-            if (!keep[k]) continue;             // dropped by the screen: not similar
-            const int32_t sc = out[q];
-            if (p_.record_candidates) cand_.emplace_back(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
-            if (sc >= p_.T) {
-                bits[k] = kSim;
-                cache_.put(unordered_key(pairs[2 * k], pairs[2 * k + 1]), sc);
+        size_t q = 0, k = 0;
+        for (size_t b = 0; b < jobs.size(); ++b) {
+            const std::vector<int32_t>& cs1 = sets_[jobs[b].set1];
+            const std::vector<int32_t>& cs2 = sets_[jobs[b].set2];
+            const size_t n2 = cs2.size();
+            const size_t c0 = n2 * c / chunks, c1 = n2 * (c + 1) / chunks;
+            for (int32_t i : js[b].rows) {
+                const int32_t ra = cl_[cs1[i]].rep;
+                for (size_t j = c0; j < c1; ++j, ++k) {
+                    if (!keep[k]) continue;     // (a pair the screen dropped is not similar)
+                    const int32_t rb = cl_[cs2[j]].rep;
+                    const int32_t sc = out[q];
+                    if (p_.record_candidates) cand_.emplace_back(unordered_key(ra, rb), sc);
+                    if (sc >= p_.T) {
+                        bits[k] = kSim;
+                        cache_.put(unordered_key(ra, rb), sc);
+                    }
+                    if (sc > p_.mT) {
+                        deferred.push_back(k);
+                        deferred_reps.emplace_back(ra, rb);
+                        rank.push_back(static_cast<int32_t>(q));
+                    }
+                    ++q;
+                }
             }
-            if (sc > p_.mT) { deferred.push_back(k); rank.push_back(static_cast<int32_t>(q)); }
-            ++q;
         }
+        if (k != n) return fail(CM_EDEVICE, "chunk walk: %zu of %zu pairs", k, n);
         s = al_.wait(0, out, &ends);
         if (s != CM_OK) return s;
         const auto q3 = Clock::now();
@@ -1323,8 +1365,8 @@ cm_status Driver::wave_a_chunked(std::vector<MergeJob>& jobs, int chunks) {
         for (size_t qe = 0; qe < deferred.size(); ++qe) {
             const size_t k = deferred[qe];
             if (ends[qe].idx != rank[qe]) return fail(CM_EDEVICE, "missing end record for pair %zu", k);
-            const int32_t u1 = len_[pairs[2 * k]] - (ends[qe].ea - ends[qe].sa + 1);
-            const int32_t u2 = len_[pairs[2 * k + 1]] - (ends[qe].eb - ends[qe].sb + 1);
+            const int32_t u1 = len_[deferred_reps[qe].first] - (ends[qe].ea - ends[qe].sa + 1);
+            const int32_t u2 = len_[deferred_reps[qe].second] - (ends[qe].eb - ends[qe].sb + 1);
             if (u1 < p_.mU) bits[k] |= kT21;
             if (u2 < p_.mU) bits[k] |= kT12;
             ++st_.end_pairs;
