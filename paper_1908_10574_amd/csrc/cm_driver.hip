@@ -156,13 +156,35 @@ public:
     }
     size_t size() const { return size_; }
     // entries as (key, value) sorted by key: for keys made with key(x, y),
-    // grouped by x with y ascending
-    void sorted_entries(std::vector<std::pair<uint64_t, int32_t>>* out) const {
+    // grouped by x with y ascending.  With every x below n_x: a counting
+    // sort by x, then each x's (short) run sorted by y; otherwise one sort.
+    void sorted_entries(std::vector<std::pair<uint64_t, int32_t>>* out, int32_t n_x) const {
         out->clear();
-        out->reserve(size_);
+        bool bounded = n_x > 0;
+        std::vector<size_t> start;
+        if (bounded) {
+            start.assign(static_cast<size_t>(n_x) + 1, 0);
+            for (size_t i = 0; i < keys_.size() && bounded; ++i) {
+                if (keys_[i] == kEmpty) continue;
+                const uint64_t x = keys_[i] >> 32;
+                if (x >= static_cast<uint64_t>(n_x)) bounded = false;
+                else ++start[x + 1];
+            }
+        }
+        if (!bounded) {
+            out->reserve(size_);
+            for (size_t i = 0; i < keys_.size(); ++i)
+                if (keys_[i] != kEmpty) out->emplace_back(keys_[i], vals_[i]);
+            std::sort(out->begin(), out->end());
+            return;
+        }
+        for (size_t x = 0; x < static_cast<size_t>(n_x); ++x) start[x + 1] += start[x];
+        out->resize(size_);
+        std::vector<size_t> pos(start.begin(), start.end() - 1);
         for (size_t i = 0; i < keys_.size(); ++i)
-            if (keys_[i] != kEmpty) out->emplace_back(keys_[i], vals_[i]);
-        std::sort(out->begin(), out->end());
+            if (keys_[i] != kEmpty) (*out)[pos[keys_[i] >> 32]++] = std::make_pair(keys_[i], vals_[i]);
+        for (size_t x = 0; x < static_cast<size_t>(n_x); ++x)
+            if (start[x + 1] - start[x] > 1) std::sort(out->begin() + start[x], out->begin() + start[x + 1]);
     }
 
 private:
@@ -1751,7 +1773,7 @@ cm_status Driver::final_stage(cm_result* res) {
     // the hash map per candidate costs a cache miss each)
     const auto t_members = Clock::now();
     std::vector<std::pair<uint64_t, int32_t>> known;
-    cache_.sorted_entries(&known);
+    cache_.sorted_entries(&known, n_);
     const auto t_known = Clock::now();
     size_t kp = 0;
     std::vector<int32_t> tmp;
