@@ -322,8 +322,11 @@ def test_graph_replay_matches_eager_20k(cm):
     ctx.set_graphs(True)
     for _ in range(2):
         g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx)
+        # captured waves send host-built pairs and align exchange requests in
+        # their own waves; eager waves generate representative pairs on the
+        # device (cells from per-merge length sums) and carry exchange requests
         for k in ("pair_set_hash", "n_similar_pairs", "rep_comparisons", "exchange_alignments", "full_merges",
-                  "exchanges", "n_clusters", "aligned_pairs"):
+                  "exchanges", "n_clusters", "aligned_pairs", "aligned_cells", "cache_hits", "end_pairs"):
             assert g["stats"][k] == eager["stats"][k], k
         assert all(r1 == r2 and np.array_equal(m1, m2) for (r1, m1), (r2, m2) in zip(g["clusters"], eager["clusters"]))
     print("graph", g["stats"]["t_total_s"], "eager", eager["stats"]["t_total_s"])
