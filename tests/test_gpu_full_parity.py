@@ -105,20 +105,23 @@ def test_family_sets_exact(cm, name):
 
 def test_family_set_2000_under_other_launch_choices(cm):
     """The same exact output with graph-captured waves, with representative
-    waves cut into small column chunks, and with the two-profile packed and
-    the int32 score kernels."""
+    waves cut into small column chunks (eager: pairs built on the device;
+    captured: on the host, which must align the same pairs and cells), and
+    with the two-profile packed and the int32 score kernels."""
     clusters, pairs, stats, _ = _load_set("clustermerge_2000")
     gen, par = SETS["clustermerge_2000"]
     ds = cmgen.clustermerge_families(**gen)
     res, off = dev(ds.residues), dev(ds.offsets)
-    for variant in ("graphs", "chunks", "packed1", "int32"):
+    chunk_stats = {}
+    for variant in ("graphs", "chunks", "graphs_chunks", "packed1", "int32"):
         print(variant, flush=True)
         ctx = cm.Context(0)
         kw = {}
         if variant == "graphs":
             ctx.set_graphs(True)
-        elif variant == "chunks":
+        elif variant in ("chunks", "graphs_chunks"):
             kw["rep_chunk_pairs"] = 5000
+            ctx.set_graphs(variant == "graphs_chunks")
         elif variant == "packed1":
             ctx.set_plan(0, 1, 8, 1)
             ctx.set_plan(0, 1, 8, ctx.get_plan(0)[3])
@@ -127,7 +130,10 @@ def test_family_set_2000_under_other_launch_choices(cm):
             ctx.set_plan(0, 0, 16, ctx.get_plan(0)[3])
         g = cm.clustermerge_run(res, off, ds.matrix, ctx=ctx, **par, **kw)
         _assert_result(g, clusters, pairs, stats)
+        if "chunks" in variant:
+            chunk_stats[variant] = (g["stats"]["aligned_pairs"], g["stats"]["aligned_cells"])
         ctx.close()
+    assert chunk_stats["chunks"] == chunk_stats["graphs_chunks"], chunk_stats
 
 
 def test_clustermerge_20000_digest(cm):
